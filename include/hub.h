@@ -1,0 +1,230 @@
+/*
+ * hub.h -- C ABI of the MI355X (gfx950) DFT+U / ACBN0 Hubbard kernel.
+ *
+ * Method: Tancogne-Dejean, Oliveira & Rubio, "Self-consistent DFT+U method
+ * for real-space time-dependent density functional theory calculations"
+ * (arXiv 1711.08935).  Section/equation labels below are the paper's.
+ *
+ * Conventions (all calls):
+ *  - Hartree atomic units.  Orthorhombic cell of lengths cell[3] (bohr) with
+ *    ngrid[3] points per axis; h_i = cell_i / ngrid_i; grid point
+ *    g = (ix * Ny + iy) * Nz + iz sits at r_g = (ix hx, iy hy, iz hz);
+ *    dV = hx hy hz.  G = Nx Ny Nz.
+ *  - k-points in reduced units: k_i = 2 pi k_red_i / cell_i.  States are
+ *    full Bloch functions on the cell grid, psi(r + T) = exp(i k.T) psi(r).
+ *  - "Device pointer": memory the caller allocated on the GPU of the context
+ *    (e.g. a torch tensor); "host pointer": ordinary CPU memory.  Every
+ *    device-side call is asynchronous on the context stream (hub_set_stream);
+ *    results are valid once that stream has reached the call.  The caller
+ *    owns every pointer it passes; the context owns only its own tables and
+ *    workspaces, released by hub_destroy.
+ *  - Errors: the return value is HUB_OK (0), a negative error code, or a
+ *    positive warning.  Arguments are validated before any launch; on an
+ *    error nothing is launched and no output is touched.  No call aborts the
+ *    process and no C++ exception crosses the ABI.  Asynchronous device
+ *    faults surface as HUB_EDEVICE from a later call.
+ *  - One context per stream; a context is not thread-safe.
+ *
+ * State layouts (T = double for HUB_F64, float for HUB_F32; complex states
+ * store (re, im) pairs of T):
+ *  - unpolarized / collinear: psi[q][g][0..ld), q = ik * nspin + ispin
+ *    (nspin = 1 unpolarized, 2 collinear), state s in column s;
+ *  - spinor: psi[k][g][0..ld), state s, component sigma in column 2s+sigma.
+ *  ncol = nstates (collinear) or 2 * nstates (spinor); ld >= ncol counts
+ *  columns (complex elements for complex states) per grid point.
+ *
+ * Result layouts (always FP64):
+ *  - c[q][j][ncol]: projections <phi_j,k|psi>; j runs over all orbitals of
+ *    all sites in site order (orbital offset of each site: hub_site_info),
+ *    m = -l..l inside a site; complex contexts interleave (re, im).
+ *  - n, pbar: [site][nblk][HUB_LMAX][HUB_LMAX] complex (re, im) pairs;
+ *    nblk = 1 (unpolarized: one stored channel that stands for two identical
+ *    spin channels), 2 (collinear: sigma), 4 (spinor: block 2*sigma+sigma').
+ *    Only the leading L x L corner of each block is used.
+ *  - nbar[q][species][nstates] (spinor: [k][species][nstates]).
+ *  - f: occupations per stored state set, [q][nstates] (spinor [k][nstates]).
+ *  - U, J, Ueff, EU: [site]; status: [site] int32; F: [site][3].
+ */
+#ifndef HUB_H
+#define HUB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HUB_LMAX 7           /* 2l+1 for the largest shell, l = 3 (f)       */
+#define HUB_MAX_SPECIES 16
+
+/* status codes */
+#define HUB_OK 0
+#define HUB_EINVAL (-1)      /* bad argument (NULL, size, mode, order)      */
+#define HUB_ENOMEM (-2)      /* host or device allocation failed            */
+#define HUB_EDEVICE (-3)     /* HIP runtime error (incl. an earlier fault)  */
+#define HUB_ESTATE (-4)      /* call not valid in the context's state       */
+#define HUB_WDEGENERATE 1    /* per-site status: a U/J denominator < 1e-12  */
+
+/* spin modes */
+#define HUB_UNPOLARIZED 1
+#define HUB_COLLINEAR 2
+#define HUB_SPINOR 4
+
+/* storage precision of states (results are always FP64) */
+#define HUB_F64 0
+#define HUB_F32 1            /* FP32 states, FP64 orbital table, FP64 sums  */
+
+/* hub_step modes */
+#define HUB_STEP_BATCHED 0   /* one launch per stage over the work list     */
+#define HUB_STEP_GRAPH 1     /* the batched launches captured as a hipGraph */
+#define HUB_STEP_PERSITE 2   /* one launch per site and stage, no graph     */
+
+typedef struct hub_ctx hub_ctx;
+
+/* Create a context (host only; touches no GPU).
+ * spin_mode: HUB_UNPOLARIZED | HUB_COLLINEAR | HUB_SPINOR (spinor needs
+ * is_complex = 1).  precision: HUB_F64 | HUB_F32.  *out receives the handle.
+ * Errors: HUB_EINVAL (NULL, ngrid < 1, cell <= 0, bad mode), HUB_ENOMEM. */
+int hub_create(hub_ctx** out, const double cell[3], const int ngrid[3],
+               int spin_mode, int is_complex, int precision);
+
+/* k-point set (host arrays): k_red[nk][3] reduced coordinates, weights[nk]
+ * (the w_k of Eq. occ_matrices).  Default: Gamma only, weight 1.  Real
+ * contexts (is_complex = 0) accept only k = 0.  Before hub_finalize*. */
+int hub_set_kpoints(hub_ctx* ctx, int nk, const double* k_red, const double* weights);
+
+/* Add one Hubbard shell (Sec. II): centre R[3] (bohr, any position; it is
+ * folded by periodicity), angular momentum l in 0..3, Slater exponent zeta of
+ * the radial part r^l exp(-zeta r), sphere radius rc (sphere points satisfy
+ * |r - R|^2 <= rc^2, inclusive), species id in [0, HUB_MAX_SPECIES) that
+ * groups the shells summed in N-bar (Eq. notation_Nbar: atoms of the same
+ * type).  *site_id (may be NULL) receives the site index.  Before
+ * hub_finalize*. */
+int hub_add_site(hub_ctx* ctx, const double R[3], int l, double zeta, double rc,
+                 int species, int* site_id);
+
+/* Fix the effective U of one site (the empirical DFT+U scheme, Sec. II);
+ * pass NaN to return the site to ACBN0 (the default).  Any time. */
+int hub_set_fixed_ueff(hub_ctx* ctx, int site, double ueff);
+
+/* Entries per work-list chunk (default 1024; 64..65536).  Before
+ * hub_finalize*. */
+int hub_set_chunk(hub_ctx* ctx, int chunk_entries);
+
+/* Kernel shape: columns handled per lane (1, 2 or 4; 0 = automatic) and
+ * waves per work-group (1, 2 or 4) for the projection (which = 0) and the
+ * application (which = 1).  Any time after creation. */
+int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves);
+
+/* Build the sphere maps, orbital tables (grid-normalized, dV sum phi^2 = 1,
+ * Sec. II), image/phase tables and the work list on the host.  Needs no GPU.
+ * Errors: HUB_EINVAL (no sites, or a sphere that holds no grid point),
+ * HUB_ENOMEM. */
+int hub_finalize_host(hub_ctx* ctx);
+
+/* hub_finalize_host (if not done) plus upload to the current HIP device;
+ * stream (hipStream_t, may be NULL for the null stream) becomes the context
+ * stream.  Errors: HUB_EDEVICE, HUB_ENOMEM. */
+int hub_finalize(hub_ctx* ctx, void* stream);
+
+/* Change the context stream (hipStream_t). */
+int hub_set_stream(hub_ctx* ctx, void* stream);
+
+/* Integer properties after hub_finalize_host: what = 0 sites, 1 orbitals J,
+ * 2 state sets (nq; spinor: nk), 3 apply layers, 4 sphere entries, 5 chunks,
+ * 6 species, 7 k-points, 8 nblk of n/pbar, 9 bytes of device tables,
+ * 10 projection workspace rows (sum of L over chunks). */
+int hub_query(const hub_ctx* ctx, int what, int64_t* value);
+
+/* Per-site data after hub_finalize_host: L = 2l+1, offset of its first
+ * orbital in j, number of sphere points, species.  Any pointer may be NULL. */
+int hub_site_info(const hub_ctx* ctx, int site, int* L, int* orb_offset,
+                  int64_t* npoints, int* species);
+
+/* Host copy of one site's sphere (Fig. 1): for every unfolded point p, in
+ * order of (g, image): folded grid index g[p], lattice image image3[3p..3p+2]
+ * (T_p = image * cell, r_p = r_g + T_p), orbital values phi[p*L + m] and, if
+ * grad is not NULL, grad[(p*L + m)*3 + i] = d phi_m / d r_i.  Arrays sized by
+ * hub_site_info's npoints.  Any output may be NULL. */
+int hub_site_points(const hub_ctx* ctx, int site, int32_t* g, int32_t* image3,
+                    double* phi, double* grad);
+
+/* Projections (Eq. occ_matrices brackets; Fig. 1 phase):
+ * c[q][j][col] = dV sum_p exp(+i k.T_p) phi_j(r_p) psi_q[g(p)][col] for every
+ * state set q, orbital j and column col < ncol.  psi: device, layout above;
+ * c: device, [nq][J][ncol].  nstates >= 1, ld >= ncol. */
+int hub_project(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, double* c);
+
+/* Occupations (Eq. occ_matrices), renormalized occupations N-bar
+ * (Eq. notation_Nbar) and P-bar (Eq. notation_Pbar); spinors: App. A and B.
+ * c: device [nq][J][ncol] from hub_project; f: device occupations.  Outputs
+ * (device): n, pbar (may be NULL), nbar (may be NULL unless pbar is given:
+ * then a NULL nbar uses an internal buffer). */
+int hub_occupations(hub_ctx* ctx, const double* c, int nstates, const double* f,
+                    double* n, double* pbar, double* nbar);
+
+/* On-site Coulomb tensor (m m'|m'' m''') of one site (Sec. III, evaluated on
+ * the grid; App. B notation): dV^2 sum_{p,p'} phi_a phi_b(p) K(p - p')
+ * phi_c phi_d(p') over the site's unfolded sphere points, K = 1/|r| and
+ * K(0) = the average of 1/r over one grid cell.  Cached in the context for
+ * hub_acbn0_uj.  site = -1 computes every site.  tensor (device, may be NULL)
+ * receives L^4 doubles [a][b][c][d] for a single site. */
+int hub_coulomb(hub_ctx* ctx, int site, double* tensor);
+
+/* ACBN0 U-bar, J-bar (Eqs. ACBN0_U, ACBN0_J; spinors App. B) and
+ * U_eff = U-bar - J-bar per site, from n and pbar (device).  Sites with a
+ * fixed U_eff (hub_set_fixed_ueff) report U = Ueff = fixed, J = 0.  Needs the
+ * Coulomb tensors (hub_coulomb(ctx, -1, NULL)) or returns HUB_ESTATE.
+ * status (device int32, may be NULL): 0, or HUB_WDEGENERATE where a
+ * denominator is below 1e-12 (that U or J is then 0). */
+int hub_acbn0_uj(hub_ctx* ctx, const double* n, const double* pbar,
+                 double* U, double* J, double* Ueff, int* status);
+
+/* Hubbard potential (Eq. pot_V_U), accumulated:
+ * hpsi_q[g][col] += alpha * scale_q[s] * (V_U psi)_q[g][col], with
+ * V_ab = Ueff (delta_ab / 2 - n_ba) per site and spin channel (spinor:
+ * V^{ss'}_ab = Ueff (delta delta / 2 - n^{s's}_ba)), evaluated from the
+ * projections c.  Ueff, n, c: device.  colscale: device [nsets][nstates] or
+ * NULL (all ones).  hpsi: device, same layout as psi with leading dimension
+ * ld; only sphere grid points are written. */
+int hub_apply(hub_ctx* ctx, const double* Ueff, const double* n, const double* c,
+              int nstates, const double* colscale, double alpha, void* hpsi, int64_t ld);
+
+/* Dudarev energy per site (Eq. E_Dudarev; App. A for spinors):
+ * EU[I] = Ueff/2 sum_sigma Tr[n - n n] (unpolarized counts the channel
+ * twice).  Ueff, n, EU: device. */
+int hub_energy(hub_ctx* ctx, const double* Ueff, const double* n, double* EU);
+
+/* Hubbard forces (Sec. IV) with frozen sphere membership and normalization:
+ * F[I][i] = g_s * 2 Re sum_q w_k sum_s f_s sum_ab V_ab conj(d_{a,i}) c_b,
+ * d = dV sum_p exp(i k.T_p) (d phi_a / d r_i)(r_p) psi[g(p)], g_s = 2 for
+ * unpolarized contexts, else 1.  psi, c, f, Ueff, n, F: device. */
+int hub_forces(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
+               const double* f, const double* Ueff, const double* n, double* F);
+
+/* One whole Hubbard step (the metric's unit of work): project -> occupations
+ * (n, N-bar, P-bar) -> U-bar, J-bar, U_eff (or fixed U) -> hpsi += alpha V_U psi.
+ * All pointers are device pointers owned by the caller; see the layouts
+ * above.  mode: HUB_STEP_BATCHED, HUB_STEP_GRAPH (captured once per distinct
+ * argument set and replayed) or HUB_STEP_PERSITE (one launch per site and
+ * stage).  Needs the Coulomb tensors unless every site has a fixed U. */
+typedef struct hub_step_io {
+    const void* psi; int64_t ld; int nstates;
+    const double* f;
+    void* hpsi; int64_t ldh; double alpha;
+    double* c; double* n; double* pbar; double* nbar;
+    double* U; double* J; double* Ueff; int32_t* status;
+} hub_step_io;
+int hub_step(hub_ctx* ctx, const hub_step_io* io, int mode);
+
+/* Release the context and everything it owns (waits for its stream). */
+int hub_destroy(hub_ctx* ctx);
+
+/* Static message for a status code. */
+const char* hub_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUB_H */

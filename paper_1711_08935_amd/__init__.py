@@ -1,0 +1,346 @@
+"""MI355X (gfx950) DFT+U / ACBN0 Hubbard kernel: Python binding of libhub.so.
+
+This module only marshals arguments: every step of the Hubbard path runs in
+the HIP kernels of ``libhub.so`` (see ``include/hub.h`` for the C ABI, the
+layouts and the error codes).  PyTorch provides device memory and streams.
+Importing fails loudly when the library has not been built
+(``python -m paper_1711_08935_amd.build`` or ``__graft_entry__.build()``).
+"""
+
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhub.so")
+
+HUB_OK, HUB_EINVAL, HUB_ENOMEM, HUB_EDEVICE, HUB_ESTATE = 0, -1, -2, -3, -4
+HUB_WDEGENERATE = 1
+SPIN_MODES = {"unpolarized": 1, "collinear": 2, "spinor": 4}
+PRECISIONS = {"f64": 0, "f32": 1}
+STEP_MODES = {"batched": 0, "graph": 1, "persite": 2}
+LMAX = 7
+
+
+class HubError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {lib().hub_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+class StepIO(ctypes.Structure):
+    _fields_ = [("psi", ctypes.c_void_p), ("ld", ctypes.c_int64), ("nstates", ctypes.c_int),
+                ("f", ctypes.c_void_p), ("hpsi", ctypes.c_void_p), ("ldh", ctypes.c_int64),
+                ("alpha", ctypes.c_double), ("c", ctypes.c_void_p), ("n", ctypes.c_void_p),
+                ("pbar", ctypes.c_void_p), ("nbar", ctypes.c_void_p), ("U", ctypes.c_void_p),
+                ("J", ctypes.c_void_p), ("Ueff", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+_LIB = None
+EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff", "hub_set_chunk",
+           "hub_set_tuning", "hub_finalize_host", "hub_finalize", "hub_set_stream", "hub_query",
+           "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
+           "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
+           "hub_strerror"]
+
+
+def lib():
+    """Load libhub.so (once) and declare the C prototypes."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "hub_create": [ctypes.POINTER(P), DP, ctypes.POINTER(I), I, I, I],
+        "hub_set_kpoints": [P, I, DP, DP],
+        "hub_add_site": [P, DP, I, D, D, I, ctypes.POINTER(I)],
+        "hub_set_fixed_ueff": [P, I, D],
+        "hub_set_chunk": [P, I],
+        "hub_set_tuning": [P, I, I, I],
+        "hub_finalize_host": [P],
+        "hub_finalize": [P, P],
+        "hub_set_stream": [P, P],
+        "hub_query": [P, I, ctypes.POINTER(I64)],
+        "hub_site_info": [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I64), ctypes.POINTER(I)],
+        "hub_site_points": [P, I, P, P, P, P],
+        "hub_project": [P, P, I64, I, P],
+        "hub_occupations": [P, P, I, P, P, P, P],
+        "hub_coulomb": [P, I, P],
+        "hub_acbn0_uj": [P, P, P, P, P, P, P],
+        "hub_apply": [P, P, P, P, I, P, D, P, I64],
+        "hub_energy": [P, P, P, P],
+        "hub_forces": [P, P, I64, I, P, P, P, P, P],
+        "hub_step": [P, ctypes.POINTER(StepIO), I],
+        "hub_destroy": [P],
+        "hub_strerror": [I],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "hub_strerror" else I
+    _LIB = L
+    return L
+
+
+def _check(code, where):
+    if code < 0:
+        raise HubError(code, where)
+    return code
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _darr(vals):
+    arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+class Hubbard:
+    """One Hubbard context: geometry, k-points, shells, tables on the GPU.
+
+    ``sites``: iterable of dicts with keys R (3,), l, zeta, rc, species.
+    ``spin``: 'unpolarized' | 'collinear' | 'spinor'; ``precision``: 'f64'
+    (FP64 states) or 'f32' (FP32 states; orbital table, sums and all results
+    FP64).  Construction builds the host tables; ``finalize()`` uploads them.
+    """
+
+    def __init__(self, cell, ngrid, sites, kpts=None, kweights=None, spin="unpolarized",
+                 is_complex=False, precision="f64", chunk=None, finalize=True):
+        L = lib()
+        self._ctx = ctypes.c_void_p()
+        cell_a = _darr(cell)
+        ng = (ctypes.c_int * 3)(*[int(v) for v in ngrid])
+        _check(L.hub_create(ctypes.byref(self._ctx), cell_a, ng, SPIN_MODES[spin], int(bool(is_complex)),
+                            PRECISIONS[precision]), "hub_create")
+        self.cell = [float(v) for v in cell]
+        self.ngrid = [int(v) for v in ngrid]
+        self.spin = spin
+        self.is_complex = bool(is_complex)
+        self.precision = precision
+        if kpts is not None:
+            kp = [float(v) for row in kpts for v in row]
+            kw = [float(v) for v in kweights]
+            _check(L.hub_set_kpoints(self._ctx, len(kw), _darr(kp), _darr(kw)), "hub_set_kpoints")
+            self.kweights = kw
+        else:
+            self.kweights = [1.0]
+        for s in sites:
+            sid = ctypes.c_int()
+            _check(L.hub_add_site(self._ctx, _darr(s["R"]), int(s["l"]), float(s["zeta"]), float(s["rc"]),
+                                  int(s.get("species", 0)), ctypes.byref(sid)), "hub_add_site")
+        if chunk is not None:
+            _check(L.hub_set_chunk(self._ctx, int(chunk)), "hub_set_chunk")
+        _check(L.hub_finalize_host(self._ctx), "hub_finalize_host")
+        self.nsites = self.query(0)
+        self.J = self.query(1)
+        self.nsets = self.query(2)
+        self.nlayers = self.query(3)
+        self.nentries = self.query(4)
+        self.nchunks = self.query(5)
+        self.nspecies = self.query(6)
+        self.nk = self.query(7)
+        self.nblk = self.query(8)
+        self.site_L, self.site_orb0, self.site_npts, self.site_species = [], [], [], []
+        for s in range(self.nsites):
+            Lm, o, npts, sp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
+            _check(L.hub_site_info(self._ctx, s, ctypes.byref(Lm), ctypes.byref(o), ctypes.byref(npts),
+                                   ctypes.byref(sp)), "hub_site_info")
+            self.site_L.append(Lm.value)
+            self.site_orb0.append(o.value)
+            self.site_npts.append(npts.value)
+            self.site_species.append(sp.value)
+        self.dV = math.prod(c / n for c, n in zip(self.cell, self.ngrid))
+        self.G = math.prod(self.ngrid)
+        self.finalized = False
+        self._kw_dev = None
+        if finalize:
+            self.finalize()
+
+    # ------------------------------------------------------------ plumbing
+    def query(self, what):
+        v = ctypes.c_int64()
+        _check(lib().hub_query(self._ctx, what, ctypes.byref(v)), "hub_query")
+        return v.value
+
+    def finalize(self):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the Hubbard kernels need a ROCm GPU")
+        _check(lib().hub_finalize(self._ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "hub_finalize")
+        self.finalized = True
+        self.table_bytes = self.query(9)
+
+    def _stream(self):
+        _check(lib().hub_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+               "hub_set_stream")
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().hub_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fixed_ueff(self, site, ueff):
+        _check(lib().hub_set_fixed_ueff(self._ctx, int(site), float(ueff)), "hub_set_fixed_ueff")
+
+    def set_tuning(self, which, cols_per_lane, waves):
+        _check(lib().hub_set_tuning(self._ctx, int(which), int(cols_per_lane), int(waves)), "hub_set_tuning")
+
+    def site_points(self, site):
+        """Host copy of one site's sphere: (g, image3, phi, grad) numpy arrays."""
+        import numpy as np
+        n = self.site_npts[site]
+        Lm = self.site_L[site]
+        g = np.zeros(n, np.int32)
+        im = np.zeros((n, 3), np.int32)
+        phi = np.zeros((n, Lm))
+        grad = np.zeros((n, Lm, 3))
+        _check(lib().hub_site_points(self._ctx, int(site), g.ctypes.data, im.ctypes.data, phi.ctypes.data,
+                                     grad.ctypes.data), "hub_site_points")
+        return g, im, phi, grad
+
+    # --------------------------------------------------------- tensor help
+    @property
+    def state_dtype(self):
+        if self.precision == "f64":
+            return torch.complex128 if self.is_complex else torch.float64
+        return torch.complex64 if self.is_complex else torch.float32
+
+    @property
+    def coef_dtype(self):
+        return torch.complex128 if self.is_complex else torch.float64
+
+    def ncol(self, nstates):
+        return 2 * nstates if self.spin == "spinor" else nstates
+
+    def _states(self, psi, nstates=None):
+        """Validate a state tensor; returns (ld, nstates)."""
+        if psi.dtype != self.state_dtype:
+            raise TypeError(f"states must be {self.state_dtype}, got {psi.dtype}")
+        if not psi.is_cuda:
+            raise TypeError("states must live on the GPU")
+        if self.spin == "spinor" and psi.dim() == 4:
+            if psi.shape[3] != 2 or not psi[0, 0].is_contiguous():
+                raise ValueError("spinor states must be [nk][G][S][2] with contiguous (S, 2)")
+            S = psi.shape[2]
+            ld = psi.stride(1)
+        else:
+            if psi.dim() != 3 or psi.stride(2) != 1:
+                raise ValueError("states must be [nsets][G][ld-major columns] with unit column stride")
+            ld = psi.stride(1)
+            S = psi.shape[2] // (2 if self.spin == "spinor" else 1)
+        if psi.shape[0] != self.nsets or psi.shape[1] != self.G:
+            raise ValueError(f"states must have {self.nsets} sets of {self.G} grid points")
+        if psi.stride(0) != self.G * ld:
+            raise ValueError("state sets must be consecutive ([q][g][ld])")
+        return ld, (nstates if nstates is not None else S)
+
+    def _dev(self, t, dtype=torch.float64):
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"expected a contiguous {dtype} GPU tensor")
+        return t
+
+    def empty_c(self, nstates, grad=False):
+        rows = self.J * (3 if grad else 1)
+        return torch.empty((self.nsets, rows, self.ncol(nstates)), dtype=self.coef_dtype, device="cuda")
+
+    def empty_n(self):
+        return torch.empty((self.nsites, self.nblk, LMAX, LMAX), dtype=torch.complex128, device="cuda")
+
+    # ---------------------------------------------------------- entry points
+    def project(self, psi, nstates=None, out=None):
+        ld, S = self._states(psi, nstates)
+        c = out if out is not None else self.empty_c(S)
+        self._stream()
+        _check(lib().hub_project(self._ctx, _dptr(psi), ld, S, _dptr(c)), "hub_project")
+        return c
+
+    def occupations(self, c, f, with_pbar=True, nbar=True):
+        S = c.shape[2] // (2 if self.spin == "spinor" else 1)
+        f = self._dev(f)
+        n = self.empty_n()
+        pbar = self.empty_n() if with_pbar else None
+        nb = torch.empty((self.nsets, self.nspecies, S), dtype=torch.float64, device="cuda") if nbar else None
+        self._stream()
+        _check(lib().hub_occupations(self._ctx, _dptr(c), S, _dptr(f), _dptr(n), _dptr(pbar), _dptr(nb)),
+               "hub_occupations")
+        return n, pbar, nb
+
+    def coulomb(self, site=-1):
+        self._stream()
+        if site < 0:
+            _check(lib().hub_coulomb(self._ctx, -1, ctypes.c_void_p(0)), "hub_coulomb")
+            return None
+        Lm = self.site_L[site]
+        T = torch.empty((Lm, Lm, Lm, Lm), dtype=torch.float64, device="cuda")
+        _check(lib().hub_coulomb(self._ctx, int(site), _dptr(T)), "hub_coulomb")
+        return T
+
+    def acbn0(self, n, pbar):
+        U = torch.empty(self.nsites, dtype=torch.float64, device="cuda")
+        J = torch.empty_like(U)
+        Ueff = torch.empty_like(U)
+        st = torch.empty(self.nsites, dtype=torch.int32, device="cuda")
+        self._stream()
+        _check(lib().hub_acbn0_uj(self._ctx, _dptr(n), _dptr(pbar), _dptr(U), _dptr(J), _dptr(Ueff), _dptr(st)),
+               "hub_acbn0_uj")
+        return U, J, Ueff, st
+
+    def apply(self, Ueff, n, c, hpsi, alpha=1.0, colscale=None, nstates=None):
+        ld, S = self._states(hpsi, nstates)
+        self._stream()
+        _check(lib().hub_apply(self._ctx, _dptr(Ueff), _dptr(n), _dptr(c), S, _dptr(colscale), float(alpha),
+                               _dptr(hpsi), ld), "hub_apply")
+        return hpsi
+
+    def energy(self, Ueff, n):
+        EU = torch.empty(self.nsites, dtype=torch.float64, device="cuda")
+        self._stream()
+        _check(lib().hub_energy(self._ctx, _dptr(Ueff), _dptr(n), _dptr(EU)), "hub_energy")
+        return EU
+
+    def forces(self, psi, c, f, Ueff, n, nstates=None):
+        ld, S = self._states(psi, nstates)
+        F = torch.empty((self.nsites, 3), dtype=torch.float64, device="cuda")
+        self._stream()
+        _check(lib().hub_forces(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)), _dptr(Ueff),
+                                _dptr(n), _dptr(F)), "hub_forces")
+        return F
+
+    def step_buffers(self, nstates):
+        return dict(c=self.empty_c(nstates), n=self.empty_n(), pbar=self.empty_n(),
+                    nbar=torch.empty((self.nsets, self.nspecies, nstates), dtype=torch.float64, device="cuda"),
+                    U=torch.empty(self.nsites, dtype=torch.float64, device="cuda"),
+                    J=torch.empty(self.nsites, dtype=torch.float64, device="cuda"),
+                    Ueff=torch.empty(self.nsites, dtype=torch.float64, device="cuda"),
+                    status=torch.empty(self.nsites, dtype=torch.int32, device="cuda"))
+
+    def step(self, psi, f, hpsi, alpha=1.0, mode="graph", bufs=None, nstates=None):
+        """One Hubbard step; returns the dict of device buffers it filled."""
+        ld, S = self._states(psi, nstates)
+        ldh, S2 = self._states(hpsi, nstates)
+        if S2 != S:
+            raise ValueError("psi and hpsi hold different state counts")
+        b = bufs if bufs is not None else self.step_buffers(S)
+        io = StepIO(psi.data_ptr(), ld, S, self._dev(f).data_ptr(), hpsi.data_ptr(), ldh, float(alpha),
+                    b["c"].data_ptr(), b["n"].data_ptr(), b["pbar"].data_ptr(), b["nbar"].data_ptr(),
+                    b["U"].data_ptr(), b["J"].data_ptr(), b["Ueff"].data_ptr(), b["status"].data_ptr())
+        self._stream()
+        _check(lib().hub_step(self._ctx, ctypes.byref(io), STEP_MODES[mode]), "hub_step")
+        return b
+
+
+from .autograd import HubbardEnergy  # noqa: E402,F401

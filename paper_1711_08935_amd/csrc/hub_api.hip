@@ -1,0 +1,785 @@
+// C ABI of the Hubbard library (declared in include/hub.h): context
+// management, upload of the host tables, kernel-shape selection and the
+// sequencing of the launches for each entry point, including the per-step
+// hipGraph.  Every compute step runs in the HIP kernels of this directory.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ksmall.h"
+
+namespace {
+
+constexpr double kTwoPi = 6.28318530717958647692;
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+struct GraphKey {
+    hub_step_io io{};
+    int ncol = 0;
+    bool valid = false;
+};
+
+}  // namespace
+
+struct hub_ctx {
+    double cell[3];
+    int ngrid[3];
+    int spin_mode, is_complex, precision;
+    int nk = 1;
+    std::vector<double> kred{0.0, 0.0, 0.0}, kw{1.0};
+    std::vector<SiteDef> sites;
+    int chunk_entries = 1024;
+    int tune_cpl[2] = {0, 0};
+    int tune_waves[2] = {4, 4};
+    bool built_host = false, built_dev = false;
+    HostTables T;
+    int device = -1;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+
+    // device tables
+    HubChunk* d_chunks = nullptr;
+    int32_t *d_all = nullptr, *d_gidx = nullptr, *d_img = nullptr;
+    double *d_phi = nullptr, *d_gphi = nullptr, *d_phase = nullptr;
+    int32_t *d_site_chunk_ptr = nullptr, *d_site_chunk_ids = nullptr, *d_orb_site = nullptr;
+    int32_t *d_site_L = nullptr, *d_site_orb0 = nullptr, *d_site_species = nullptr;
+    int32_t *d_species_orb_ptr = nullptr, *d_species_orb_ids = nullptr;
+    double *d_kw = nullptr, *d_ueff_fixed = nullptr, *d_tensor = nullptr;
+    std::vector<char> have_tensor;
+    size_t table_bytes = 0;
+
+    // workspaces
+    double* d_part = nullptr;
+    size_t part_cap = 0;
+    double* d_grad = nullptr;
+    size_t grad_cap = 0;
+    double* d_nbar_ws = nullptr;
+    size_t nbar_cap = 0;
+
+    // captured step
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+
+    int nsets() const { return spin_mode == HUB_SPINOR ? nk : nk * (spin_mode == HUB_COLLINEAR ? 2 : 1); }
+    int nspin() const { return spin_mode == HUB_COLLINEAR ? 2 : 1; }
+    int nblk() const { return spin_mode == HUB_SPINOR ? 4 : (spin_mode == HUB_COLLINEAR ? 2 : 1); }
+    int ncplx() const { return is_complex ? 2 : 1; }
+    int ncol(int nstates) const { return spin_mode == HUB_SPINOR ? 2 * nstates : nstates; }
+    size_t elem() const { return (precision == HUB_F64 ? 8 : 4) * static_cast<size_t>(ncplx()); }
+    int64_t G() const { return static_cast<int64_t>(ngrid[0]) * ngrid[1] * ngrid[2]; }
+};
+
+namespace {
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return HUB_OK;
+    if (e == hipErrorOutOfMemory) return HUB_ENOMEM;
+    return HUB_EDEVICE;
+}
+
+#define HUB_TRY(expr)                          \
+    do {                                       \
+        hipError_t _e = (expr);                \
+        if (_e != hipSuccess) return map_err(_e); \
+    } while (0)
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src, size_t& bytes) {
+    const size_t nb = std::max<size_t>(1, src.size()) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), nb);
+    if (e != hipSuccess) return e;
+    bytes += nb;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+void release(hub_ctx* c) {
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(c->d_chunks); f(c->d_all); f(c->d_gidx); f(c->d_img); f(c->d_phi); f(c->d_gphi); f(c->d_phase);
+    f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
+    f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
+    f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+void drop_graph(hub_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gkey.valid = false;
+}
+
+int ensure(double** buf, size_t* cap, size_t n, hub_ctx* c) {
+    if (*cap >= n && *buf) return HUB_OK;
+    if (*buf) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+        drop_graph(c);
+    }
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(buf), std::max<size_t>(1, n) * sizeof(double));
+    if (e != hipSuccess) return map_err(e);
+    *cap = n;
+    return HUB_OK;
+}
+
+// Columns per lane: the widest vector that keeps every lane's columns
+// aligned and inside the row, and still fills one wave with columns.
+int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int ncol, int which) {
+    const size_t e = c->elem();
+    auto ok = [&](int cpl) {
+        const size_t vb = std::min<size_t>(16, cpl * e);
+        return (ld % cpl == 0) && (reinterpret_cast<uintptr_t>(ptr) % vb == 0);
+    };
+    const int want = c->tune_cpl[which];
+    if (want == 1 || ((want == 2 || want == 4) && ok(want))) return want;
+    for (int cpl : {4, 2}) {
+        if (ok(cpl) && ncol >= 64 * cpl) return cpl;
+    }
+    return 1;
+}
+
+bool built(const hub_ctx* c) { return c && c->built_dev; }
+
+ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad) {
+    ProjArgs a{};
+    a.psi = psi;
+    a.ld = ld;
+    a.qstride = c->G() * ld * c->ncplx();
+    a.ncol = ncol;
+    a.nspin = c->nspin();
+    a.spinor = c->spin_mode == HUB_SPINOR;
+    a.chunks = c->d_chunks;
+    a.chunk_list = c->d_all;
+    a.gidx = c->d_gidx;
+    a.img = c->d_img;
+    a.tab = grad ? c->d_gphi : c->d_phi;
+    a.tabmult = grad ? 3 : 1;
+    a.phase = c->d_phase;
+    a.nimg = static_cast<int>(c->T.images.size() / 3);
+    a.prows = c->T.part_rows * a.tabmult;
+    return a;
+}
+
+ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
+    ReduceArgs r{};
+    r.part = c->d_part;
+    r.prows = c->T.part_rows * mult;
+    r.out = out;
+    r.nrows = c->T.J * mult;
+    r.ncol = ncol;
+    r.ncplx = c->ncplx();
+    r.mult = mult;
+    r.chunks = c->d_chunks;
+    r.site_chunk_ptr = c->d_site_chunk_ptr;
+    r.site_chunk_ids = c->d_site_chunk_ids;
+    r.orb_site = c->d_orb_site;
+    r.site_orb0 = c->d_site_orb0;
+    r.dV = (c->cell[0] / c->ngrid[0]) * (c->cell[1] / c->ngrid[1]) * (c->cell[2] / c->ngrid[2]);
+    return r;
+}
+
+// project + reduce into c (per_site: one projection launch per site)
+int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site, bool grad) {
+    const int ncol = c->ncol(nstates);
+    const int mult = grad ? 3 : 1;
+    const size_t need = static_cast<size_t>(c->nsets()) * c->T.part_rows * mult * ncol * c->ncplx();
+    int st = ensure(&c->d_part, &c->part_cap, need, c);
+    if (st) return st;
+    ProjArgs a = proj_args(c, psi, ld, ncol, grad);
+    a.part = c->d_part;
+    const int cpl = pick_cpl(c, psi, ld, ncol, 0);
+    const int waves = c->tune_waves[0];
+    if (!per_site) {
+        HUB_TRY(launch_project(a, static_cast<int>(c->T.chunks.size()), c->nsets(), c->precision, c->is_complex,
+                               cpl, waves, c->stream));
+    } else {
+        for (int s = 0; s < c->T.nsites; ++s) {
+            ProjArgs b = a;
+            b.chunk_list = c->d_site_chunk_ids + c->T.site_chunk_ptr[s];
+            HUB_TRY(launch_project(b, c->T.site_chunk_ptr[s + 1] - c->T.site_chunk_ptr[s], c->nsets(), c->precision,
+                                   c->is_complex, cpl, waves, c->stream));
+        }
+    }
+    ReduceArgs r = reduce_args(c, out, ncol, mult);
+    HUB_TRY(launch_reduce(r, c->nsets(), c->stream));
+    return HUB_OK;
+}
+
+int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, double* n, double* pbar, double* nbar,
+                   bool per_site) {
+    const int ncol = c->ncol(nstates);
+    if (pbar && !nbar) {
+        const size_t need = static_cast<size_t>(c->nsets()) * c->T.nspecies * nstates;
+        int st = ensure(&c->d_nbar_ws, &c->nbar_cap, need, c);
+        if (st) return st;
+        nbar = c->d_nbar_ws;
+    }
+    if (nbar) {
+        NbarArgs b{};
+        b.c = cc;
+        b.nbar = nbar;
+        b.J = c->T.J;
+        b.ncol = ncol;
+        b.nstates = nstates;
+        b.ncplx = c->ncplx();
+        b.spinor = c->spin_mode == HUB_SPINOR;
+        b.nspecies = c->T.nspecies;
+        b.species_orb_ptr = c->d_species_orb_ptr;
+        b.species_orb_ids = c->d_species_orb_ids;
+        HUB_TRY(launch_nbar(b, c->nsets(), c->stream));
+    }
+    OccArgs o{};
+    o.c = cc;
+    o.f = f;
+    o.nbar = nbar;
+    o.n = n;
+    o.pbar = pbar;
+    o.kweights = c->d_kw;
+    o.site_L = c->d_site_L;
+    o.site_orb0 = c->d_site_orb0;
+    o.site_species = c->d_site_species;
+    o.J = c->T.J;
+    o.ncol = ncol;
+    o.nstates = nstates;
+    o.ncplx = c->ncplx();
+    o.spinor = c->spin_mode == HUB_SPINOR;
+    o.nspin = c->nspin();
+    o.nk = c->nk;
+    o.nblk = c->nblk();
+    o.nspecies = c->T.nspecies;
+    if (!per_site) {
+        HUB_TRY(launch_occ(o, 0, c->T.nsites, c->stream));
+    } else {
+        for (int s = 0; s < c->T.nsites; ++s) HUB_TRY(launch_occ(o, s, 1, c->stream));
+    }
+    return HUB_OK;
+}
+
+bool need_tensors(const hub_ctx* c) {
+    for (size_t s = 0; s < c->sites.size(); ++s)
+        if (std::isnan(c->sites[s].ueff_fixed) && !c->have_tensor[s]) return true;
+    return false;
+}
+
+int do_acbn0(hub_ctx* c, const double* n, const double* pbar, double* U, double* J, double* Ueff, int32_t* status,
+             bool per_site) {
+    Acbn0Args a{};
+    a.n = n;
+    a.pbar = pbar;
+    a.tensor = c->d_tensor;
+    a.site_L = c->d_site_L;
+    a.ueff_fixed = c->d_ueff_fixed;
+    a.U = U;
+    a.J = J;
+    a.Ueff = Ueff;
+    a.status = status;
+    a.nblk = c->nblk();
+    if (!per_site) {
+        HUB_TRY(launch_acbn0(a, 0, c->T.nsites, c->stream));
+    } else {
+        for (int s = 0; s < c->T.nsites; ++s) HUB_TRY(launch_acbn0(a, s, 1, c->stream));
+    }
+    return HUB_OK;
+}
+
+int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, int nstates, const double* colscale,
+             double alpha, void* hpsi, int64_t ld, bool per_site) {
+    const int ncol = c->ncol(nstates);
+    ApplyArgs a{};
+    a.hpsi = hpsi;
+    a.ld = ld;
+    a.qstride = c->G() * ld * c->ncplx();
+    a.ncol = ncol;
+    a.nstates = nstates;
+    a.nspin = c->nspin();
+    a.spinor = c->spin_mode == HUB_SPINOR;
+    a.nblk = c->nblk();
+    a.chunks = c->d_chunks;
+    a.gidx = c->d_gidx;
+    a.img = c->d_img;
+    a.tab = c->d_phi;
+    a.phase = c->d_phase;
+    a.nimg = static_cast<int>(c->T.images.size() / 3);
+    a.c = cc;
+    a.J = c->T.J;
+    a.n = n;
+    a.ueff = Ueff;
+    a.colscale = colscale;
+    a.alpha = alpha;
+    const int cpl = pick_cpl(c, hpsi, ld, ncol, 1);
+    const int waves = c->tune_waves[1];
+    const int ns = c->T.nsites;
+    for (int lay = 0; lay < c->T.nlayers; ++lay) {
+        if (!per_site) {
+            ApplyArgs b = a;
+            const int c0 = c->T.layer_chunk_ptr[lay];
+            b.chunk_list = c->d_all + c0;
+            HUB_TRY(launch_apply(b, c->T.layer_chunk_ptr[lay + 1] - c0, c->nsets(), c->precision, c->is_complex, cpl,
+                                 waves, c->stream));
+        } else {
+            for (int s = 0; s < ns; ++s) {
+                const int c0 = c->T.layer_site_ptr[static_cast<size_t>(lay) * ns + s];
+                const int c1 = c->T.layer_site_ptr[static_cast<size_t>(lay) * ns + s + 1];
+                if (c1 <= c0) continue;
+                ApplyArgs b = a;
+                b.chunk_list = c->d_all + c0;
+                HUB_TRY(launch_apply(b, c1 - c0, c->nsets(), c->precision, c->is_complex, cpl, waves, c->stream));
+            }
+        }
+    }
+    return HUB_OK;
+}
+
+int run_step(hub_ctx* c, const hub_step_io* io, bool per_site) {
+    int st = do_project(c, io->psi, io->ld, io->nstates, io->c, per_site, false);
+    if (st) return st;
+    st = do_occupations(c, io->c, io->nstates, io->f, io->n, io->pbar, io->nbar, per_site);
+    if (st) return st;
+    st = do_acbn0(c, io->n, io->pbar, io->U, io->J, io->Ueff, io->status, per_site);
+    if (st) return st;
+    return do_apply(c, io->Ueff, io->n, io->c, io->nstates, nullptr, io->alpha, io->hpsi, io->ldh, per_site);
+}
+
+bool valid_states(const hub_ctx* c, const void* psi, int64_t ld, int nstates) {
+    return psi != nullptr && nstates >= 1 && ld >= c->ncol(nstates);
+}
+
+}  // namespace
+
+// =====================================================================  ABI
+
+extern "C" {
+
+const char* hub_strerror(int code) {
+    switch (code) {
+    case HUB_OK: return "ok";
+    case HUB_EINVAL: return "invalid argument";
+    case HUB_ENOMEM: return "out of memory";
+    case HUB_EDEVICE: return "HIP device error";
+    case HUB_ESTATE: return "call not valid in the current context state";
+    case HUB_WDEGENERATE: return "degenerate U/J denominator";
+    default: return "unknown status";
+    }
+}
+
+int hub_create(hub_ctx** out, const double cell[3], const int ngrid[3], int spin_mode, int is_complex,
+               int precision) {
+    if (!out || !cell || !ngrid) return HUB_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < 3; ++i)
+        if (!(cell[i] > 0.0) || !std::isfinite(cell[i]) || ngrid[i] < 1) return HUB_EINVAL;
+    if (spin_mode != HUB_UNPOLARIZED && spin_mode != HUB_COLLINEAR && spin_mode != HUB_SPINOR) return HUB_EINVAL;
+    if (is_complex != 0 && is_complex != 1) return HUB_EINVAL;
+    if (spin_mode == HUB_SPINOR && !is_complex) return HUB_EINVAL;
+    if (precision != HUB_F64 && precision != HUB_F32) return HUB_EINVAL;
+    if (static_cast<int64_t>(ngrid[0]) * ngrid[1] * ngrid[2] > INT32_MAX) return HUB_EINVAL;
+    hub_ctx* c = new (std::nothrow) hub_ctx();
+    if (!c) return HUB_ENOMEM;
+    for (int i = 0; i < 3; ++i) {
+        c->cell[i] = cell[i];
+        c->ngrid[i] = ngrid[i];
+    }
+    c->spin_mode = spin_mode;
+    c->is_complex = is_complex;
+    c->precision = precision;
+    *out = c;
+    return HUB_OK;
+}
+
+int hub_set_kpoints(hub_ctx* c, int nk, const double* k_red, const double* w) {
+    if (!c || nk < 1 || !k_red || !w) return HUB_EINVAL;
+    if (c->built_host) return HUB_ESTATE;
+    for (int i = 0; i < 3 * nk; ++i) {
+        if (!std::isfinite(k_red[i])) return HUB_EINVAL;
+        if (!c->is_complex && k_red[i] != 0.0) return HUB_EINVAL;
+    }
+    for (int i = 0; i < nk; ++i)
+        if (!std::isfinite(w[i])) return HUB_EINVAL;
+    c->nk = nk;
+    c->kred.assign(k_red, k_red + 3 * nk);
+    c->kw.assign(w, w + nk);
+    return HUB_OK;
+}
+
+int hub_add_site(hub_ctx* c, const double R[3], int l, double zeta, double rc, int species, int* site_id) {
+    if (!c || !R) return HUB_EINVAL;
+    if (c->built_host) return HUB_ESTATE;
+    if (l < 0 || l > 3 || !(zeta > 0.0) || !(rc > 0.0) || !std::isfinite(zeta) || !std::isfinite(rc)) return HUB_EINVAL;
+    if (species < 0 || species >= HUB_MAX_SPECIES) return HUB_EINVAL;
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(R[i])) return HUB_EINVAL;
+    SiteDef s;
+    for (int i = 0; i < 3; ++i) s.R[i] = R[i];
+    s.l = l;
+    s.zeta = zeta;
+    s.rc = rc;
+    s.species = species;
+    s.ueff_fixed = std::nan("");
+    c->sites.push_back(s);
+    if (site_id) *site_id = static_cast<int>(c->sites.size()) - 1;
+    return HUB_OK;
+}
+
+int hub_set_fixed_ueff(hub_ctx* c, int site, double ueff) {
+    if (!c || site < 0 || site >= static_cast<int>(c->sites.size())) return HUB_EINVAL;
+    if (std::isinf(ueff)) return HUB_EINVAL;
+    c->sites[site].ueff_fixed = ueff;
+    if (c->built_dev) {
+        hipError_t e = hipMemcpyAsync(c->d_ueff_fixed + site, &c->sites[site].ueff_fixed, sizeof(double),
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        drop_graph(c);
+        return map_err(e);
+    }
+    return HUB_OK;
+}
+
+int hub_set_chunk(hub_ctx* c, int chunk_entries) {
+    if (!c || chunk_entries < 64 || chunk_entries > 65536) return HUB_EINVAL;
+    if (c->built_host) return HUB_ESTATE;
+    c->chunk_entries = chunk_entries;
+    return HUB_OK;
+}
+
+int hub_set_tuning(hub_ctx* c, int which, int cpl, int waves) {
+    if (!c || (which != 0 && which != 1)) return HUB_EINVAL;
+    if (cpl != 0 && cpl != 1 && cpl != 2 && cpl != 4) return HUB_EINVAL;
+    if (waves != 1 && waves != 2 && waves != 4) return HUB_EINVAL;
+    c->tune_cpl[which] = cpl;
+    c->tune_waves[which] = waves;
+    drop_graph(c);
+    return HUB_OK;
+}
+
+int hub_finalize_host(hub_ctx* c) {
+    if (!c) return HUB_EINVAL;
+    if (c->built_host) return HUB_OK;
+    if (c->sites.empty()) return HUB_EINVAL;
+    int st;
+    try {
+        st = hub_build_host(c->cell, c->ngrid, c->sites, c->chunk_entries, c->T);
+    } catch (const std::bad_alloc&) {
+        return HUB_ENOMEM;
+    } catch (...) {
+        return HUB_EINVAL;
+    }
+    if (st) return st;
+    c->have_tensor.assign(c->sites.size(), 0);
+    c->built_host = true;
+    return HUB_OK;
+}
+
+int hub_finalize(hub_ctx* c, void* stream) {
+    if (!c) return HUB_EINVAL;
+    int st = hub_finalize_host(c);
+    if (st) return st;
+    if (c->built_dev) return HUB_OK;
+    HUB_TRY(hipGetDevice(&c->device));
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    const HostTables& T = c->T;
+    std::vector<int32_t> all(T.chunks.size());
+    for (size_t i = 0; i < all.size(); ++i) all[i] = static_cast<int32_t>(i);
+    const int nimg = static_cast<int>(T.images.size() / 3);
+    std::vector<double> phase(static_cast<size_t>(c->nk) * nimg * 2);
+    for (int k = 0; k < c->nk; ++k)
+        for (int i = 0; i < nimg; ++i) {
+            const double t = c->kred[3 * k] * T.images[3 * i] + c->kred[3 * k + 1] * T.images[3 * i + 1] +
+                             c->kred[3 * k + 2] * T.images[3 * i + 2];
+            phase[(static_cast<size_t>(k) * nimg + i) * 2] = std::cos(kTwoPi * t);
+            phase[(static_cast<size_t>(k) * nimg + i) * 2 + 1] = std::sin(kTwoPi * t);
+        }
+    std::vector<double> fixed(c->sites.size());
+    for (size_t s = 0; s < fixed.size(); ++s) fixed[s] = c->sites[s].ueff_fixed;
+    size_t& b = c->table_bytes;
+    b = 0;
+    hipError_t e = hipSuccess;
+    auto up = [&](auto** dst, const auto& src) {
+        if (e == hipSuccess) e = upload(dst, src, b);
+    };
+    up(&c->d_chunks, T.chunks);
+    up(&c->d_all, all);
+    up(&c->d_gidx, T.gidx);
+    up(&c->d_img, T.img);
+    up(&c->d_phi, T.phi);
+    up(&c->d_gphi, T.gphi);
+    up(&c->d_phase, phase);
+    up(&c->d_site_chunk_ptr, T.site_chunk_ptr);
+    up(&c->d_site_chunk_ids, T.site_chunk_ids);
+    up(&c->d_orb_site, T.orb_site);
+    up(&c->d_site_L, T.site_L);
+    up(&c->d_site_orb0, T.site_orb0);
+    up(&c->d_site_species, T.site_species);
+    up(&c->d_species_orb_ptr, T.species_orb_ptr);
+    up(&c->d_species_orb_ids, T.species_orb_ids);
+    up(&c->d_kw, c->kw);
+    up(&c->d_ueff_fixed, fixed);
+    if (e == hipSuccess) {
+        e = hipMalloc(reinterpret_cast<void**>(&c->d_tensor), c->sites.size() * 2401 * sizeof(double));
+        b += c->sites.size() * 2401 * sizeof(double);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        release(c);
+        return map_err(e);
+    }
+    c->built_dev = true;
+    return HUB_OK;
+}
+
+int hub_set_stream(hub_ctx* c, void* stream) {
+    if (!c) return HUB_EINVAL;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    return HUB_OK;
+}
+
+int hub_query(const hub_ctx* c, int what, int64_t* v) {
+    if (!c || !v) return HUB_EINVAL;
+    if (!c->built_host) return HUB_ESTATE;
+    const HostTables& T = c->T;
+    switch (what) {
+    case 0: *v = T.nsites; break;
+    case 1: *v = T.J; break;
+    case 2: *v = c->nsets(); break;
+    case 3: *v = T.nlayers; break;
+    case 4: *v = T.nentries; break;
+    case 5: *v = static_cast<int64_t>(T.chunks.size()); break;
+    case 6: *v = T.nspecies; break;
+    case 7: *v = c->nk; break;
+    case 8: *v = c->nblk(); break;
+    case 9: *v = static_cast<int64_t>(c->table_bytes); break;
+    case 10: *v = T.part_rows; break;
+    default: return HUB_EINVAL;
+    }
+    return HUB_OK;
+}
+
+int hub_site_info(const hub_ctx* c, int site, int* L, int* orb_offset, int64_t* npoints, int* species) {
+    if (!c) return HUB_EINVAL;
+    if (!c->built_host) return HUB_ESTATE;
+    if (site < 0 || site >= c->T.nsites) return HUB_EINVAL;
+    if (L) *L = c->T.site_L[site];
+    if (orb_offset) *orb_offset = c->T.site_orb0[site];
+    if (npoints) *npoints = static_cast<int64_t>(c->T.spheres[site].g.size());
+    if (species) *species = c->T.site_species[site];
+    return HUB_OK;
+}
+
+int hub_site_points(const hub_ctx* c, int site, int32_t* g, int32_t* image3, double* phi, double* grad) {
+    if (!c) return HUB_EINVAL;
+    if (!c->built_host) return HUB_ESTATE;
+    if (site < 0 || site >= c->T.nsites) return HUB_EINVAL;
+    const SiteSphere& s = c->T.spheres[site];
+    if (g) std::memcpy(g, s.g.data(), s.g.size() * sizeof(int32_t));
+    if (image3) std::memcpy(image3, s.img3.data(), s.img3.size() * sizeof(int32_t));
+    if (phi) std::memcpy(phi, s.phi.data(), s.phi.size() * sizeof(double));
+    if (grad) std::memcpy(grad, s.grad.data(), s.grad.size() * sizeof(double));
+    return HUB_OK;
+}
+
+int hub_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* cout) {
+    if (!c || !cout) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
+    return do_project(c, psi, ld, nstates, cout, false, false);
+}
+
+int hub_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, double* n, double* pbar,
+                    double* nbar) {
+    if (!c || !cc || !f || !n || nstates < 1) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    return do_occupations(c, cc, nstates, f, n, pbar, nbar, false);
+}
+
+int hub_coulomb(hub_ctx* c, int site, double* tensor) {
+    if (!c) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    const int ns = c->T.nsites;
+    if (site < -1 || site >= ns) return HUB_EINVAL;
+    if (site == -1 && tensor) return HUB_EINVAL;
+    const int s0 = site < 0 ? 0 : site, s1 = site < 0 ? ns : site + 1;
+    size_t maxp = 1;
+    for (int s = s0; s < s1; ++s) maxp = std::max(maxp, c->T.spheres[s].g.size());
+    int32_t* d_ijk = nullptr;
+    double *d_phi = nullptr, *d_rho = nullptr, *d_W = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_ijk), maxp * 3 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_phi), maxp * 7 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_rho), maxp * 28 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_W), maxp * 28 * sizeof(double));
+    double h[3];
+    for (int i = 0; i < 3; ++i) h[i] = c->cell[i] / c->ngrid[i];
+    const double g0 = hub_g0_cell_average(h);
+    for (int s = s0; s < s1 && e == hipSuccess; ++s) {
+        const SiteSphere& sp = c->T.spheres[s];
+        const int L = c->T.site_L[s];
+        e = hipMemcpyAsync(d_ijk, sp.ijk.data(), sp.ijk.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_phi, sp.phi.data(), sp.phi.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) break;
+        CoulombArgs a{};
+        a.ijk = d_ijk;
+        a.phi = d_phi;
+        a.P = static_cast<int>(sp.g.size());
+        a.L = L;
+        a.npair = L * (L + 1) / 2;
+        a.rho = d_rho;
+        a.W = d_W;
+        a.tensor = c->d_tensor + static_cast<size_t>(s) * 2401;
+        for (int i = 0; i < 3; ++i) a.h[i] = h[i];
+        a.g0 = g0;
+        a.dV = h[0] * h[1] * h[2];
+        e = launch_coulomb(a, c->stream);
+        if (e == hipSuccess && tensor)
+            e = hipMemcpyAsync(tensor, a.tensor, static_cast<size_t>(L) * L * L * L * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream);
+        // host arrays are reused next iteration: wait for the copies
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) c->have_tensor[s] = 1;
+    }
+    if (d_ijk) (void)hipFree(d_ijk);
+    if (d_phi) (void)hipFree(d_phi);
+    if (d_rho) (void)hipFree(d_rho);
+    if (d_W) (void)hipFree(d_W);
+    return map_err(e);
+}
+
+int hub_acbn0_uj(hub_ctx* c, const double* n, const double* pbar, double* U, double* J, double* Ueff,
+                 int* status) {
+    if (!c || !n || !pbar || !U || !J || !Ueff) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (need_tensors(c)) return HUB_ESTATE;
+    return do_acbn0(c, n, pbar, U, J, Ueff, reinterpret_cast<int32_t*>(status), false);
+}
+
+int hub_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, int nstates,
+              const double* colscale, double alpha, void* hpsi, int64_t ld) {
+    if (!c || !Ueff || !n || !cc) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, hpsi, ld, nstates) || !std::isfinite(alpha)) return HUB_EINVAL;
+    return do_apply(c, Ueff, n, cc, nstates, colscale, alpha, hpsi, ld, false);
+}
+
+int hub_energy(hub_ctx* c, const double* Ueff, const double* n, double* EU) {
+    if (!c || !Ueff || !n || !EU) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    EnergyArgs a{};
+    a.n = n;
+    a.Ueff = Ueff;
+    a.EU = EU;
+    a.site_L = c->d_site_L;
+    a.nsites = c->T.nsites;
+    a.nblk = c->nblk();
+    HUB_TRY(launch_energy(a, c->stream));
+    return HUB_OK;
+}
+
+int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
+               const double* Ueff, const double* n, double* F) {
+    if (!c || !cc || !f || !Ueff || !n || !F) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
+    const int ncol = c->ncol(nstates);
+    const size_t need = static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx();
+    int st = ensure(&c->d_grad, &c->grad_cap, need, c);
+    if (st) return st;
+    st = do_project(c, psi, ld, nstates, c->d_grad, false, true);
+    if (st) return st;
+    ForceArgs a{};
+    a.c = cc;
+    a.d = c->d_grad;
+    a.f = f;
+    a.n = n;
+    a.ueff = Ueff;
+    a.kweights = c->d_kw;
+    a.F = F;
+    a.site_L = c->d_site_L;
+    a.site_orb0 = c->d_site_orb0;
+    a.nsites = c->T.nsites;
+    a.J = c->T.J;
+    a.ncol = ncol;
+    a.nstates = nstates;
+    a.ncplx = c->ncplx();
+    a.spinor = c->spin_mode == HUB_SPINOR;
+    a.nspin = c->nspin();
+    a.nq = c->nsets();
+    a.nblk = c->nblk();
+    HUB_TRY(launch_forces(a, c->stream));
+    return HUB_OK;
+}
+
+int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
+    if (!c || !io) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, io->psi, io->ld, io->nstates) || !valid_states(c, io->hpsi, io->ldh, io->nstates))
+        return HUB_EINVAL;
+    if (!io->f || !io->c || !io->n || !io->pbar || !io->U || !io->J || !io->Ueff || !std::isfinite(io->alpha))
+        return HUB_EINVAL;
+    if (mode != HUB_STEP_BATCHED && mode != HUB_STEP_GRAPH && mode != HUB_STEP_PERSITE) return HUB_EINVAL;
+    if (need_tensors(c)) return HUB_ESTATE;
+    // the step needs the projection workspace and the N-bar buffer; size them
+    // before any capture so that the graph never sees a reallocation
+    const int ncol = c->ncol(io->nstates);
+    int st = ensure(&c->d_part, &c->part_cap,
+                    static_cast<size_t>(c->nsets()) * c->T.part_rows * ncol * c->ncplx(), c);
+    if (st) return st;
+    if (!io->nbar) {
+        st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);
+        if (st) return st;
+    }
+    if (mode != HUB_STEP_GRAPH) return run_step(c, io, mode == HUB_STEP_PERSITE);
+
+    const bool same = c->gkey.valid && c->gkey.ncol == ncol && std::memcmp(&c->gkey.io, io, sizeof(hub_step_io)) == 0;
+    if (!same) {
+        drop_graph(c);
+        HUB_TRY(hipStreamSynchronize(c->stream));
+        hipStream_t keep = c->stream;
+        c->stream = c->cap_stream;
+        HUB_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        st = run_step(c, io, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        c->stream = keep;
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return map_err(e);
+        c->graph = g;
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(c);
+            return map_err(e);
+        }
+        c->gkey.io = *io;
+        c->gkey.ncol = ncol;
+        c->gkey.valid = true;
+    }
+    HUB_TRY(hipGraphLaunch(c->gexec, c->stream));
+    return HUB_OK;
+}
+
+int hub_destroy(hub_ctx* c) {
+    if (!c) return HUB_EINVAL;
+    if (c->built_dev) (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+    return HUB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal declarations shared by the host builder, the C-ABI layer and the
+// HIP kernels of the Hubbard library.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "hub.h"
+
+// One work-list chunk: a run of sphere entries of one site inside one apply
+// layer.  Within a layer no two entries share a grid point, so chunks of the
+// same layer can be applied concurrently without atomics.
+struct HubChunk {
+    int32_t site;
+    int32_t layer;
+    int32_t e0;      // first entry
+    int32_t ne;      // number of entries
+    int32_t L;       // orbitals of the site (2l+1)
+    int32_t orb0;    // global index j of the site's first orbital
+    int32_t part0;   // first row of this chunk in the projection workspace
+    int32_t species;
+    int64_t phi0;    // offset of the chunk's orbital values (entries * L)
+};
+
+struct SiteDef {
+    double R[3];
+    int l;
+    double zeta;
+    double rc;
+    int species;
+    double ueff_fixed;   // NaN: ACBN0
+};
+
+// Host copy of one site's sphere, points sorted by (g, image).
+struct SiteSphere {
+    std::vector<int32_t> g;      // folded grid index
+    std::vector<int32_t> img3;   // lattice image (3 per point)
+    std::vector<int32_t> ijk;    // unfolded integer coordinates (3 per point)
+    std::vector<double> phi;     // [p][m]
+    std::vector<double> grad;    // [p][m][3]
+};
+
+struct HostTables {
+    int nsites = 0, J = 0, nlayers = 0, nspecies = 0;
+    std::vector<int32_t> site_L, site_orb0, site_species;
+    std::vector<HubChunk> chunks;            // sorted by (layer, site)
+    std::vector<int32_t> gidx, img;          // per entry
+    std::vector<double> phi;                 // per entry, L values
+    std::vector<double> gphi;                // per entry, 3L values [m][i]
+    std::vector<int32_t> images;             // unique lattice images, 3 per image
+    std::vector<int32_t> site_chunk_ptr;     // CSR site -> chunk ids
+    std::vector<int32_t> site_chunk_ids;
+    std::vector<int32_t> layer_chunk_ptr;    // chunks of layer l: [ptr[l], ptr[l+1])
+    std::vector<int32_t> layer_site_ptr;     // chunk range of (layer, site): [l*nsites+s]
+    std::vector<int32_t> species_orb_ptr;    // CSR species -> orbital j
+    std::vector<int32_t> species_orb_ids;
+    std::vector<int32_t> orb_site;           // j -> site
+    int64_t part_rows = 0;                   // sum of L over chunks
+    int64_t nentries = 0;
+    std::vector<SiteSphere> spheres;
+};
+
+// Host builder (sphere.cpp).  Returns HUB_OK or a negative status.
+int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<SiteDef>& sites,
+                   int chunk_entries, HostTables& out);
+
+// Closed-form average of 1/|r| over one grid cell centred at the origin.
+double hub_g0_cell_average(const double h[3]);

@@ -1,0 +1,209 @@
+// Apply kernel: hpsi_q[g][col] += alpha * scale * (V_U psi)_q[g][col] for the
+// entries of one work-list chunk (Eq. pot_V_U).
+//
+// Per lane and column: B_a = sum_b V_ab c_b with V_ab = Ueff (delta_ab/2 -
+// n_ba) of the chunk's site and spin channel (spinor: B^s_a = sum_{s' b}
+// V^{ss'}_ab c^{s'}_b, V^{ss'}_ab = Ueff (delta delta / 2 - n^{s's}_ba)); the
+// transpose follows from differentiating E_U (Eq. minimization).  Then for
+// every sphere entry e of the chunk:
+//   hpsi[g_e][col] += exp(-i k.T_e) sum_a phi_a(e) B_a(col).
+// The host groups entries in layers that never repeat a grid point, and
+// launches one layer at a time, so no two lanes in flight update the same
+// element: no atomics, deterministic results.  Sums are FP64; the updated
+// element is rounded once to the storage type.
+//
+// Work mapping: blockIdx.x = chunk, blockIdx.y = column tile, blockIdx.z =
+// state set; each wave of the work-group takes interleaved entries (no
+// reduction needed; B is recomputed per wave).
+
+#include "kcommon.h"
+
+namespace {
+
+template <bool CPX, bool SPINOR, int CPL, int L>
+__device__ __forceinline__ void coefficients(const ApplyArgs& a, const HubChunk& C, int q, int col0,
+                                             double (&B)[L][CPL * (CPX ? 2 : 1)]) {
+    constexpr int NC = CPX ? 2 : 1;
+    const double U = a.ueff[C.site];
+    const int ch = SPINOR ? 0 : (q % a.nspin);
+    const double* __restrict__ nb = a.n + static_cast<int64_t>(C.site) * a.nblk * 98;
+    const double* __restrict__ cq = a.c + (static_cast<int64_t>(q) * a.J + C.orb0) * a.ncol * NC;
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+        const int col = col0 + cc;
+        const bool ok = col < a.ncol;
+        double sc = a.alpha;
+        if (a.colscale != nullptr && ok) {
+            const int s = SPINOR ? (col >> 1) : col;
+            sc *= a.colscale[static_cast<int64_t>(q) * a.nstates + s];
+        }
+        if (!ok) sc = 0.0;
+        if constexpr (!SPINOR) {
+            double cv[L][NC];
+#pragma unroll
+            for (int b = 0; b < L; ++b)
+#pragma unroll
+                for (int r = 0; r < NC; ++r) cv[b][r] = ok ? cq[(static_cast<int64_t>(b) * a.ncol + col) * NC + r] : 0.0;
+            const double* __restrict__ nm = nb + ch * 98;
+#pragma unroll
+            for (int ai = 0; ai < L; ++ai) {
+                double br = 0.0, bi = 0.0;
+#pragma unroll
+                for (int b = 0; b < L; ++b) {
+                    // V_ab = U (delta_ab / 2 - n_ba)
+                    const double vr = U * ((ai == b ? 0.5 : 0.0) - nm[(b * 7 + ai) * 2]);
+                    if constexpr (CPX) {
+                        const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
+                        br = fma(vr, cv[b][0], fma(-vi, cv[b][1], br));
+                        bi = fma(vr, cv[b][1], fma(vi, cv[b][0], bi));
+                    } else {
+                        br = fma(vr, cv[b][0], br);
+                    }
+                }
+                B[ai][cc * NC] = sc * br;
+                if constexpr (CPX) B[ai][cc * NC + 1] = sc * bi;
+            }
+        } else {
+            // spinor columns 2s + sigma; V^{sigma sigma'}_ab = U (dd/2 - n^{sigma' sigma}_ba)
+            const int sg = col & 1;
+            const int base = col - sg;
+            double cv[2][L][2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int b = 0; b < L; ++b)
+#pragma unroll
+                    for (int r = 0; r < 2; ++r)
+                        cv[t][b][r] = ok ? cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2 + r] : 0.0;
+#pragma unroll
+            for (int ai = 0; ai < L; ++ai) {
+                double br = 0.0, bi = 0.0;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const double* __restrict__ nm = nb + (2 * t + sg) * 98;   // block (sigma' = t, sigma = sg)
+#pragma unroll
+                    for (int b = 0; b < L; ++b) {
+                        const double vr = U * ((ai == b && t == sg) ? 0.5 : 0.0) - U * nm[(b * 7 + ai) * 2];
+                        const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
+                        br = fma(vr, cv[t][b][0], fma(-vi, cv[t][b][1], br));
+                        bi = fma(vr, cv[t][b][1], fma(vi, cv[t][b][0], bi));
+                    }
+                }
+                B[ai][cc * 2] = sc * br;
+                B[ai][cc * 2 + 1] = sc * bi;
+            }
+        }
+    }
+}
+
+template <typename T, bool CPX, bool SPINOR, int CPL, int L>
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C) {
+    constexpr int NC = CPX ? 2 : 1;
+    constexpr int NV = CPL * NC;
+    constexpr int U = 2;
+    const int lane = threadIdx.x & (HUB_WAVE - 1);
+    const int wave = threadIdx.x / HUB_WAVE;
+    const int nw = blockDim.x / HUB_WAVE;
+    const int q = blockIdx.z;
+    const int col0 = (blockIdx.y * HUB_WAVE + lane) * CPL;
+    if (col0 >= a.ncol) return;
+    const int k = a.spinor ? q : q / a.nspin;
+
+    double B[L][NV];
+    coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
+
+    T* __restrict__ h_q = reinterpret_cast<T*>(a.hpsi) + static_cast<int64_t>(q) * a.qstride;
+    const int32_t* __restrict__ gi = a.gidx + C.e0;
+    const int32_t* __restrict__ im = a.img + C.e0;
+    const double* __restrict__ tb = a.tab + C.phi0;
+    const double* __restrict__ ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
+
+    for (int e = wave; e < C.ne; e += nw * U) {
+        T row[U][NV];
+        int64_t off[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = e + u * nw;
+            ok[u] = idx < C.ne;
+            const int ii = ok[u] ? idx : e;
+            off[u] = (static_cast<int64_t>(gi[ii]) * a.ld + col0) * NC;
+            load_vec<T, NV>(h_q + off[u], row[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const int ii = e + u * nw;
+            const double* __restrict__ w = tb + static_cast<int64_t>(ii) * L;
+            double add[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) add[v] = 0.0;
+#pragma unroll
+            for (int ai = 0; ai < L; ++ai) {
+                const double wa = w[ai];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) add[v] = fma(wa, B[ai][v], add[v]);
+            }
+            T out[NV];
+            if constexpr (CPX) {
+                const int ig = im[ii];
+                const double pr = ph[2 * ig], pi = -ph[2 * ig + 1];     // exp(-i k.T)
+#pragma unroll
+                for (int cc = 0; cc < CPL; ++cc) {
+                    const double ar = add[2 * cc], ai_ = add[2 * cc + 1];
+                    out[2 * cc] = static_cast<T>(static_cast<double>(row[u][2 * cc]) + (pr * ar - pi * ai_));
+                    out[2 * cc + 1] = static_cast<T>(static_cast<double>(row[u][2 * cc + 1]) + (pr * ai_ + pi * ar));
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[v] = static_cast<T>(static_cast<double>(row[u][v]) + add[v]);
+            }
+            store_vec<T, NV>(h_q + off[u], out);
+        }
+    }
+}
+
+template <typename T, bool CPX, bool SPINOR, int CPL>
+__global__ void __launch_bounds__(256) k_apply(const ApplyArgs a) {
+    const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
+    switch (C.L) {
+    case 1: apply_body<T, CPX, SPINOR, CPL, 1>(a, C); break;
+    case 3: apply_body<T, CPX, SPINOR, CPL, 3>(a, C); break;
+    case 5: apply_body<T, CPX, SPINOR, CPL, 5>(a, C); break;
+    case 7: apply_body<T, CPX, SPINOR, CPL, 7>(a, C); break;
+    default: break;
+    }
+}
+
+template <typename T, bool CPX, bool SPINOR, int CPL>
+hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
+    const int tiles = (a.ncol + HUB_WAVE * CPL - 1) / (HUB_WAVE * CPL);
+    dim3 grid(nchunks, tiles, nq);
+    hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL>), grid, dim3(HUB_WAVE * waves), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool CPX, bool SPINOR>
+hipError_t launch_c(const ApplyArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
+    switch (cpl) {
+    case 1: return launch_t<T, CPX, SPINOR, 1>(a, nchunks, nq, waves, st);
+    case 2: return launch_t<T, CPX, SPINOR, 2>(a, nchunks, nq, waves, st);
+    case 4: return launch_t<T, CPX, SPINOR, 4>(a, nchunks, nq, waves, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_apply(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                        hipStream_t st) {
+    if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    if (prec == HUB_F64) {
+        if (a.spinor) return launch_c<double, true, true>(a, nchunks, nq, cpl, waves, st);
+        return cplx ? launch_c<double, true, false>(a, nchunks, nq, cpl, waves, st)
+                    : launch_c<double, false, false>(a, nchunks, nq, cpl, waves, st);
+    }
+    if (a.spinor) return launch_c<float, true, true>(a, nchunks, nq, cpl, waves, st);
+    return cplx ? launch_c<float, true, false>(a, nchunks, nq, cpl, waves, st)
+                : launch_c<float, false, false>(a, nchunks, nq, cpl, waves, st);
+}

@@ -1,0 +1,432 @@
+// Small FP64 kernels of the Hubbard step: chunk reduction of the projections,
+// renormalized occupations N-bar, occupation matrices n and P-bar, ACBN0
+// U-bar/J-bar, Dudarev energy and Hubbard forces.  All reductions run in a
+// fixed order (no atomics), so results are bitwise reproducible.
+
+#include "ksmall.h"
+
+namespace {
+
+constexpr int NB = 256;   // threads of the per-site kernels
+constexpr int TILE = 128; // states staged per LDS tile in k_occ
+
+// ---------------------------------------------------------------- reduction
+// out[q][r][col] = dV * sum over the chunks of the row's site of
+// part[q][chunk.part0 * mult + (r - orb0 * mult)][col].
+__global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const int q = blockIdx.z;
+    if (col >= a.ncol) return;
+    const int site = a.orb_site[r / a.mult];
+    const int local = r - a.site_orb0[site] * a.mult;
+    const int NC = a.ncplx;
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = a.site_chunk_ptr[site]; t < a.site_chunk_ptr[site + 1]; ++t) {
+        const HubChunk& C = a.chunks[a.site_chunk_ids[t]];
+        const int64_t row = static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.mult + local;
+        const double* p = a.part + (row * a.ncol + col) * NC;
+        s0 += p[0];
+        if (NC == 2) s1 += p[1];
+    }
+    double* o = a.out + ((static_cast<int64_t>(q) * a.nrows + r) * a.ncol + col) * NC;
+    o[0] = a.dV * s0;
+    if (NC == 2) o[1] = a.dV * s1;
+}
+
+// ---------------------------------------------------------------- N-bar
+// nbar[q][T][s] = sum_{j in species T} sum_{columns of s} |c[q][j][col]|^2
+__global__ void __launch_bounds__(256) k_nbar(const NbarArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int T = blockIdx.y;
+    const int q = blockIdx.z;
+    if (s >= a.nstates) return;
+    const int NC = a.ncplx;
+    const int cps = a.spinor ? 2 : 1;
+    double acc = 0.0;
+    for (int t = a.species_orb_ptr[T]; t < a.species_orb_ptr[T + 1]; ++t) {
+        const int j = a.species_orb_ids[t];
+        for (int x = 0; x < cps; ++x) {
+            const double* p = a.c + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + s * cps + x) * NC;
+            acc = fma(p[0], p[0], acc);
+            if (NC == 2) acc = fma(p[1], p[1], acc);
+        }
+    }
+    a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s] = acc;
+}
+
+// ---------------------------------------------------------------- occupations
+// One work-group per site.  For every block (spin channel, or spinor block
+// sigma sigma'), n_ab = sum_k w_k sum_s f_s conj(c_a) c_b (Eq. occ_matrices)
+// and pbar_ab = the same with the extra weight N-bar_s of the site's species
+// (Eq. notation_Pbar).  States are staged through LDS in tiles of NB; the
+// (a, b) pairs are spread over the threads with several state slices each,
+// and the slices are summed in a fixed order at the end.
+__global__ void __launch_bounds__(NB) k_occ(const OccArgs a) {
+    const int site = blockIdx.x;
+    const int L = a.site_L[site];
+    const int orb0 = a.site_orb0[site];
+    const int T = a.site_species[site];
+    const int NC = a.ncplx;
+    const int nsig = a.spinor ? 2 : 1;               // spin components staged per state
+    const int ncp = a.spinor ? 2 * L : L;            // rows of the combined matrix
+    const int npairs = ncp * ncp;
+    const int nslice = NB / npairs;
+    const int tid = threadIdx.x;
+    const int pair = tid % npairs;
+    const int slice = tid / npairs;
+    const bool worker = slice < nslice;
+    const int ra = pair / ncp, rb = pair % ncp;      // combined index: sigma * L + m
+
+    __shared__ double cs[2][7][TILE][2];
+    __shared__ double wt[TILE], wtn[TILE];
+    __shared__ double red[NB][4];
+
+    const int nchan = a.spinor ? 1 : a.nspin;
+    for (int ch = 0; ch < nchan; ++ch) {
+        double nr = 0.0, ni = 0.0, pr = 0.0, pi = 0.0;
+        for (int k = 0; k < a.nk; ++k) {
+            const int q = a.spinor ? k : k * a.nspin + ch;
+            const double wk = a.kweights[k];
+            for (int s0 = 0; s0 < a.nstates; s0 += TILE) {
+                const int s = s0 + tid;
+                if (tid >= TILE) {
+                } else if (s < a.nstates) {
+                    const double f = a.f[static_cast<int64_t>(q) * a.nstates + s];
+                    const double nb = (a.nbar != nullptr)
+                                          ? a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s]
+                                          : 0.0;
+                    wt[tid] = wk * f;
+                    wtn[tid] = wk * f * nb;
+                    for (int x = 0; x < nsig; ++x)
+                        for (int m = 0; m < L; ++m) {
+                            const double* p =
+                                a.c + ((static_cast<int64_t>(q) * a.J + orb0 + m) * a.ncol + s * nsig + x) * NC;
+                            cs[x][m][tid][0] = p[0];
+                            cs[x][m][tid][1] = (NC == 2) ? p[1] : 0.0;
+                        }
+                } else {
+                    wt[tid] = 0.0;
+                    wtn[tid] = 0.0;
+                    for (int x = 0; x < nsig; ++x)
+                        for (int m = 0; m < L; ++m) cs[x][m][tid][0] = cs[x][m][tid][1] = 0.0;
+                }
+                __syncthreads();
+                if (worker) {
+                    const int xa = ra / L, ma = ra % L, xb = rb / L, mb = rb % L;
+                    const int nt = min(TILE, a.nstates - s0);
+                    for (int t = slice; t < nt; t += nslice) {
+                        // conj(c_a) c_b
+                        const double ar = cs[xa][ma][t][0], ai = cs[xa][ma][t][1];
+                        const double br = cs[xb][mb][t][0], bi = cs[xb][mb][t][1];
+                        const double re = ar * br + ai * bi;
+                        const double im = ar * bi - ai * br;
+                        nr = fma(wt[t], re, nr);
+                        ni = fma(wt[t], im, ni);
+                        pr = fma(wtn[t], re, pr);
+                        pi = fma(wtn[t], im, pi);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        red[tid][0] = nr; red[tid][1] = ni; red[tid][2] = pr; red[tid][3] = pi;
+        __syncthreads();
+        // write all blocks of this channel (zeros outside the L x L corner)
+        const int nblk_here = a.spinor ? 4 : 1;
+        for (int o = tid; o < nblk_here * 49; o += NB) {
+            const int blk = o / 49, e = o % 49, i = e / 7, j = e % 7;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            if (i < L && j < L) {
+                const int x = a.spinor ? blk / 2 : 0, y = a.spinor ? blk % 2 : 0;
+                const int p = (x * L + i) * ncp + (y * L + j);
+                for (int z = 0; z < nslice; ++z)
+                    for (int r = 0; r < 4; ++r) v[r] += red[z * npairs + p][r];
+            }
+            const int oblk = a.spinor ? blk : ch;
+            const int64_t base = ((static_cast<int64_t>(site) * a.nblk + oblk) * 49 + e) * 2;
+            a.n[base] = v[0];
+            a.n[base + 1] = v[1];
+            if (a.pbar != nullptr) {
+                a.pbar[base] = v[2];
+                a.pbar[base + 1] = v[3];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- ACBN0
+// U-bar and J-bar of one site (Eqs. ACBN0_U, ACBN0_J; App. B), with the
+// numerators read as P_mm' P_m''m''' (mm'|m''m''') and P_mm' P_m''m'''
+// (mm'''|m''m'), denominators from the bare diagonal occupations.
+__global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
+    const int site = blockIdx.x;
+    const int L = a.site_L[site];
+    const int tid = threadIdx.x;
+    const double fixed = a.ueff_fixed[site];
+    if (!isnan(fixed)) {
+        if (tid == 0) {
+            a.U[site] = fixed;
+            a.J[site] = 0.0;
+            a.Ueff[site] = fixed;
+            if (a.status) a.status[site] = 0;
+        }
+        return;
+    }
+    __shared__ double P[4][7][7][2];
+    __shared__ double Nd[4][7][2];
+    __shared__ double Ts[2401];
+    __shared__ double redU[NB], redJ[NB];
+    const int nb = a.nblk;
+    for (int o = tid; o < nb * 49; o += NB) {
+        const int b = o / 49, e = o % 49;
+        const int64_t base = ((static_cast<int64_t>(site) * nb + b) * 49 + e) * 2;
+        P[b][e / 7][e % 7][0] = a.pbar[base];
+        P[b][e / 7][e % 7][1] = a.pbar[base + 1];
+        if (e / 7 == e % 7) {
+            Nd[b][e / 7][0] = a.n[base];
+            Nd[b][e / 7][1] = a.n[base + 1];
+        }
+    }
+    const int L2 = L * L, L4 = L2 * L2;
+    const double* Tg = a.tensor + static_cast<int64_t>(site) * 2401;
+    for (int o = tid; o < L4; o += NB) Ts[o] = Tg[o];
+    __syncthreads();
+
+    // channel layout: unpolarized -> both channels are block 0
+    const int c0 = 0;
+    const int c1 = (nb == 2) ? 1 : (nb == 4 ? 3 : 0);
+    double su = 0.0, sj = 0.0;
+    for (int o = tid; o < L4; o += NB) {
+        const int ab = o / L2, cd = o % L2;
+        const int A = ab / L, B = ab % L, Cc = cd / L, D = cd % L;
+        const double t_abcd = Ts[o];
+        const double t_adcb = Ts[((A * L + D) * L + Cc) * L + B];
+        // numerator U: sum_{alpha beta} P^a_ab P^b_cd (ab|cd) = Re(Ps_ab Ps_cd) (ab|cd)
+        const double sr_ab = P[c0][A][B][0] + P[c1][A][B][0], si_ab = P[c0][A][B][1] + P[c1][A][B][1];
+        const double sr_cd = P[c0][Cc][D][0] + P[c1][Cc][D][0], si_cd = P[c0][Cc][D][1] + P[c1][Cc][D][1];
+        su = fma(sr_ab * sr_cd - si_ab * si_cd, t_abcd, su);
+        if (nb == 4) {
+            // sum_{s s'} Re(P^{ss'}_ab P^{s's}_cd) (ad|cb)
+            double v = 0.0;
+            for (int x = 0; x < 2; ++x)
+                for (int y = 0; y < 2; ++y) {
+                    const int b1 = 2 * x + y, b2 = 2 * y + x;
+                    v += P[b1][A][B][0] * P[b2][Cc][D][0] - P[b1][A][B][1] * P[b2][Cc][D][1];
+                }
+            sj = fma(v, t_adcb, sj);
+        } else {
+            double v = P[c0][A][B][0] * P[c0][Cc][D][0] - P[c0][A][B][1] * P[c0][Cc][D][1];
+            v += P[c1][A][B][0] * P[c1][Cc][D][0] - P[c1][A][B][1] * P[c1][Cc][D][1];
+            sj = fma(v, t_adcb, sj);
+        }
+    }
+    redU[tid] = su;
+    redJ[tid] = sj;
+    __syncthreads();
+    for (int w = NB / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            redU[tid] += redU[tid + w];
+            redJ[tid] += redJ[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    double dU = 0.0, dJ = 0.0;
+    if (nb != 4) {
+        // collinear: N^alpha_m = n^alpha_mm (real part)
+        double N[2][7];
+        for (int m = 0; m < L; ++m) {
+            N[0][m] = Nd[c0][m][0];
+            N[1][m] = Nd[c1][m][0];
+        }
+        for (int al = 0; al < 2; ++al)
+            for (int m = 0; m < L; ++m)
+                for (int mp = 0; mp < L; ++mp)
+                    if (m != mp) dJ += N[al][m] * N[al][mp];
+        dU = dJ;
+        for (int al = 0; al < 2; ++al)
+            for (int m = 0; m < L; ++m)
+                for (int mp = 0; mp < L; ++mp) dU += N[al][m] * N[1 - al][mp];
+    } else {
+        // spinor (App. B): complex diagonal blocks N^{xy}_m = n^{xy}_mm
+        auto re_mul = [&](int b1, int m1, int b2, int m2) {
+            return Nd[b1][m1][0] * Nd[b2][m2][0] - Nd[b1][m1][1] * Nd[b2][m2][1];
+        };
+        for (int s = 0; s < 2; ++s) {
+            const int ss = 3 * s, oo = 3 * (1 - s), so = 2 * s + (1 - s), os = 2 * (1 - s) + s;
+            for (int m = 0; m < L; ++m)
+                for (int mp = 0; mp < L; ++mp) {
+                    dU += re_mul(ss, m, oo, mp);
+                    if (m != mp) {
+                        dU += re_mul(ss, m, ss, mp);
+                        dJ += re_mul(ss, m, ss, mp) + re_mul(so, m, os, mp);
+                    }
+                }
+            for (int m = 0; m < L; ++m) dU -= re_mul(so, m, os, m);
+        }
+    }
+    int st = 0;
+    double U = 0.0, J = 0.0;
+    if (fabs(dU) < 1e-12) st = HUB_WDEGENERATE; else U = redU[0] / dU;
+    if (fabs(dJ) < 1e-12) st = HUB_WDEGENERATE; else J = redJ[0] / dJ;
+    a.U[site] = U;
+    a.J[site] = J;
+    a.Ueff[site] = U - J;
+    if (a.status) a.status[site] = st;
+}
+
+// ---------------------------------------------------------------- energy
+// E_U = Ueff/2 sum_channels Tr[n - n n] (Eq. E_Dudarev); spinor: the 2L x 2L
+// matrix of App. A.  Unpolarized contexts count their channel twice.
+__global__ void k_energy(const EnergyArgs a) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= a.nsites) return;
+    const int L = a.site_L[site];
+    const double* nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
+    double val = 0.0;
+    if (a.nblk == 4) {
+        const int M = 2 * L;
+        auto el = [&](int i, int j, int r) {
+            const int x = i / L, y = j / L;
+            return nb[((2 * x + y) * 49 + (i % L) * 7 + (j % L)) * 2 + r];
+        };
+        for (int i = 0; i < M; ++i) {
+            val += el(i, i, 0);
+            for (int j = 0; j < M; ++j) val -= el(i, j, 0) * el(j, i, 0) - el(i, j, 1) * el(j, i, 1);
+        }
+    } else {
+        for (int b = 0; b < a.nblk; ++b) {
+            const double* m = nb + b * 98;
+            double v = 0.0;
+            for (int i = 0; i < L; ++i) {
+                v += m[(i * 7 + i) * 2];
+                for (int j = 0; j < L; ++j)
+                    v -= m[(i * 7 + j) * 2] * m[(j * 7 + i) * 2] - m[(i * 7 + j) * 2 + 1] * m[(j * 7 + i) * 2 + 1];
+            }
+            val += (a.nblk == 1) ? 2.0 * v : v;
+        }
+    }
+    a.EU[site] = 0.5 * a.Ueff[site] * val;
+}
+
+// ---------------------------------------------------------------- forces
+// F_i = g_s 2 Re sum_q w_k sum_col f_s sum_a conj(d_{a,i}(col)) B_a(col),
+// B = V c as in the apply kernel (Sec. IV with U_eff fixed).
+__global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
+    const int site = blockIdx.x;
+    const int L = a.site_L[site];
+    const int orb0 = a.site_orb0[site];
+    const int NC = a.ncplx;
+    const double U = a.ueff[site];
+    const int tid = threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t total = static_cast<int64_t>(a.nq) * a.ncol;
+    for (int64_t o = tid; o < total; o += NB) {
+        const int q = static_cast<int>(o / a.ncol);
+        const int col = static_cast<int>(o % a.ncol);
+        const int k = a.spinor ? q : q / a.nspin;
+        const int ch = a.spinor ? 0 : q % a.nspin;
+        const int s = a.spinor ? col / 2 : col;
+        const double wf = a.kweights[k] * a.f[static_cast<int64_t>(q) * a.nstates + s];
+        if (wf == 0.0) continue;
+        const double* cq = a.c + (static_cast<int64_t>(q) * a.J + orb0) * a.ncol * NC;
+        const double* nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
+        for (int ai = 0; ai < L; ++ai) {
+            double br = 0.0, bi = 0.0;
+            if (!a.spinor) {
+                const double* nm = nb + ch * 98;
+                for (int b = 0; b < L; ++b) {
+                    const double vr = U * ((ai == b ? 0.5 : 0.0) - nm[(b * 7 + ai) * 2]);
+                    const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
+                    const double cr = cq[(static_cast<int64_t>(b) * a.ncol + col) * NC];
+                    const double ci = (NC == 2) ? cq[(static_cast<int64_t>(b) * a.ncol + col) * NC + 1] : 0.0;
+                    br += vr * cr - vi * ci;
+                    bi += vr * ci + vi * cr;
+                }
+            } else {
+                const int sg = col & 1, base = col - sg;
+                for (int t = 0; t < 2; ++t) {
+                    const double* nm = nb + (2 * t + sg) * 98;
+                    for (int b = 0; b < L; ++b) {
+                        const double vr = U * ((ai == b && t == sg) ? 0.5 : 0.0) - U * nm[(b * 7 + ai) * 2];
+                        const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
+                        const double cr = cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2];
+                        const double ci = cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2 + 1];
+                        br += vr * cr - vi * ci;
+                        bi += vr * ci + vi * cr;
+                    }
+                }
+            }
+            for (int i = 0; i < 3; ++i) {
+                const double* dp = a.d + ((static_cast<int64_t>(q) * a.J * 3 + (orb0 + ai) * 3 + i) * a.ncol + col) * NC;
+                const double dr = dp[0], di = (NC == 2) ? dp[1] : 0.0;
+                acc[i] += wf * (dr * br + di * bi);           // Re(conj(d) B)
+            }
+        }
+    }
+    __shared__ double red[NB][3];
+    for (int i = 0; i < 3; ++i) red[tid][i] = acc[i];
+    __syncthreads();
+    for (int w = NB / 2; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int i = 0; i < 3; ++i) red[tid][i] += red[tid + w][i];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double gs = (a.nblk == 1) ? 2.0 : 1.0;
+        for (int i = 0; i < 3; ++i) a.F[site * 3 + i] = gs * 2.0 * red[0][i];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st) {
+    if (a.nrows <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    dim3 grid((a.ncol + 255) / 256, a.nrows, nq);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbar(const NbarArgs& a, int nq, hipStream_t st) {
+    dim3 grid((a.nstates + 255) / 256, a.nspecies, nq);
+    hipLaunchKernelGGL(k_nbar, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st) {
+    OccArgs b = a;
+    b.site_L += site0;
+    b.site_orb0 += site0;
+    b.site_species += site0;
+    b.n += static_cast<int64_t>(site0) * a.nblk * 98;
+    if (b.pbar) b.pbar += static_cast<int64_t>(site0) * a.nblk * 98;
+    hipLaunchKernelGGL(k_occ, dim3(nsites), dim3(NB), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t st) {
+    Acbn0Args b = a;
+    b.site_L += site0;
+    b.ueff_fixed += site0;
+    b.n += static_cast<int64_t>(site0) * a.nblk * 98;
+    b.pbar += static_cast<int64_t>(site0) * a.nblk * 98;
+    b.tensor += static_cast<int64_t>(site0) * 2401;
+    b.U += site0;
+    b.J += site0;
+    b.Ueff += site0;
+    if (b.status) b.status += site0;
+    hipLaunchKernelGGL(k_acbn0, dim3(nsites), dim3(NB), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const EnergyArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy, dim3((a.nsites + 63) / 64), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(const ForceArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_forces, dim3(a.nsites), dim3(NB), 0, st, a);
+    return hipGetLastError();
+}

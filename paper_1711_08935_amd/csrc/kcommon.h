@@ -1,0 +1,109 @@
+// Device-side helpers and launch argument blocks of the Hubbard kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hub_internal.h"
+
+#define HUB_WAVE 64
+
+// Launch arguments of the projection kernel (gather + contraction).
+struct ProjArgs {
+    const void* psi;          // states, T[nq][G][ld] (x2 for complex)
+    int64_t ld;               // columns per grid point
+    int64_t qstride;          // scalars between state sets (G * ld * ncplx)
+    int ncol;                 // columns used (nstates or 2 nstates)
+    int nspin;                // collinear channels (state set q -> k = q / nspin)
+    int spinor;               // 1: state set q is k-point q
+    const HubChunk* chunks;
+    const int32_t* chunk_list;
+    const int32_t* gidx;
+    const int32_t* img;
+    const double* tab;        // orbital table (or gradient table)
+    int tabmult;              // 1: phi, 3: grad phi
+    const double* phase;      // [nk][nimg] (re, im) of exp(+i k.T)
+    int nimg;
+    double* part;             // [nq][prows][ncol] (x2 complex)
+    int64_t prows;            // rows per state set = part_rows * tabmult
+};
+
+// Launch arguments of the apply kernel (coefficients + scatter).
+struct ApplyArgs {
+    void* hpsi;
+    int64_t ld;
+    int64_t qstride;
+    int ncol;
+    int nstates;
+    int nspin;
+    int spinor;
+    int nblk;                 // blocks per site in n
+    const HubChunk* chunks;
+    const int32_t* chunk_list;
+    const int32_t* gidx;
+    const int32_t* img;
+    const double* tab;
+    const double* phase;
+    int nimg;
+    const double* c;          // [nq][J][ncol] (x2 complex)
+    int J;
+    const double* n;          // [site][nblk][7][7][2]
+    const double* ueff;       // [site]
+    const double* colscale;   // [nq][nstates] or null
+    double alpha;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[N]) {
+    if constexpr (sizeof(T) * N >= 16) {
+        constexpr int per = 16 / sizeof(T);
+        using V16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+        for (int i = 0; i < N / per; ++i) {
+            const V16 t = *reinterpret_cast<const V16*>(p + i * per);
+            if constexpr (sizeof(T) == 4) {
+                v[i * per + 0] = t.x; v[i * per + 1] = t.y; v[i * per + 2] = t.z; v[i * per + 3] = t.w;
+            } else {
+                v[i * per + 0] = t.x; v[i * per + 1] = t.y;
+            }
+        }
+    } else if constexpr (sizeof(T) == 4 && N == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        v[0] = t.x; v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = p[i];
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&v)[N]) {
+    if constexpr (sizeof(T) * N >= 16) {
+        constexpr int per = 16 / sizeof(T);
+        using V16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+        for (int i = 0; i < N / per; ++i) {
+            V16 t;
+            if constexpr (sizeof(T) == 4) {
+                t.x = v[i * per + 0]; t.y = v[i * per + 1]; t.z = v[i * per + 2]; t.w = v[i * per + 3];
+            } else {
+                t.x = v[i * per + 0]; t.y = v[i * per + 1];
+            }
+            *reinterpret_cast<V16*>(p + i * per) = t;
+        }
+    } else if constexpr (sizeof(T) == 4 && N == 2) {
+        float2 t;
+        t.x = v[0]; t.y = v[1];
+        *reinterpret_cast<float2*>(p) = t;
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) p[i] = v[i];
+    }
+}
+
+// Launchers (defined in the .hip files).
+hipError_t launch_project(const ProjArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                          hipStream_t st);
+hipError_t launch_apply(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                        hipStream_t st);

@@ -1,0 +1,66 @@
+// Launch argument blocks of the small FP64 kernels (reduction, N-bar,
+// occupations, ACBN0, energy, forces, Coulomb).
+#pragma once
+
+#include "kcommon.h"
+
+struct ReduceArgs {
+    const double* part; int64_t prows;    // workspace rows per state set
+    double* out; int nrows;               // output rows per state set (J * mult)
+    int ncol; int ncplx; int mult;
+    const HubChunk* chunks;
+    const int32_t* site_chunk_ptr; const int32_t* site_chunk_ids;
+    const int32_t* orb_site; const int32_t* site_orb0;
+    double dV;
+};
+
+struct NbarArgs {
+    const double* c; double* nbar;
+    int J; int ncol; int nstates; int ncplx; int spinor; int nspecies;
+    const int32_t* species_orb_ptr; const int32_t* species_orb_ids;
+};
+
+struct OccArgs {
+    const double* c; const double* f; const double* nbar;
+    double* n; double* pbar;
+    const double* kweights;
+    const int32_t* site_L; const int32_t* site_orb0; const int32_t* site_species;
+    int J; int ncol; int nstates; int ncplx; int spinor; int nspin; int nk; int nblk; int nspecies;
+};
+
+struct Acbn0Args {
+    const double* n; const double* pbar; const double* tensor;   // tensor: [site][2401]
+    const int32_t* site_L; const double* ueff_fixed;
+    double* U; double* J; double* Ueff; int32_t* status;
+    int nblk;
+};
+
+struct EnergyArgs {
+    const double* n; const double* Ueff; double* EU;
+    const int32_t* site_L; int nsites; int nblk;
+};
+
+struct ForceArgs {
+    const double* c; const double* d; const double* f; const double* n; const double* ueff;
+    const double* kweights; double* F;
+    const int32_t* site_L; const int32_t* site_orb0;
+    int nsites; int J; int ncol; int nstates; int ncplx; int spinor; int nspin; int nq; int nblk;
+};
+
+struct CoulombArgs {
+    const int32_t* ijk;        // unfolded integer coordinates of the site's points [P][3]
+    const double* phi;         // [P][L]
+    int P; int L; int npair;
+    double* rho;               // scratch [P][npair]
+    double* W;                 // scratch [P][npair]
+    double* tensor;            // output [L^4]
+    double h[3]; double g0; double dV;
+};
+
+hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st);
+hipError_t launch_nbar(const NbarArgs& a, int nq, hipStream_t st);
+hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st);
+hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t st);
+hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
+hipError_t launch_forces(const ForceArgs& a, hipStream_t st);
+hipError_t launch_coulomb(const CoulombArgs& a, hipStream_t st);

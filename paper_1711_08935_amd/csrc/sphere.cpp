@@ -1,0 +1,318 @@
+// Host-side setup of the Hubbard library: sphere maps, orbital tables and
+// the layered work list.  Built with -ffp-contract=off: sphere membership is
+// decided by the canonical FP64 expression d_i = j_i * h_i - R_i,
+// |d|^2 = (dx*dx + dy*dy) + dz*dz <= rc*rc, which must not be contracted.
+//
+// Paper: localized orbitals on spherical sub-grids around the atoms, points
+// outside the periodic box mapped back onto the grid with a phase (Sec. II
+// and Fig. 1); sphere truncation radius (Sec. II, radius discussion).
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <tuple>
+
+#include "hub_internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Real solid harmonics S_lm(x, y, z) = r^l Y_lm, m = -l..l, standard real
+// combinations without the Condon-Shortley sign (p: y, z, x), and their
+// gradients, written out as polynomials.
+void solid_harmonics(int l, double x, double y, double z, double* S, double* dS) {
+    switch (l) {
+    case 0: {
+        S[0] = 0.5 * std::sqrt(1.0 / kPi);
+        dS[0] = dS[1] = dS[2] = 0.0;
+        break;
+    }
+    case 1: {
+        const double c = std::sqrt(3.0 / (4.0 * kPi));
+        S[0] = c * y; dS[0] = 0; dS[1] = c; dS[2] = 0;
+        S[1] = c * z; dS[3] = 0; dS[4] = 0; dS[5] = c;
+        S[2] = c * x; dS[6] = c; dS[7] = 0; dS[8] = 0;
+        break;
+    }
+    case 2: {
+        const double a = std::sqrt(15.0 / (4.0 * kPi));
+        const double b = std::sqrt(5.0 / (16.0 * kPi));
+        const double c = std::sqrt(15.0 / (16.0 * kPi));
+        S[0] = a * x * y;                        dS[0] = a * y;      dS[1] = a * x;       dS[2] = 0;
+        S[1] = a * y * z;                        dS[3] = 0;          dS[4] = a * z;       dS[5] = a * y;
+        S[2] = b * (2 * z * z - x * x - y * y);  dS[6] = -2 * b * x; dS[7] = -2 * b * y;  dS[8] = 4 * b * z;
+        S[3] = a * x * z;                        dS[9] = a * z;      dS[10] = 0;          dS[11] = a * x;
+        S[4] = c * (x * x - y * y);              dS[12] = 2 * c * x; dS[13] = -2 * c * y; dS[14] = 0;
+        break;
+    }
+    case 3: {
+        const double A = std::sqrt(35.0 / (32.0 * kPi));
+        const double B = std::sqrt(105.0 / (4.0 * kPi));
+        const double C = std::sqrt(21.0 / (32.0 * kPi));
+        const double D = std::sqrt(7.0 / (16.0 * kPi));
+        const double E = std::sqrt(105.0 / (16.0 * kPi));
+        const double xx = x * x, yy = y * y, zz = z * z;
+        S[0] = A * y * (3 * xx - yy);
+        dS[0] = 6 * A * x * y; dS[1] = A * (3 * xx - 3 * yy); dS[2] = 0;
+        S[1] = B * x * y * z;
+        dS[3] = B * y * z; dS[4] = B * x * z; dS[5] = B * x * y;
+        S[2] = C * y * (4 * zz - xx - yy);
+        dS[6] = -2 * C * x * y; dS[7] = C * (4 * zz - xx - 3 * yy); dS[8] = 8 * C * y * z;
+        S[3] = D * z * (2 * zz - 3 * xx - 3 * yy);
+        dS[9] = -6 * D * x * z; dS[10] = -6 * D * y * z; dS[11] = D * (6 * zz - 3 * xx - 3 * yy);
+        S[4] = C * x * (4 * zz - xx - yy);
+        dS[12] = C * (4 * zz - 3 * xx - yy); dS[13] = -2 * C * x * y; dS[14] = 8 * C * x * z;
+        S[5] = E * z * (xx - yy);
+        dS[15] = 2 * E * x * z; dS[16] = -2 * E * y * z; dS[17] = E * (xx - yy);
+        S[6] = A * x * (xx - 3 * yy);
+        dS[18] = A * (3 * xx - 3 * yy); dS[19] = -6 * A * x * y; dS[20] = 0;
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+inline int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+struct Pt {
+    int32_t g;
+    int32_t img[3];
+    int32_t ijk[3];
+    double d[3];
+};
+
+}  // namespace
+
+double hub_g0_cell_average(const double h[3]) {
+    // 8/(hx hy hz) * F(a, b, c), F = integral of 1/r over [0,a]x[0,b]x[0,c]
+    // with a = hx/2 etc.: the potential of a uniform cuboid at its corner,
+    // F = ab asinh(c/sqrt(a^2+b^2)) + bc asinh(a/sqrt(b^2+c^2))
+    //   + ca asinh(b/sqrt(c^2+a^2)) - a^2/2 atan(bc/(a r))
+    //   - b^2/2 atan(ca/(b r)) - c^2/2 atan(ab/(c r)),  r = sqrt(a^2+b^2+c^2).
+    const double a = 0.5 * h[0], b = 0.5 * h[1], c = 0.5 * h[2];
+    const double r = std::sqrt(a * a + b * b + c * c);
+    const double F = a * b * std::asinh(c / std::hypot(a, b)) + b * c * std::asinh(a / std::hypot(b, c)) +
+                     c * a * std::asinh(b / std::hypot(c, a)) - 0.5 * a * a * std::atan(b * c / (a * r)) -
+                     0.5 * b * b * std::atan(c * a / (b * r)) - 0.5 * c * c * std::atan(a * b / (c * r));
+    return 8.0 * F / (h[0] * h[1] * h[2]);
+}
+
+int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<SiteDef>& sites,
+                   int chunk_entries, HostTables& T) {
+    T = HostTables();
+    const int ns = static_cast<int>(sites.size());
+    if (ns == 0) return HUB_EINVAL;
+    double h[3];
+    for (int i = 0; i < 3; ++i) h[i] = cell[i] / static_cast<double>(ngrid[i]);
+    const double dV = h[0] * h[1] * h[2];
+    const int64_t G = static_cast<int64_t>(ngrid[0]) * ngrid[1] * ngrid[2];
+    if (G > INT32_MAX) return HUB_EINVAL;
+
+    T.nsites = ns;
+    T.site_L.resize(ns);
+    T.site_orb0.resize(ns);
+    T.site_species.resize(ns);
+    T.spheres.resize(ns);
+    int J = 0, nspec = 0;
+    for (int s = 0; s < ns; ++s) {
+        T.site_L[s] = 2 * sites[s].l + 1;
+        T.site_orb0[s] = J;
+        T.site_species[s] = sites[s].species;
+        J += T.site_L[s];
+        nspec = std::max(nspec, sites[s].species + 1);
+    }
+    T.J = J;
+    T.nspecies = nspec;
+
+    std::map<std::tuple<int, int, int>, int> image_id;
+    std::vector<std::vector<Pt>> pts(ns);
+
+    // ---- spheres: enumerate unfolded integer coordinates around R
+    for (int s = 0; s < ns; ++s) {
+        const SiteDef& S = sites[s];
+        const double rc2 = S.rc * S.rc;
+        int64_t lo[3], hi[3];
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = static_cast<int64_t>(std::floor((S.R[i] - S.rc) / h[i])) - 1;
+            hi[i] = static_cast<int64_t>(std::ceil((S.R[i] + S.rc) / h[i])) + 1;
+        }
+        std::vector<Pt>& P = pts[s];
+        for (int64_t jx = lo[0]; jx <= hi[0]; ++jx) {
+            const double dx = static_cast<double>(jx) * h[0] - S.R[0];
+            for (int64_t jy = lo[1]; jy <= hi[1]; ++jy) {
+                const double dy = static_cast<double>(jy) * h[1] - S.R[1];
+                const double dxy = dx * dx + dy * dy;
+                for (int64_t jz = lo[2]; jz <= hi[2]; ++jz) {
+                    const double dz = static_cast<double>(jz) * h[2] - S.R[2];
+                    const double d2 = dxy + dz * dz;
+                    if (!(d2 <= rc2)) continue;
+                    Pt p;
+                    const int64_t j[3] = {jx, jy, jz};
+                    int64_t f[3];
+                    for (int i = 0; i < 3; ++i) {
+                        const int64_t n = floor_div(j[i], ngrid[i]);
+                        f[i] = j[i] - n * ngrid[i];
+                        p.img[i] = static_cast<int32_t>(n);
+                        p.ijk[i] = static_cast<int32_t>(j[i]);
+                    }
+                    p.g = static_cast<int32_t>((f[0] * ngrid[1] + f[1]) * ngrid[2] + f[2]);
+                    p.d[0] = dx; p.d[1] = dy; p.d[2] = dz;
+                    P.push_back(p);
+                }
+            }
+        }
+        if (P.empty()) return HUB_EINVAL;   // a sphere with no grid point has no orbital
+        std::sort(P.begin(), P.end(), [](const Pt& a, const Pt& b) {
+            return std::tie(a.g, a.img[0], a.img[1], a.img[2]) < std::tie(b.g, b.img[0], b.img[1], b.img[2]);
+        });
+        // orbital values and grid normalization dV sum phi^2 = 1 per m
+        const int L = T.site_L[s];
+        SiteSphere& sp = T.spheres[s];
+        const size_t np = P.size();
+        sp.g.resize(np);
+        sp.img3.resize(3 * np);
+        sp.ijk.resize(3 * np);
+        sp.phi.resize(np * L);
+        sp.grad.resize(np * L * 3);
+        std::vector<double> norm2(L, 0.0);
+        double Sv[7], dSv[21];
+        for (size_t p = 0; p < np; ++p) {
+            const Pt& q = P[p];
+            sp.g[p] = q.g;
+            for (int i = 0; i < 3; ++i) {
+                sp.img3[3 * p + i] = q.img[i];
+                sp.ijk[3 * p + i] = q.ijk[i];
+            }
+            const double r = std::sqrt((q.d[0] * q.d[0] + q.d[1] * q.d[1]) + q.d[2] * q.d[2]);
+            const double rad = std::exp(-S.zeta * r);
+            solid_harmonics(S.l, q.d[0], q.d[1], q.d[2], Sv, dSv);
+            for (int m = 0; m < L; ++m) {
+                const double chi = rad * Sv[m];
+                sp.phi[p * L + m] = chi;
+                norm2[m] += chi * chi;
+                for (int i = 0; i < 3; ++i) {
+                    const double radial = (r > 0.0) ? S.zeta * (q.d[i] / r) * Sv[m] : 0.0;
+                    sp.grad[(p * L + m) * 3 + i] = rad * (dSv[3 * m + i] - radial);
+                }
+            }
+        }
+        for (int m = 0; m < L; ++m) {
+            const double nm = 1.0 / std::sqrt(dV * norm2[m]);
+            for (size_t p = 0; p < np; ++p) {
+                sp.phi[p * L + m] *= nm;
+                for (int i = 0; i < 3; ++i) sp.grad[(p * L + m) * 3 + i] *= nm;
+            }
+        }
+        for (size_t p = 0; p < np; ++p) {
+            auto key = std::make_tuple(P[p].img[0], P[p].img[1], P[p].img[2]);
+            if (!image_id.count(key)) {
+                const int id = static_cast<int>(image_id.size());
+                image_id[key] = id;
+            }
+        }
+    }
+    T.images.resize(3 * image_id.size());
+    for (const auto& kv : image_id) {
+        T.images[3 * kv.second + 0] = std::get<0>(kv.first);
+        T.images[3 * kv.second + 1] = std::get<1>(kv.first);
+        T.images[3 * kv.second + 2] = std::get<2>(kv.first);
+    }
+
+    // ---- layers: the k-th entry (in site order) that lands on grid point g
+    // goes to layer k, so a layer never holds the same g twice.
+    std::vector<uint16_t> cover(static_cast<size_t>(G), 0);
+    std::vector<std::vector<int>> layer_of(ns);
+    int nlayers = 0;
+    for (int s = 0; s < ns; ++s) {
+        const size_t np = pts[s].size();
+        layer_of[s].resize(np);
+        for (size_t p = 0; p < np; ++p) {
+            const int32_t g = pts[s][p].g;
+            if (cover[g] == 65535) return HUB_EINVAL;
+            const int lay = cover[g]++;
+            layer_of[s][p] = lay;
+            nlayers = std::max(nlayers, lay + 1);
+        }
+    }
+    T.nlayers = nlayers;
+
+    // ---- entries ordered by (layer, site, g); chunks of <= chunk_entries
+    const int chunk = std::max(1, chunk_entries);
+    T.layer_chunk_ptr.assign(nlayers + 1, 0);
+    T.layer_site_ptr.assign(static_cast<size_t>(nlayers) * ns + 1, 0);
+    int64_t e = 0, phi0 = 0;
+    int part_rows = 0;
+    for (int lay = 0; lay < nlayers; ++lay) {
+        T.layer_chunk_ptr[lay] = static_cast<int32_t>(T.chunks.size());
+        for (int s = 0; s < ns; ++s) {
+            T.layer_site_ptr[static_cast<size_t>(lay) * ns + s] = static_cast<int32_t>(T.chunks.size());
+            const int L = T.site_L[s];
+            const SiteSphere& sp = T.spheres[s];
+            std::vector<size_t> mine;
+            for (size_t p = 0; p < pts[s].size(); ++p)
+                if (layer_of[s][p] == lay) mine.push_back(p);
+            for (size_t b = 0; b < mine.size(); b += chunk) {
+                const size_t nb = std::min(mine.size() - b, static_cast<size_t>(chunk));
+                HubChunk C;
+                C.site = s;
+                C.layer = lay;
+                C.e0 = static_cast<int32_t>(e);
+                C.ne = static_cast<int32_t>(nb);
+                C.L = L;
+                C.orb0 = T.site_orb0[s];
+                C.part0 = part_rows;
+                C.species = sites[s].species;
+                C.phi0 = phi0;
+                for (size_t t = 0; t < nb; ++t) {
+                    const size_t p = mine[b + t];
+                    T.gidx.push_back(sp.g[p]);
+                    const Pt& q = pts[s][p];
+                    T.img.push_back(image_id[std::make_tuple(q.img[0], q.img[1], q.img[2])]);
+                    for (int m = 0; m < L; ++m) T.phi.push_back(sp.phi[p * L + m]);
+                    for (int m = 0; m < L; ++m)
+                        for (int i = 0; i < 3; ++i) T.gphi.push_back(sp.grad[(p * L + m) * 3 + i]);
+                }
+                e += static_cast<int64_t>(nb);
+                phi0 += static_cast<int64_t>(nb) * L;
+                part_rows += L;
+                T.chunks.push_back(C);
+            }
+        }
+    }
+    T.layer_chunk_ptr[nlayers] = static_cast<int32_t>(T.chunks.size());
+    T.layer_site_ptr[static_cast<size_t>(nlayers) * ns] = static_cast<int32_t>(T.chunks.size());
+    T.part_rows = part_rows;
+    T.nentries = e;
+    if (e > INT32_MAX) return HUB_EINVAL;
+
+    // ---- CSR maps
+    T.site_chunk_ptr.assign(ns + 1, 0);
+    for (const HubChunk& C : T.chunks) T.site_chunk_ptr[C.site + 1]++;
+    for (int s = 0; s < ns; ++s) T.site_chunk_ptr[s + 1] += T.site_chunk_ptr[s];
+    T.site_chunk_ids.resize(T.chunks.size());
+    {
+        std::vector<int32_t> fill(T.site_chunk_ptr.begin(), T.site_chunk_ptr.end() - 1);
+        for (size_t c = 0; c < T.chunks.size(); ++c) T.site_chunk_ids[fill[T.chunks[c].site]++] = static_cast<int32_t>(c);
+    }
+    T.species_orb_ptr.assign(nspec + 1, 0);
+    for (int s = 0; s < ns; ++s) T.species_orb_ptr[sites[s].species + 1] += T.site_L[s];
+    for (int t = 0; t < nspec; ++t) T.species_orb_ptr[t + 1] += T.species_orb_ptr[t];
+    T.species_orb_ids.resize(J);
+    T.orb_site.resize(J);
+    {
+        std::vector<int32_t> fill(T.species_orb_ptr.begin(), T.species_orb_ptr.end() - 1);
+        for (int s = 0; s < ns; ++s)
+            for (int m = 0; m < T.site_L[s]; ++m) {
+                T.species_orb_ids[fill[sites[s].species]++] = T.site_orb0[s] + m;
+                T.orb_site[T.site_orb0[s] + m] = s;
+            }
+    }
+    return HUB_OK;
+}

@@ -1,0 +1,102 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol declared in
+include/hub.h, rejects bad arguments before touching a GPU, and its host-side
+sphere builder agrees with the oracle's independent enumeration (point sets,
+images, orbital values and gradients).  No kernel is launched here."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+H = pytest.importorskip("paper_1711_08935_amd")
+
+from oracle.orbitals import build_sphere, radial_angular_grad  # noqa: E402
+from synth import make_config  # noqa: E402
+from tests.helpers import to_system  # noqa: E402
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "hub.h")).read()
+    return sorted(set(re.findall(r"\b(hub_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = H.lib()
+    syms = _header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(H.EXPORTS)
+
+
+def test_strerror_and_invalid_arguments():
+    lib = H.lib()
+    assert lib.hub_strerror(0) == b"ok"
+    assert lib.hub_strerror(-1) == b"invalid argument"
+    ctx = ctypes.c_void_p()
+    cell = (ctypes.c_double * 3)(10, 10, 10)
+    ng = (ctypes.c_int * 3)(8, 8, 8)
+    bad_ng = (ctypes.c_int * 3)(8, 0, 8)
+    assert lib.hub_create(None, cell, ng, 1, 0, 0) == H.HUB_EINVAL
+    assert lib.hub_create(ctypes.byref(ctx), cell, bad_ng, 1, 0, 0) == H.HUB_EINVAL
+    assert lib.hub_create(ctypes.byref(ctx), cell, ng, 3, 0, 0) == H.HUB_EINVAL      # bad spin mode
+    assert lib.hub_create(ctypes.byref(ctx), cell, ng, 4, 0, 0) == H.HUB_EINVAL      # spinor must be complex
+    assert lib.hub_create(ctypes.byref(ctx), cell, ng, 1, 0, 7) == H.HUB_EINVAL      # precision
+    assert lib.hub_create(ctypes.byref(ctx), cell, ng, 1, 0, 0) == H.HUB_OK
+    R = (ctypes.c_double * 3)(5, 5, 5)
+    assert lib.hub_add_site(ctx, R, 4, 1.0, 2.0, 0, None) == H.HUB_EINVAL            # l > 3
+    assert lib.hub_add_site(ctx, R, 2, -1.0, 2.0, 0, None) == H.HUB_EINVAL
+    assert lib.hub_add_site(ctx, R, 2, 1.0, 2.0, 99, None) == H.HUB_EINVAL
+    kr = (ctypes.c_double * 3)(0.25, 0, 0)
+    w = (ctypes.c_double * 1)(1.0)
+    assert lib.hub_set_kpoints(ctx, 1, kr, w) == H.HUB_EINVAL                         # real context, k != 0
+    v = ctypes.c_int64()
+    assert lib.hub_query(ctx, 0, ctypes.byref(v)) == H.HUB_ESTATE
+    assert lib.hub_finalize_host(ctx) == H.HUB_EINVAL                                 # no sites
+    assert lib.hub_add_site(ctx, R, 2, 2.0, 3.0, 0, None) == H.HUB_OK
+    assert lib.hub_finalize_host(ctx) == H.HUB_OK
+    assert lib.hub_add_site(ctx, R, 2, 2.0, 3.0, 0, None) == H.HUB_ESTATE             # after build
+    # device entry points refuse to run before hub_finalize (no GPU touched)
+    assert lib.hub_project(ctx, ctypes.c_void_p(1), 8, 8, ctypes.c_void_p(1)) == H.HUB_ESTATE
+    assert lib.hub_step(ctx, None, 0) == H.HUB_EINVAL
+    assert lib.hub_destroy(ctx) == H.HUB_OK
+    # a sphere that holds no grid point is rejected
+    ctx2 = ctypes.c_void_p()
+    assert lib.hub_create(ctypes.byref(ctx2), cell, ng, 1, 0, 0) == H.HUB_OK
+    R2 = (ctypes.c_double * 3)(0.6, 0.6, 0.6)
+    assert lib.hub_add_site(ctx2, R2, 1, 1.0, 0.05, 0, None) == H.HUB_OK
+    assert lib.hub_finalize_host(ctx2) == H.HUB_EINVAL
+    assert lib.hub_destroy(ctx2) == H.HUB_OK
+
+
+@pytest.mark.parametrize("name", ["gamma_d", "nio_afm", "spinor_layers", "rt_batched"])
+def test_host_spheres_match_oracle(name):
+    cfg = make_config(name, small=True)
+    hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                    is_complex=cfg.is_complex, finalize=False)
+    sys_ = to_system(cfg)
+    for I, site in enumerate(sys_.sites):
+        g, im, phi, grad = hub.site_points(I)
+        sp = build_sphere(sys_, site)
+        np.testing.assert_array_equal(g, sp.g)
+        np.testing.assert_array_equal(im, sp.n)
+        assert np.max(np.abs(phi - sp.phi.T)) < 1e-12 * np.max(np.abs(sp.phi))
+        og = radial_angular_grad(site, sp.d) * sp.norms[:, None, None]          # (L, 3, P)
+        assert np.max(np.abs(grad - og.transpose(2, 0, 1))) < 1e-12 * np.max(np.abs(og))
+    # every sphere entry is in exactly one layer; counts agree
+    assert hub.nentries == sum(len(build_sphere(sys_, s).g) for s in sys_.sites)
+
+
+def test_layers_and_counts_full_size_geometry():
+    cfg = make_config("nio_afm")
+    hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                    is_complex=True, finalize=False)
+    assert hub.site_npts == [58893, 58893, 34049, 34049]
+    assert hub.nlayers >= 2 and hub.nsets == 16 and hub.nspecies == 2
+    cfg3 = make_config("rt_batched")
+    hub3 = H.Hubbard(cfg3.cell, cfg3.ngrid, cfg3.sites, spin=cfg3.spin, finalize=False)
+    assert hub3.nlayers == 1                      # non-overlapping spheres: one layer
+    assert hub3.nentries == 759292 and hub3.J == 272
