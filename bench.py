@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Hubbard steps/s on one MI355X (one step = project + occupations + ACBN0
+U/J + apply, for every site, k-point, spin and state).
+
+Default workload: the NiO-like collinear antiferromagnet (cubic cell 8.35
+bohr, 48^3 grid, 2 Ni d + 2 O p sites, 2x2x2 k-points, 64 complex states per
+k and spin, Fermi-Dirac occupations), synthetic states.  ``value`` is the
+FP32-storage path (FP64 orbital table, FP64 sums) run as one captured
+hipGraph per step; the plain FP64 path (one launch per site and stage, no
+graph) and the FP64 graph path are timed beside it.  Occupation errors of
+the FP32 path are measured against the FP64 path on the same master states.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+Prints one JSON line.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+KERNEL_SOURCES = ["k_project.hip", "k_apply.hip", "kcommon.h"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="nio_afm",
+                    choices=["nio_afm", "rt_batched", "gamma_d", "spinor_layers", "forces_fcc"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="time only the FP32 graph path")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_08935_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def union_points(hub):
+    import numpy as np
+    gs = [hub.site_points(s)[0] for s in range(hub.nsites)]
+    return int(np.unique(np.concatenate(gs)).size)
+
+
+def time_steps(hub, psi, f, hpsi, mode, steps, warmup, bufs, rotate=None):
+    """Wall-clock (and HIP-event) time of ``steps`` Hubbard steps.  With
+    ``rotate`` the states change between steps and only the Hubbard steps are
+    timed (events around each step on the current stream)."""
+    import torch
+    for _ in range(warmup):
+        hub.step(psi, f, hpsi, mode=mode, bufs=bufs)
+    torch.cuda.synchronize()
+    if rotate is None:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            hub.step(psi, f, hpsi, mode=mode, bufs=bufs)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, e0.elapsed_time(e1) / 1e3
+    evs = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        rotate(i)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        hub.step(psi, f, hpsi, mode=mode, bufs=bufs)
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, sum(a.elapsed_time(b) for a, b in evs) / 1e3
+
+
+def cpu_baseline(cfg, psi_host, f, nsteps):
+    """The FP64 oracle (sphere form) timed on the host cores."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import projection as OP
+    from oracle import step as OS
+    from tests.helpers import to_system
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    tens = OS.site_tensors(sys_, sps)
+    times = []
+    for i in range(nsteps):
+        t0 = time.perf_counter()
+        OS.hubbard_step(sys_, psi_host, f, sps, tens, form="sphere")
+        times.append(time.perf_counter() - t0)
+        log(f"oracle step {i}: {times[-1]:.2f} s")
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return statistics.median(times), threads
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is a "
+                          "design (see DESIGN.md), so --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1711_08935_amd as H
+    from synth import make_config, make_occupations, make_states
+
+    cfg = make_config(args.workload)
+    log(f"workload {cfg.name}: grid {cfg.ngrid}, {len(cfg.sites)} sites, {cfg.nk} k, spin {cfg.spin}, "
+        f"{cfg.nstates} states")
+    t0 = time.perf_counter()
+    psi64 = make_states(cfg, device="cuda")
+    f = make_occupations(cfg)
+    f_d = torch.from_numpy(f).cuda()
+    torch.cuda.synchronize()
+    log(f"states generated in {time.perf_counter() - t0:.1f} s")
+
+    def ctx(prec):
+        return H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                         is_complex=cfg.is_complex, precision=prec)
+
+    hub32 = ctx("f32")
+    psi32 = psi64.to(hub32.state_dtype)
+    S = cfg.nstates
+    t0 = time.perf_counter()
+    hub32.coulomb(-1)
+    torch.cuda.synchronize()
+    coulomb_s = time.perf_counter() - t0
+    log(f"Coulomb tensors (setup) {coulomb_s * 1e3:.1f} ms")
+
+    rotate = None
+    if cfg.name == "rt_batched":
+        half = S // 2
+        rng = np.random.default_rng(cfg.seed + 100)
+        theta = torch.from_numpy(1e-3 * rng.uniform(0.5, 1.0, size=half) * rng.choice([-1.0, 1.0], size=half)).cuda()
+        cth, sth = torch.cos(theta), torch.sin(theta)
+
+        def rotate(i):
+            # synthetic propagator: Givens rotation of state pairs (i, i + S/2)
+            a = psi64[:, :, :half].clone()
+            b = psi64[:, :, half:2 * half]
+            psi64[:, :, :half] = cth * a - sth * b
+            psi64[:, :, half:2 * half] = sth * a + cth * b
+            psi32.copy_(psi64)
+
+    bufs32 = hub32.step_buffers(S)
+    hpsi32 = torch.zeros_like(psi32)
+    wall, ev = time_steps(hub32, psi32, f_d, hpsi32, "graph", args.steps, args.warmup, bufs32, rotate)
+    hub_time = ev if rotate is not None else wall
+    value = args.steps / hub_time
+    log(f"f32 graph: {value:.1f} steps/s ({hub_time / args.steps * 1e3:.3f} ms/step, wall {wall:.3f} s)")
+
+    detail = {"coulomb_setup_ms": round(coulomb_s * 1e3, 2)}
+    # ---------------------------------------------------------- profile pass
+    hub32.profile(True)
+    for _ in range(max(5, min(args.steps, 30))):
+        hub32.step(psi32, f_d, hpsi32, mode="batched", bufs=bufs32)
+    prof = hub32.profile_read()
+    hub32.profile(False)
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    detail["stage_avg_ms_f32"] = {k: round(v, 4) for k, v in stage_ms.items() if v > 0}
+    U_pts = union_points(hub32)
+    ncol = hub32.ncol(S)
+    esz = psi32.element_size()
+    proj_bytes = U_pts * ncol * esz * hub32.nsets               # psi read at every sphere point once
+    apply_bytes = 2 * proj_bytes                                # hpsi read + write
+    achieved = proj_bytes / (stage_ms["project"] * 1e-3) / 1e9
+    detail["apply_GBs"] = round(apply_bytes / (stage_ms["apply"] * 1e-3) / 1e9, 1)
+    detail["apply_frac"] = round(detail["apply_GBs"] / PEAK_HBM_GBS, 4)
+    detail["algorithmic_bytes_per_step"] = int(proj_bytes + apply_bytes)
+    detail["step_GBs"] = round((proj_bytes + apply_bytes) * value / 1e9, 1)
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_project_{cfg.name}.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": "k_project (gather + FP64 contraction)", "bytes_per_launch": int(proj_bytes)}
+
+    # ------------------------------------------------ FP64 comparison paths
+    if not args.no_compare:
+        hub64 = ctx("f64")
+        hub64.coulomb(-1)
+        bufs64 = hub64.step_buffers(S)
+        hpsi64 = torch.zeros_like(psi64)
+        k64 = max(5, args.steps // 2)
+        w, e = time_steps(hub64, psi64, f_d, hpsi64, "persite", k64, 2, bufs64, rotate)
+        plain = k64 / (e if rotate is not None else w)
+        w, e = time_steps(hub64, psi64, f_d, hpsi64, "graph", k64, 2, bufs64, rotate)
+        g64 = k64 / (e if rotate is not None else w)
+        log(f"f64 plain per-site: {plain:.1f} steps/s, f64 graph: {g64:.1f} steps/s")
+        detail.update(fp64_plain_steps_per_s=round(plain, 2), fp64_graph_steps_per_s=round(g64, 2),
+                      speedup_vs_fp64_plain=round(value / plain, 3))
+        # accuracy: one step of each path on the current master states
+        b32 = hub32.step(psi32, f_d, torch.zeros_like(psi32), mode="batched", bufs=hub32.step_buffers(S))
+        b64 = hub64.step(psi64, f_d, torch.zeros_like(psi64), mode="batched", bufs=hub64.step_buffers(S))
+        up = psi32.to(psi64.dtype)
+        b64r = hub64.step(up, f_d, torch.zeros_like(up), mode="batched", bufs=hub64.step_buffers(S))
+        torch.cuda.synchronize()
+        d_end = (b32["n"] - b64["n"]).abs().max().item()
+        d_ar = (b32["n"] - b64r["n"]).abs().max().item()
+        du = max((b32["U"] - b64["U"]).abs().max().item(), (b32["J"] - b64["J"]).abs().max().item())
+        du_ar = max((b32["U"] - b64r["U"]).abs().max().item(), (b32["J"] - b64r["J"]).abs().max().item())
+        detail.update(f32_occ_err_vs_f64_master=d_end, f32_occ_err_arithmetic=d_ar,
+                      f32_uj_err_vs_f64_master=du, f32_uj_err_arithmetic=du_ar)
+        log(f"f32 occupation error: vs FP64 master {d_end:.2e}, arithmetic {d_ar:.2e}; U/J {du:.2e} / {du_ar:.2e}")
+        del hub64
+
+    # ---------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline and cfg.name in ("nio_afm", "gamma_d", "spinor_layers"):
+        psi_host = psi64.cpu().numpy()
+        t_step, threads = cpu_baseline(cfg, psi_host, f, args.cpu_steps)
+        cpu = {"value": round(1.0 / t_step, 4), "unit": "Hubbard steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"median of {args.cpu_steps} whole FP64 oracle steps (sphere form, all "
+                         f"{hub32.nsets} k/spin sets) on the same states; Coulomb setup excluded"}
+
+    out = {
+        "metric": "Hubbard steps/s (project+occ+U/J+apply), FP32-split vs FP64 at 1e-9 occ err",
+        "value": round(value, 2), "unit": "Hubbard steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(hub_time / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": cfg.name, "grid": list(cfg.ngrid), "sites": len(cfg.sites),
+                                        "kpoints": cfg.nk, "spin": cfg.spin, "states": S,
+                                        "mode": "hipGraph per step", "storage": "f32 states, f64 orbital table",
+                                        "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "detail": detail,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -217,6 +217,25 @@ typedef struct hub_step_io {
 } hub_step_io;
 int hub_step(hub_ctx* ctx, const hub_step_io* io, int mode);
 
+/* Per-stage device timing with HIP events recorded around the launches of
+ * each stage on the context stream (eager launches only; a captured step
+ * graph is not split).  Stages: HUB_STAGE_* below.  hub_profile(ctx, 1)
+ * starts recording, 0 stops.  hub_profile_read synchronizes the context
+ * stream, returns the accumulated milliseconds ms[HUB_NSTAGES] and launch
+ * counts counts[HUB_NSTAGES] (host arrays, either may be NULL) and resets
+ * them. */
+#define HUB_NSTAGES 8
+#define HUB_STAGE_PROJECT 0
+#define HUB_STAGE_REDUCE 1
+#define HUB_STAGE_NBAR 2
+#define HUB_STAGE_OCC 3
+#define HUB_STAGE_ACBN0 4
+#define HUB_STAGE_APPLY 5
+#define HUB_STAGE_GRADPROJ 6
+#define HUB_STAGE_FORCES 7
+int hub_profile(hub_ctx* ctx, int enable);
+int hub_profile_read(hub_ctx* ctx, double* ms, int64_t* counts);
+
 /* Release the context and everything it owns (waits for its stream). */
 int hub_destroy(hub_ctx* ctx);
 

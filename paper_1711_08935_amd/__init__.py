@@ -43,7 +43,8 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_set_tuning", "hub_finalize_host", "hub_finalize", "hub_set_stream", "hub_query",
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
-           "hub_strerror"]
+           "hub_strerror", "hub_profile", "hub_profile_read"]
+STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
 def lib():
@@ -79,6 +80,8 @@ def lib():
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
+        "hub_profile": [P, I],
+        "hub_profile_read": [P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -319,6 +322,16 @@ class Hubbard:
         _check(lib().hub_forces(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)), _dptr(Ueff),
                                 _dptr(n), _dptr(F)), "hub_forces")
         return F
+
+    def profile(self, enable=True):
+        _check(lib().hub_profile(self._ctx, int(bool(enable))), "hub_profile")
+
+    def profile_read(self):
+        """{stage: (milliseconds, launches)} accumulated since the last read."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        _check(lib().hub_profile_read(self._ctx, ms, cnt), "hub_profile_read")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
     def step_buffers(self, nstates):
         return dict(c=self.empty_c(nstates), n=self.empty_n(), pbar=self.empty_n(),

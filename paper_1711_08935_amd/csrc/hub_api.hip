@@ -65,6 +65,14 @@ struct hub_ctx {
     double* d_nbar_ws = nullptr;
     size_t nbar_cap = 0;
 
+    // per-stage event timing
+    bool prof = false;
+    bool capturing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double prof_ms[HUB_NSTAGES] = {0};
+    int64_t prof_n[HUB_NSTAGES] = {0};
+
     // captured step
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -124,6 +132,40 @@ void drop_graph(hub_ctx* c) {
     c->gkey.valid = false;
 }
 
+// Stage timer: records an event pair around the launches of one stage when
+// profiling is on and no graph is being captured.
+struct StageTimer {
+    hub_ctx* c;
+    int stage;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t get() {
+        if (!c->ev_pool.empty()) {
+            hipEvent_t e = c->ev_pool.back();
+            c->ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    StageTimer(hub_ctx* ctx, int st) : c(ctx), stage(st) {
+        if (c->prof && !c->capturing) {
+            e0 = get();
+            e1 = get();
+            if (e0) (void)hipEventRecord(e0, c->stream);
+        }
+    }
+    ~StageTimer() {
+        if (e0 && e1) {
+            (void)hipEventRecord(e1, c->stream);
+            c->ev_pending.push_back({stage, {e0, e1}});
+        } else {
+            if (e0) c->ev_pool.push_back(e0);
+            if (e1) c->ev_pool.push_back(e1);
+        }
+    }
+};
+
 int ensure(double** buf, size_t* cap, size_t n, hub_ctx* c) {
     if (*cap >= n && *buf) return HUB_OK;
     if (*buf) {
@@ -163,16 +205,12 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad)
     a.ld = ld;
     a.qstride = c->G() * ld * c->ncplx();
     a.ncol = ncol;
-    a.nspin = c->nspin();
-    a.spinor = c->spin_mode == HUB_SPINOR;
+    a.ncplx = c->ncplx();
     a.chunks = c->d_chunks;
     a.chunk_list = c->d_all;
     a.gidx = c->d_gidx;
-    a.img = c->d_img;
     a.tab = grad ? c->d_gphi : c->d_phi;
     a.tabmult = grad ? 3 : 1;
-    a.phase = c->d_phase;
-    a.nimg = static_cast<int>(c->T.images.size() / 3);
     a.prows = c->T.part_rows * a.tabmult;
     return a;
 }
@@ -191,6 +229,10 @@ ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
     r.site_chunk_ids = c->d_site_chunk_ids;
     r.orb_site = c->d_orb_site;
     r.site_orb0 = c->d_site_orb0;
+    r.phase = c->d_phase;
+    r.nimg = static_cast<int>(c->T.images.size() / 3);
+    r.nspin = c->nspin();
+    r.spinor = c->spin_mode == HUB_SPINOR;
     r.dV = (c->cell[0] / c->ngrid[0]) * (c->cell[1] / c->ngrid[1]) * (c->cell[2] / c->ngrid[2]);
     return r;
 }
@@ -204,8 +246,11 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     if (st) return st;
     ProjArgs a = proj_args(c, psi, ld, ncol, grad);
     a.part = c->d_part;
-    const int cpl = pick_cpl(c, psi, ld, ncol, 0);
+    int cpl = pick_cpl(c, psi, ld, ncol, 0);
+    if (grad && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();     // gradient tiles hold 3L functions
     const int waves = c->tune_waves[0];
+    {
+    StageTimer tm(c, grad ? HUB_STAGE_GRADPROJ : HUB_STAGE_PROJECT);
     if (!per_site) {
         HUB_TRY(launch_project(a, static_cast<int>(c->T.chunks.size()), c->nsets(), c->precision, c->is_complex,
                                cpl, waves, c->stream));
@@ -217,7 +262,9 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
                                    c->is_complex, cpl, waves, c->stream));
         }
     }
+    }
     ReduceArgs r = reduce_args(c, out, ncol, mult);
+    StageTimer tm(c, HUB_STAGE_REDUCE);
     HUB_TRY(launch_reduce(r, c->nsets(), c->stream));
     return HUB_OK;
 }
@@ -243,6 +290,7 @@ int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, d
         b.nspecies = c->T.nspecies;
         b.species_orb_ptr = c->d_species_orb_ptr;
         b.species_orb_ids = c->d_species_orb_ids;
+        StageTimer tm(c, HUB_STAGE_NBAR);
         HUB_TRY(launch_nbar(b, c->nsets(), c->stream));
     }
     OccArgs o{};
@@ -264,6 +312,7 @@ int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, d
     o.nk = c->nk;
     o.nblk = c->nblk();
     o.nspecies = c->T.nspecies;
+    StageTimer tm(c, HUB_STAGE_OCC);
     if (!per_site) {
         HUB_TRY(launch_occ(o, 0, c->T.nsites, c->stream));
     } else {
@@ -291,6 +340,7 @@ int do_acbn0(hub_ctx* c, const double* n, const double* pbar, double* U, double*
     a.Ueff = Ueff;
     a.status = status;
     a.nblk = c->nblk();
+    StageTimer tm(c, HUB_STAGE_ACBN0);
     if (!per_site) {
         HUB_TRY(launch_acbn0(a, 0, c->T.nsites, c->stream));
     } else {
@@ -313,7 +363,6 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.nblk = c->nblk();
     a.chunks = c->d_chunks;
     a.gidx = c->d_gidx;
-    a.img = c->d_img;
     a.tab = c->d_phi;
     a.phase = c->d_phase;
     a.nimg = static_cast<int>(c->T.images.size() / 3);
@@ -326,6 +375,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     const int cpl = pick_cpl(c, hpsi, ld, ncol, 1);
     const int waves = c->tune_waves[1];
     const int ns = c->T.nsites;
+    StageTimer tm(c, HUB_STAGE_APPLY);
     for (int lay = 0; lay < c->T.nlayers; ++lay) {
         if (!per_site) {
             ApplyArgs b = a;
@@ -719,6 +769,7 @@ int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const doubl
     a.nspin = c->nspin();
     a.nq = c->nsets();
     a.nblk = c->nblk();
+    StageTimer tm(c, HUB_STAGE_FORCES);
     HUB_TRY(launch_forces(a, c->stream));
     return HUB_OK;
 }
@@ -751,7 +802,9 @@ int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
         hipStream_t keep = c->stream;
         c->stream = c->cap_stream;
         HUB_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
         st = run_step(c, io, false);
+        c->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         c->stream = keep;
@@ -774,9 +827,41 @@ int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
     return HUB_OK;
 }
 
+int hub_profile(hub_ctx* c, int enable) {
+    if (!c || (enable != 0 && enable != 1)) return HUB_EINVAL;
+    c->prof = enable == 1;
+    return HUB_OK;
+}
+
+int hub_profile_read(hub_ctx* c, double* ms, int64_t* counts) {
+    if (!c) return HUB_EINVAL;
+    if (!c->ev_pending.empty()) HUB_TRY(hipStreamSynchronize(c->stream));
+    for (auto& p : c->ev_pending) {
+        float t = 0.0f;
+        HUB_TRY(hipEventElapsedTime(&t, p.second.first, p.second.second));
+        c->prof_ms[p.first] += t;
+        c->prof_n[p.first] += 1;
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    c->ev_pending.clear();
+    for (int i = 0; i < HUB_NSTAGES; ++i) {
+        if (ms) ms[i] = c->prof_ms[i];
+        if (counts) counts[i] = c->prof_n[i];
+        c->prof_ms[i] = 0.0;
+        c->prof_n[i] = 0;
+    }
+    return HUB_OK;
+}
+
 int hub_destroy(hub_ctx* c) {
     if (!c) return HUB_EINVAL;
     if (c->built_dev) (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->ev_pending) {
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     release(c);
     delete c;
     return HUB_OK;

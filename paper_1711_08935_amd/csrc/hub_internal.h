@@ -8,7 +8,8 @@
 #include "hub.h"
 
 // One work-list chunk: a run of sphere entries of one site inside one apply
-// layer.  Within a layer no two entries share a grid point, so chunks of the
+// layer, all with the same lattice image (so one Bloch phase serves the whole
+// chunk).  Within a layer no two entries share a grid point, so chunks of the
 // same layer can be applied concurrently without atomics.
 struct HubChunk {
     int32_t site;
@@ -20,6 +21,8 @@ struct HubChunk {
     int32_t part0;   // first row of this chunk in the projection workspace
     int32_t species;
     int64_t phi0;    // offset of the chunk's orbital values (entries * L)
+    int32_t img;     // lattice image shared by every entry of the chunk
+    int32_t pad;
 };
 
 struct SiteDef {

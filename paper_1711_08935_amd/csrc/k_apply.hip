@@ -6,7 +6,9 @@
 // V^{ss'}_ab c^{s'}_b, V^{ss'}_ab = Ueff (delta delta / 2 - n^{s's}_ba)); the
 // transpose follows from differentiating E_U (Eq. minimization).  Then for
 // every sphere entry e of the chunk:
-//   hpsi[g_e][col] += exp(-i k.T_e) sum_a phi_a(e) B_a(col).
+//   hpsi[g_e][col] += exp(-i k.T_e) sum_a phi_a(e) B_a(col),
+// where the phase is the same for every entry of a chunk and is folded into
+// B once per chunk.
 // The host groups entries in layers that never repeat a grid point, and
 // launches one layer at a time, so no two lanes in flight update the same
 // element: no atomics, deterministic results.  Sums are FP64; the updated
@@ -94,29 +96,40 @@ __device__ __forceinline__ void coefficients(const ApplyArgs& a, const HubChunk&
             }
         }
     }
+    if constexpr (CPX) {
+        // fold the chunk's Bloch phase exp(-i k.T) into the coefficients
+        const int k = a.spinor ? q : q / a.nspin;
+        const double pr = a.phase[(static_cast<int64_t>(k) * a.nimg + C.img) * 2];
+        const double pi = -a.phase[(static_cast<int64_t>(k) * a.nimg + C.img) * 2 + 1];
+#pragma unroll
+        for (int ai = 0; ai < L; ++ai)
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) {
+                const double br = B[ai][2 * cc], bi = B[ai][2 * cc + 1];
+                B[ai][2 * cc] = pr * br - pi * bi;
+                B[ai][2 * cc + 1] = pr * bi + pi * br;
+            }
+    }
 }
 
 template <typename T, bool CPX, bool SPINOR, int CPL, int L>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C) {
     constexpr int NC = CPX ? 2 : 1;
     constexpr int NV = CPL * NC;
-    constexpr int U = 2;
+    constexpr int U = (L > 5) ? 2 : 4;
     const int lane = threadIdx.x & (HUB_WAVE - 1);
     const int wave = threadIdx.x / HUB_WAVE;
     const int nw = blockDim.x / HUB_WAVE;
     const int q = blockIdx.z;
     const int col0 = (blockIdx.y * HUB_WAVE + lane) * CPL;
     if (col0 >= a.ncol) return;
-    const int k = a.spinor ? q : q / a.nspin;
 
     double B[L][NV];
     coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
 
     T* __restrict__ h_q = reinterpret_cast<T*>(a.hpsi) + static_cast<int64_t>(q) * a.qstride;
     const int32_t* __restrict__ gi = a.gidx + C.e0;
-    const int32_t* __restrict__ im = a.img + C.e0;
     const double* __restrict__ tb = a.tab + C.phi0;
-    const double* __restrict__ ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
 
     for (int e = wave; e < C.ne; e += nw * U) {
         T row[U][NV];
@@ -145,19 +158,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
                 for (int v = 0; v < NV; ++v) add[v] = fma(wa, B[ai][v], add[v]);
             }
             T out[NV];
-            if constexpr (CPX) {
-                const int ig = im[ii];
-                const double pr = ph[2 * ig], pi = -ph[2 * ig + 1];     // exp(-i k.T)
 #pragma unroll
-                for (int cc = 0; cc < CPL; ++cc) {
-                    const double ar = add[2 * cc], ai_ = add[2 * cc + 1];
-                    out[2 * cc] = static_cast<T>(static_cast<double>(row[u][2 * cc]) + (pr * ar - pi * ai_));
-                    out[2 * cc + 1] = static_cast<T>(static_cast<double>(row[u][2 * cc + 1]) + (pr * ai_ + pi * ar));
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) out[v] = static_cast<T>(static_cast<double>(row[u][v]) + add[v]);
-            }
+            for (int v = 0; v < NV; ++v) out[v] = static_cast<T>(static_cast<double>(row[u][v]) + add[v]);
             store_vec<T, NV>(h_q + off[u], out);
         }
     }

@@ -1,42 +1,48 @@
 // Projection kernel: partial sums of <phi_j,k|psi> over one work-list chunk.
 //
-// part[q][row][col] = sum_{e in chunk} exp(+i k.T_e) tab[e][f] psi_q[g_e][col]
+// part[q][row][col] = sum_{e in chunk} tab[e][f] psi_q[g_e][col]
 // for the chunk's functions f (orbitals, or their three gradient components),
-// row = chunk.part0 * tabmult + f.  The dV factor and the sum over the chunks
-// of a site are applied by the reduction kernel.  Paper: the brackets of
-// Eq. occ_matrices with the Bloch phase of Fig. 1 (Sec. II).
+// row = chunk.part0 * tabmult + f.  Every entry of a chunk has the same
+// lattice image, so the Bloch phase exp(+i k.T) of Fig. 1, the dV factor
+// and the sum over the chunks of a site are applied once per chunk by the
+// reduction kernel.  Paper: the brackets of Eq. occ_matrices (Sec. II).
 //
 // Work mapping (gfx950, 64-wide waves): blockIdx.x = chunk, blockIdx.y =
 // tile of 64*CPL columns, blockIdx.z = state set.  Each lane owns CPL
-// consecutive columns and reads them with one or two 16-byte loads from the
-// state row of grid point g_e, so a wave reads 64*CPL contiguous columns per
-// sphere entry.  Entry data (g, image, orbital values) is uniform across the
-// wave.  The waves of a work-group take interleaved entries and are summed
-// through LDS at the end.  Products and sums are FP64 for both storage
-// precisions.
+// consecutive columns and reads them with 16-byte loads from the state row
+// of grid point g_e, so a wave reads 64*CPL contiguous columns per sphere
+// entry.  Entry data (g, orbital values) is uniform across the wave and is
+// read through the scalar cache.  The waves of a work-group take interleaved
+// entries and are summed through LDS at the end.  Products and sums are FP64
+// for both storage precisions; for complex states the real orbital value
+// multiplies the real and imaginary parts separately (2 FMAs per column).
 
 #include "kcommon.h"
 
 namespace {
 
-template <typename T, bool CPX, int CPL, int NF>
-__device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C) {
-    constexpr int NC = CPX ? 2 : 1;
-    constexpr int NV = CPL * NC;
-    constexpr int U = (NF > 9) ? 2 : 4;
+template <int NV>
+struct ProjLds {
+    double red[3][HUB_WAVE][NV];
+};
+
+template <typename T, int NV, int NF>
+__device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C, ProjLds<NV>& lds) {
+    constexpr int NC_MAX = 2;
+    (void)NC_MAX;
+    constexpr int U = (NF > 9) ? 2 : ((NF > 5) ? 4 : 8);
     const int lane = threadIdx.x & (HUB_WAVE - 1);
     const int wave = threadIdx.x / HUB_WAVE;
     const int nw = blockDim.x / HUB_WAVE;
     const int q = blockIdx.z;
-    const int col0 = (blockIdx.y * HUB_WAVE + lane) * CPL;
+    const int NC = a.ncplx;
+    const int cpl = NV / NC;
+    const int col0 = (blockIdx.y * HUB_WAVE + lane) * cpl;
     const bool active = col0 < a.ncol;
-    const int k = a.spinor ? q : q / a.nspin;
 
     const T* __restrict__ psi_q = reinterpret_cast<const T*>(a.psi) + static_cast<int64_t>(q) * a.qstride;
     const int32_t* __restrict__ gi = a.gidx + C.e0;
-    const int32_t* __restrict__ im = a.img + C.e0;
     const double* __restrict__ tb = a.tab + C.phi0 * a.tabmult;
-    const double* __restrict__ ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
 
     double acc[NF][NV];
 #pragma unroll
@@ -46,11 +52,10 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 
     for (int e = wave; e < C.ne; e += nw * U) {
         T row[U][NV];
-        int idx[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            idx[u] = e + u * nw;
-            const int ii = (idx[u] < C.ne) ? idx[u] : e;
+            const int idx = e + u * nw;
+            const int ii = (idx < C.ne) ? idx : e;
             const int64_t g = gi[ii];
             if (active) {
                 load_vec<T, NV>(psi_q + (g * a.ld + col0) * NC, row[u]);
@@ -61,51 +66,31 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool ok = idx[u] < C.ne;
-            const int ii = ok ? idx[u] : e;
-            const double* __restrict__ w = tb + static_cast<int64_t>(ii) * NF;
-            double pr = 1.0, pi = 0.0;
-            if constexpr (CPX) {
-                const int ig = im[ii];
-                pr = ph[2 * ig];
-                pi = ph[2 * ig + 1];
-            }
-            if (!ok) { pr = 0.0; pi = 0.0; }
+            const int idx = e + u * nw;
+            const bool ok = idx < C.ne;
+            const double* __restrict__ w = tb + static_cast<int64_t>(ok ? idx : e) * NF;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const double wf = w[f];
-                if constexpr (CPX) {
-                    const double wr = wf * pr, wi = wf * pi;
+                const double wf = ok ? w[f] : 0.0;
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const double vr = static_cast<double>(row[u][2 * c]);
-                        const double vi = static_cast<double>(row[u][2 * c + 1]);
-                        acc[f][2 * c] = fma(wr, vr, fma(-wi, vi, acc[f][2 * c]));
-                        acc[f][2 * c + 1] = fma(wr, vi, fma(wi, vr, acc[f][2 * c + 1]));
-                    }
-                } else {
-                    const double wr = ok ? wf : 0.0;
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) acc[f][c] = fma(wr, static_cast<double>(row[u][c]), acc[f][c]);
-                }
+                for (int v = 0; v < NV; ++v) acc[f][v] = fma(wf, static_cast<double>(row[u][v]), acc[f][v]);
             }
         }
     }
 
     // sum the waves of the work-group, one function at a time
     if (nw > 1) {
-        __shared__ double red[3][HUB_WAVE][NV];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             if (wave > 0) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) red[wave - 1][lane][v] = acc[f][v];
+                for (int v = 0; v < NV; ++v) lds.red[wave - 1][lane][v] = acc[f][v];
             }
             __syncthreads();
             if (wave == 0) {
                 for (int w = 1; w < nw; ++w)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[f][v] += red[w - 1][lane][v];
+                    for (int v = 0; v < NV; ++v) acc[f][v] += lds.red[w - 1][lane][v];
             }
             __syncthreads();
         }
@@ -116,45 +101,56 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            if (col0 + c < a.ncol) {
-#pragma unroll
-                for (int r = 0; r < NC; ++r)
-                    out[(static_cast<int64_t>(f) * a.ncol + col0 + c) * NC + r] = acc[f][c * NC + r];
-            }
+        for (int v = 0; v < NV; ++v) {
+            const int col = col0 + v / NC;
+            if (col < a.ncol) out[(static_cast<int64_t>(f) * a.ncol + col0) * NC + v] = acc[f][v];
         }
     }
 }
 
-template <typename T, bool CPX, int CPL>
+// NV = scalars per lane (columns per lane times 1 or 2); GRAD selects the
+// gradient table (three functions per orbital).
+template <typename T, int NV, bool GRAD>
 __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
+    __shared__ ProjLds<NV> lds;
     const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
-    switch (C.L * a.tabmult) {
-    case 1: project_body<T, CPX, CPL, 1>(a, C); break;
-    case 3: project_body<T, CPX, CPL, 3>(a, C); break;
-    case 5: project_body<T, CPX, CPL, 5>(a, C); break;
-    case 7: project_body<T, CPX, CPL, 7>(a, C); break;
-    case 9: project_body<T, CPX, CPL, 9>(a, C); break;
-    case 15: project_body<T, CPX, CPL, 15>(a, C); break;
-    case 21: project_body<T, CPX, CPL, 21>(a, C); break;
-    default: break;
+    if constexpr (!GRAD) {
+        switch (C.L) {
+        case 1: project_body<T, NV, 1>(a, C, lds); break;
+        case 3: project_body<T, NV, 3>(a, C, lds); break;
+        case 5: project_body<T, NV, 5>(a, C, lds); break;
+        case 7: project_body<T, NV, 7>(a, C, lds); break;
+        default: break;
+        }
+    } else {
+        switch (C.L) {
+        case 1: project_body<T, NV, 3>(a, C, lds); break;
+        case 3: project_body<T, NV, 9>(a, C, lds); break;
+        case 5: project_body<T, NV, 15>(a, C, lds); break;
+        case 7: project_body<T, NV, 21>(a, C, lds); break;
+        default: break;
+        }
     }
 }
 
-template <typename T, bool CPX, int CPL>
-hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
-    const int tiles = (a.ncol + HUB_WAVE * CPL - 1) / (HUB_WAVE * CPL);
+template <typename T, int NV, bool GRAD>
+hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
+    const int tiles = (a.ncol + HUB_WAVE * cpl - 1) / (HUB_WAVE * cpl);
     dim3 grid(nchunks, tiles, nq);
-    hipLaunchKernelGGL((k_project<T, CPX, CPL>), grid, dim3(HUB_WAVE * waves), 0, st, a);
+    hipLaunchKernelGGL((k_project<T, NV, GRAD>), grid, dim3(HUB_WAVE * waves), 0, st, a);
     return hipGetLastError();
 }
 
-template <typename T, bool CPX>
-hipError_t launch_c(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
-    switch (cpl) {
-    case 1: return launch_t<T, CPX, 1>(a, nchunks, nq, waves, st);
-    case 2: return launch_t<T, CPX, 2>(a, nchunks, nq, waves, st);
-    case 4: return launch_t<T, CPX, 4>(a, nchunks, nq, waves, st);
+template <typename T, bool GRAD>
+hipError_t launch_g(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, hipStream_t st) {
+    const int nv = cpl * (cplx ? 2 : 1);
+    switch (nv) {
+    case 1: return launch_t<T, 1, GRAD>(a, nchunks, nq, cpl, waves, st);
+    case 2: return launch_t<T, 2, GRAD>(a, nchunks, nq, cpl, waves, st);
+    case 4: return launch_t<T, 4, GRAD>(a, nchunks, nq, cpl, waves, st);
+    case 8:
+        if constexpr (!GRAD) return launch_t<T, 8, GRAD>(a, nchunks, nq, cpl, waves, st);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -164,10 +160,11 @@ hipError_t launch_c(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, 
 hipError_t launch_project(const ProjArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
                           hipStream_t st) {
     if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    const bool grad = a.tabmult == 3;
     if (prec == HUB_F64) {
-        return cplx ? launch_c<double, true>(a, nchunks, nq, cpl, waves, st)
-                    : launch_c<double, false>(a, nchunks, nq, cpl, waves, st);
+        return grad ? launch_g<double, true>(a, nchunks, nq, cplx, cpl, waves, st)
+                    : launch_g<double, false>(a, nchunks, nq, cplx, cpl, waves, st);
     }
-    return cplx ? launch_c<float, true>(a, nchunks, nq, cpl, waves, st)
-                : launch_c<float, false>(a, nchunks, nq, cpl, waves, st);
+    return grad ? launch_g<float, true>(a, nchunks, nq, cplx, cpl, waves, st)
+                : launch_g<float, false>(a, nchunks, nq, cplx, cpl, waves, st);
 }

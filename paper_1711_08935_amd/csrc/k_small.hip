@@ -12,7 +12,8 @@ constexpr int TILE = 128; // states staged per LDS tile in k_occ
 
 // ---------------------------------------------------------------- reduction
 // out[q][r][col] = dV * sum over the chunks of the row's site of
-// part[q][chunk.part0 * mult + (r - orb0 * mult)][col].
+// exp(+i k.T_chunk) part[q][chunk.part0 * mult + (r - orb0 * mult)][col]
+// (the Bloch phase of Fig. 1, shared by all entries of a chunk).
 __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
@@ -21,13 +22,20 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
     const int site = a.orb_site[r / a.mult];
     const int local = r - a.site_orb0[site] * a.mult;
     const int NC = a.ncplx;
+    const int k = a.spinor ? q : q / a.nspin;
+    const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     double s0 = 0.0, s1 = 0.0;
     for (int t = a.site_chunk_ptr[site]; t < a.site_chunk_ptr[site + 1]; ++t) {
         const HubChunk& C = a.chunks[a.site_chunk_ids[t]];
         const int64_t row = static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.mult + local;
         const double* p = a.part + (row * a.ncol + col) * NC;
-        s0 += p[0];
-        if (NC == 2) s1 += p[1];
+        if (NC == 2) {
+            const double pr = ph[2 * C.img], pi = ph[2 * C.img + 1];
+            s0 += pr * p[0] - pi * p[1];
+            s1 += pr * p[1] + pi * p[0];
+        } else {
+            s0 += p[0];
+        }
     }
     double* o = a.out + ((static_cast<int64_t>(q) * a.nrows + r) * a.ncol + col) * NC;
     o[0] = a.dV * s0;

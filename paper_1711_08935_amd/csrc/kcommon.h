@@ -15,16 +15,12 @@ struct ProjArgs {
     int64_t ld;               // columns per grid point
     int64_t qstride;          // scalars between state sets (G * ld * ncplx)
     int ncol;                 // columns used (nstates or 2 nstates)
-    int nspin;                // collinear channels (state set q -> k = q / nspin)
-    int spinor;               // 1: state set q is k-point q
+    int ncplx;                // 1 real, 2 complex
     const HubChunk* chunks;
     const int32_t* chunk_list;
     const int32_t* gidx;
-    const int32_t* img;
     const double* tab;        // orbital table (or gradient table)
     int tabmult;              // 1: phi, 3: grad phi
-    const double* phase;      // [nk][nimg] (re, im) of exp(+i k.T)
-    int nimg;
     double* part;             // [nq][prows][ncol] (x2 complex)
     int64_t prows;            // rows per state set = part_rows * tabmult
 };
@@ -42,9 +38,8 @@ struct ApplyArgs {
     const HubChunk* chunks;
     const int32_t* chunk_list;
     const int32_t* gidx;
-    const int32_t* img;
     const double* tab;
-    const double* phase;
+    const double* phase;      // [nk][nimg] (re, im) of exp(+i k.T)
     int nimg;
     const double* c;          // [nq][J][ncol] (x2 complex)
     int J;

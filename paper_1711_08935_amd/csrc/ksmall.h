@@ -11,6 +11,8 @@ struct ReduceArgs {
     const HubChunk* chunks;
     const int32_t* site_chunk_ptr; const int32_t* site_chunk_ids;
     const int32_t* orb_site; const int32_t* site_orb0;
+    const double* phase; int nimg;        // exp(+i k.T) per k-point and image
+    int nspin; int spinor;                // state set -> k-point
     double dV;
 };
 

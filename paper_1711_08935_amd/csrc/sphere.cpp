@@ -255,12 +255,21 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
             T.layer_site_ptr[static_cast<size_t>(lay) * ns + s] = static_cast<int32_t>(T.chunks.size());
             const int L = T.site_L[s];
             const SiteSphere& sp = T.spheres[s];
+            // entries of this (layer, site), grouped by lattice image, g ascending
             std::vector<size_t> mine;
             for (size_t p = 0; p < pts[s].size(); ++p)
                 if (layer_of[s][p] == lay) mine.push_back(p);
-            for (size_t b = 0; b < mine.size(); b += chunk) {
-                const size_t nb = std::min(mine.size() - b, static_cast<size_t>(chunk));
+            auto img_of = [&](size_t p) {
+                return image_id[std::make_tuple(pts[s][p].img[0], pts[s][p].img[1], pts[s][p].img[2])];
+            };
+            std::stable_sort(mine.begin(), mine.end(), [&](size_t a, size_t b) { return img_of(a) < img_of(b); });
+            for (size_t b = 0; b < mine.size();) {
+                const int im = img_of(mine[b]);
+                size_t nb = 0;
+                while (b + nb < mine.size() && nb < static_cast<size_t>(chunk) && img_of(mine[b + nb]) == im) ++nb;
                 HubChunk C;
+                C.img = im;
+                C.pad = 0;
                 C.site = s;
                 C.layer = lay;
                 C.e0 = static_cast<int32_t>(e);
@@ -283,6 +292,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                 phi0 += static_cast<int64_t>(nb) * L;
                 part_rows += L;
                 T.chunks.push_back(C);
+                b += nb;
             }
         }
     }
