@@ -113,12 +113,14 @@ __device__ __forceinline__ void coefficients(const ApplyArgs& a, const HubChunk&
 }
 
 template <typename T, bool CPX, bool SPINOR, int CPL, int L>
-__device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C) {
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C, const int32_t* __restrict__ gidx,
+                                           const double* __restrict__ tab, T* __restrict__ hpsi) {
     constexpr int NC = CPX ? 2 : 1;
     constexpr int NV = CPL * NC;
     constexpr int U = (L > 5) ? 2 : 4;
     const int lane = threadIdx.x & (HUB_WAVE - 1);
-    const int wave = threadIdx.x / HUB_WAVE;
+    // wave index made provably uniform so entry data goes through scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
     const int nw = blockDim.x / HUB_WAVE;
     const int q = blockIdx.z;
     const int col0 = (blockIdx.y * HUB_WAVE + lane) * CPL;
@@ -127,9 +129,9 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     double B[L][NV];
     coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
 
-    T* __restrict__ h_q = reinterpret_cast<T*>(a.hpsi) + static_cast<int64_t>(q) * a.qstride;
-    const int32_t* __restrict__ gi = a.gidx + C.e0;
-    const double* __restrict__ tb = a.tab + C.phi0;
+    T* __restrict__ h_q = hpsi + static_cast<int64_t>(q) * a.qstride;
+    const int32_t* __restrict__ gi = gidx + C.e0;
+    const double* __restrict__ tb = tab + C.phi0;
 
     for (int e = wave; e < C.ne; e += nw * U) {
         T row[U][NV];
@@ -165,14 +167,18 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     }
 }
 
+// The sphere tables and the output are separate restrict-qualified kernel
+// arguments: the stores into hpsi inside the entry loop then cannot alias the
+// table reads, and the uniform entry data stays on scalar loads.
 template <typename T, bool CPX, bool SPINOR, int CPL>
-__global__ void __launch_bounds__(256) k_apply(const ApplyArgs a) {
+__global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t* __restrict__ gidx,
+                                               const double* __restrict__ tab, T* __restrict__ hpsi) {
     const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
     switch (C.L) {
-    case 1: apply_body<T, CPX, SPINOR, CPL, 1>(a, C); break;
-    case 3: apply_body<T, CPX, SPINOR, CPL, 3>(a, C); break;
-    case 5: apply_body<T, CPX, SPINOR, CPL, 5>(a, C); break;
-    case 7: apply_body<T, CPX, SPINOR, CPL, 7>(a, C); break;
+    case 1: apply_body<T, CPX, SPINOR, CPL, 1>(a, C, gidx, tab, hpsi); break;
+    case 3: apply_body<T, CPX, SPINOR, CPL, 3>(a, C, gidx, tab, hpsi); break;
+    case 5: apply_body<T, CPX, SPINOR, CPL, 5>(a, C, gidx, tab, hpsi); break;
+    case 7: apply_body<T, CPX, SPINOR, CPL, 7>(a, C, gidx, tab, hpsi); break;
     default: break;
     }
 }
@@ -181,7 +187,8 @@ template <typename T, bool CPX, bool SPINOR, int CPL>
 hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
     const int tiles = (a.ncol + HUB_WAVE * CPL - 1) / (HUB_WAVE * CPL);
     dim3 grid(nchunks, tiles, nq);
-    hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL>), grid, dim3(HUB_WAVE * waves), 0, st, a);
+    hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL>), grid, dim3(HUB_WAVE * waves), 0, st, a, a.gidx, a.tab,
+                       reinterpret_cast<T*>(a.hpsi));
     return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     (void)NC_MAX;
     constexpr int U = (NF > 9) ? 2 : ((NF > 5) ? 4 : 8);
     const int lane = threadIdx.x & (HUB_WAVE - 1);
-    const int wave = threadIdx.x / HUB_WAVE;
+    // wave index made provably uniform so entry data goes through scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
     const int nw = blockDim.x / HUB_WAVE;
     const int q = blockIdx.z;
     const int NC = a.ncplx;
@@ -50,28 +51,32 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[f][v] = 0.0;
 
+    // Lanes past the last column read column 0 (their sums are discarded)
+    // and entries past the end of the chunk re-read the first entry with a
+    // zero weight, so every load below is unconditional: no divergent branch
+    // separates the U loads, and all of them are in flight together.
+    const int colc = active ? col0 : 0;
     for (int e = wave; e < C.ne; e += nw * U) {
         T row[U][NV];
+        int ii[U];
+        double okf[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int idx = e + u * nw;
-            const int ii = (idx < C.ne) ? idx : e;
-            const int64_t g = gi[ii];
-            if (active) {
-                load_vec<T, NV>(psi_q + (g * a.ld + col0) * NC, row[u]);
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) row[u][v] = T(0);
-            }
+            ii[u] = (idx < C.ne) ? idx : e;
+            okf[u] = (idx < C.ne) ? 1.0 : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = e + u * nw;
-            const bool ok = idx < C.ne;
-            const double* __restrict__ w = tb + static_cast<int64_t>(ok ? idx : e) * NF;
+            const int64_t g = gi[ii[u]];
+            load_vec<T, NV>(psi_q + (g * a.ld + colc) * NC, row[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double* __restrict__ w = tb + static_cast<int64_t>(ii[u]) * NF;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const double wf = ok ? w[f] : 0.0;
+                const double wf = w[f] * okf[u];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) acc[f][v] = fma(wf, static_cast<double>(row[u][v]), acc[f][v]);
             }
