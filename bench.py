@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time only the FP32 graph path")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
     return ap.parse_args()
 
 
@@ -125,6 +126,7 @@ def main():
     import torch
 
     import paper_1711_08935_amd as H
+    from paper_1711_08935_amd.tune import autotune
     from synth import make_config, make_occupations, make_states
 
     cfg = make_config(args.workload)
@@ -167,12 +169,21 @@ def main():
 
     bufs32 = hub32.step_buffers(S)
     hpsi32 = torch.zeros_like(psi32)
+    tuned = None
+    if not args.no_tune:
+        # setup: fill the step buffers once, then pick kernel shapes on them
+        hub32.step(psi32, f_d, hpsi32, mode="batched", bufs=bufs32)
+        tuned = autotune(hub32, psi32, bufs32["c"], bufs32["n"], bufs32["Ueff"])
+        log(f"autotune: project {tuned['project']}, apply {tuned['apply']}")
     wall, ev = time_steps(hub32, psi32, f_d, hpsi32, "graph", args.steps, args.warmup, bufs32, rotate)
     hub_time = ev if rotate is not None else wall
     value = args.steps / hub_time
     log(f"f32 graph: {value:.1f} steps/s ({hub_time / args.steps * 1e3:.3f} ms/step, wall {wall:.3f} s)")
 
     detail = {"coulomb_setup_ms": round(coulomb_s * 1e3, 2)}
+    if tuned is not None:
+        detail["tuned_shapes"] = {"project": list(tuned["project"][0]), "apply": list(tuned["apply"][0]),
+                                  "candidates_ms": tuned["table"]}
     # ---------------------------------------------------------- profile pass
     hub32.profile(True)
     for _ in range(max(5, min(args.steps, 30))):
@@ -208,6 +219,9 @@ def main():
         hub64.coulomb(-1)
         bufs64 = hub64.step_buffers(S)
         hpsi64 = torch.zeros_like(psi64)
+        if not args.no_tune:
+            hub64.step(psi64, f_d, hpsi64, mode="batched", bufs=bufs64)
+            autotune(hub64, psi64, bufs64["c"], bufs64["n"], bufs64["Ueff"])
         k64 = max(5, args.steps // 2)
         w, e = time_steps(hub64, psi64, f_d, hpsi64, "persite", k64, 2, bufs64, rotate)
         plain = k64 / (e if rotate is not None else w)

@@ -181,9 +181,10 @@ int ensure(double** buf, size_t* cap, size_t n, hub_ctx* c) {
     return HUB_OK;
 }
 
-// Columns per lane: the widest vector that keeps every lane's columns
-// aligned and inside the row, and still fills one wave with columns.
-int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int ncol, int which) {
+// Columns per lane: by default the vector that gives each lane 16 bytes per
+// state row (lanes span several state sets when a set is narrow), provided
+// every lane's columns stay aligned and inside the row (ld % cpl == 0).
+int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int which) {
     const size_t e = c->elem();
     auto ok = [&](int cpl) {
         const size_t vb = std::min<size_t>(16, cpl * e);
@@ -191,8 +192,8 @@ int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int ncol, int which)
     };
     const int want = c->tune_cpl[which];
     if (want == 1 || ((want == 2 || want == 4) && ok(want))) return want;
-    for (int cpl : {4, 2}) {
-        if (ok(cpl) && ncol >= 64 * cpl) return cpl;
+    for (int cpl : {4, 2, 1}) {
+        if (cpl * e <= 16 && ok(cpl)) return cpl;
     }
     return 1;
 }
@@ -206,6 +207,7 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad)
     a.qstride = c->G() * ld * c->ncplx();
     a.ncol = ncol;
     a.ncplx = c->ncplx();
+    a.nq = c->nsets();
     a.chunks = c->d_chunks;
     a.chunk_list = c->d_all;
     a.gidx = c->d_gidx;
@@ -246,7 +248,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     if (st) return st;
     ProjArgs a = proj_args(c, psi, ld, ncol, grad);
     a.part = c->d_part;
-    int cpl = pick_cpl(c, psi, ld, ncol, 0);
+    int cpl = pick_cpl(c, psi, ld, 0);
     if (grad && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();     // gradient tiles hold 3L functions
     const int waves = c->tune_waves[0];
     {
@@ -358,6 +360,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.qstride = c->G() * ld * c->ncplx();
     a.ncol = ncol;
     a.nstates = nstates;
+    a.nq = c->nsets();
     a.nspin = c->nspin();
     a.spinor = c->spin_mode == HUB_SPINOR;
     a.nblk = c->nblk();
@@ -372,7 +375,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.ueff = Ueff;
     a.colscale = colscale;
     a.alpha = alpha;
-    const int cpl = pick_cpl(c, hpsi, ld, ncol, 1);
+    const int cpl = pick_cpl(c, hpsi, ld, 1);
     const int waves = c->tune_waves[1];
     const int ns = c->T.nsites;
     StageTimer tm(c, HUB_STAGE_APPLY);

@@ -14,9 +14,10 @@
 // element: no atomics, deterministic results.  Sums are FP64; the updated
 // element is rounded once to the storage type.
 //
-// Work mapping: blockIdx.x = chunk, blockIdx.y = column tile, blockIdx.z =
-// state set; each wave of the work-group takes interleaved entries (no
-// reduction needed; B is recomputed per wave).
+// Work mapping: blockIdx.x = chunk, blockIdx.y = tile of 64 lanes over the
+// flattened (state set, column group) space (as in the projection); each
+// wave of the work-group takes interleaved entries (no reduction needed; B
+// is recomputed per wave).
 
 #include "kcommon.h"
 
@@ -122,9 +123,11 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     // wave index made provably uniform so entry data goes through scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
     const int nw = blockDim.x / HUB_WAVE;
-    const int q = blockIdx.z;
-    const int col0 = (blockIdx.y * HUB_WAVE + lane) * CPL;
-    if (col0 >= a.ncol) return;
+    const int cg = (a.ncol + CPL - 1) / CPL;
+    const int t = blockIdx.y * HUB_WAVE + lane;
+    if (t >= a.nq * cg) return;
+    const int q = t / cg;
+    const int col0 = (t - q * cg) * CPL;
 
     double B[L][NV];
     coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
@@ -185,8 +188,8 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t*
 
 template <typename T, bool CPX, bool SPINOR, int CPL>
 hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
-    const int tiles = (a.ncol + HUB_WAVE * CPL - 1) / (HUB_WAVE * CPL);
-    dim3 grid(nchunks, tiles, nq);
+    const int64_t groups = static_cast<int64_t>(nq) * ((a.ncol + CPL - 1) / CPL);
+    dim3 grid(nchunks, static_cast<unsigned>((groups + HUB_WAVE - 1) / HUB_WAVE), 1);
     hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL>), grid, dim3(HUB_WAVE * waves), 0, st, a, a.gidx, a.tab,
                        reinterpret_cast<T*>(a.hpsi));
     return hipGetLastError();

@@ -8,10 +8,12 @@
 // reduction kernel.  Paper: the brackets of Eq. occ_matrices (Sec. II).
 //
 // Work mapping (gfx950, 64-wide waves): blockIdx.x = chunk, blockIdx.y =
-// tile of 64*CPL columns, blockIdx.z = state set.  Each lane owns CPL
-// consecutive columns and reads them with 16-byte loads from the state row
-// of grid point g_e, so a wave reads 64*CPL contiguous columns per sphere
-// entry.  Entry data (g, orbital values) is uniform across the wave and is
+// tile of 64 lanes over the flattened (state set, column group) space, with
+// CG = ceil(ncol / CPL) groups per set.  Each lane owns CPL consecutive
+// columns of one set and reads them with 16- or 32-byte loads from the state
+// row of grid point g_e; when a set has fewer than 64*CPL columns one wave
+// covers several sets, so no lane idles and every load instruction moves a
+// full wave's worth of bytes.  Entry data (g, orbital values) is uniform across the wave and is
 // read through the scalar cache.  The waves of a work-group take interleaved
 // entries and are summed through LDS at the end.  Products and sums are FP64
 // for both storage precisions; for complex states the real orbital value
@@ -35,11 +37,13 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     // wave index made provably uniform so entry data goes through scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
     const int nw = blockDim.x / HUB_WAVE;
-    const int q = blockIdx.z;
     const int NC = a.ncplx;
     const int cpl = NV / NC;
-    const int col0 = (blockIdx.y * HUB_WAVE + lane) * cpl;
-    const bool active = col0 < a.ncol;
+    const int cg = (a.ncol + cpl - 1) / cpl;
+    const int t = blockIdx.y * HUB_WAVE + lane;
+    const bool active = t < a.nq * cg;
+    const int q = active ? t / cg : 0;
+    const int col0 = (t - (t / cg) * cg) * cpl;
 
     const T* __restrict__ psi_q = reinterpret_cast<const T*>(a.psi) + static_cast<int64_t>(q) * a.qstride;
     const int32_t* __restrict__ gi = a.gidx + C.e0;
@@ -51,7 +55,7 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[f][v] = 0.0;
 
-    // Lanes past the last column read column 0 (their sums are discarded)
+    // Lanes past the last set read column 0 of set 0 (their sums are discarded)
     // and entries past the end of the chunk re-read the first entry with a
     // zero weight, so every load below is unconditional: no divergent branch
     // separates the U loads, and all of them are in flight together.
@@ -140,8 +144,8 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
 
 template <typename T, int NV, bool GRAD>
 hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
-    const int tiles = (a.ncol + HUB_WAVE * cpl - 1) / (HUB_WAVE * cpl);
-    dim3 grid(nchunks, tiles, nq);
+    const int64_t groups = static_cast<int64_t>(nq) * ((a.ncol + cpl - 1) / cpl);
+    dim3 grid(nchunks, static_cast<unsigned>((groups + HUB_WAVE - 1) / HUB_WAVE), 1);
     hipLaunchKernelGGL((k_project<T, NV, GRAD>), grid, dim3(HUB_WAVE * waves), 0, st, a);
     return hipGetLastError();
 }

@@ -16,6 +16,7 @@ struct ProjArgs {
     int64_t qstride;          // scalars between state sets (G * ld * ncplx)
     int ncol;                 // columns used (nstates or 2 nstates)
     int ncplx;                // 1 real, 2 complex
+    int nq;                   // state sets
     const HubChunk* chunks;
     const int32_t* chunk_list;
     const int32_t* gidx;
@@ -32,6 +33,7 @@ struct ApplyArgs {
     int64_t qstride;
     int ncol;
     int nstates;
+    int nq;                   // state sets
     int nspin;
     int spinor;
     int nblk;                 // blocks per site in n

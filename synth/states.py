@@ -62,12 +62,22 @@ def _nmon(l):
     return (l + 1) * (l + 2) // 2
 
 
-def _cholqr2(A, dV):
+def _cholqr2(A, dV, rows=65536):
+    """CholQR applied twice under the dV metric.  Only plain matrix products
+    run on the device (in row blocks of a standard shape); the small Gram
+    matrix is factorized and its triangular factor inverted on the host."""
     for _ in range(2):
-        S = dV * (A.conj().transpose(0, 1) @ A)
-        S = 0.5 * (S + S.conj().transpose(0, 1))
-        R = torch.linalg.cholesky(S, upper=True)
-        A = torch.linalg.solve_triangular(R, A, upper=True, left=False)
+        S = torch.zeros((A.shape[1], A.shape[1]), dtype=A.dtype, device=A.device)
+        for r0 in range(0, A.shape[0], rows):
+            blk = A[r0:r0 + rows]
+            S += blk.conj().transpose(0, 1) @ blk
+        S = (dV * S).cpu().numpy()
+        S = 0.5 * (S + S.conj().T)
+        R = np.linalg.cholesky(S).conj().T                      # S = R^H R, R upper triangular
+        Rinv = np.linalg.solve(R, np.eye(R.shape[0], dtype=R.dtype))
+        Rinv_d = torch.from_numpy(np.ascontiguousarray(Rinv)).to(A.device)
+        for r0 in range(0, A.shape[0], rows):
+            A[r0:r0 + rows] = A[r0:r0 + rows] @ Rinv_d
     return A
 
 

@@ -1,0 +1,109 @@
+"""GPU edge cases against the oracle: a single state, a padded odd leading
+dimension (forces one column per lane), an s shell next to p/d/f shells, a
+site on the cell corner whose sphere overlaps its own periodic images
+(duplicate grid points inside one site, several apply layers), a non-cubic
+cell with complex k-points, and argument errors raised before any launch."""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1711_08935_amd as H  # noqa: E402
+from synth import Config  # noqa: E402
+from tests.gpu_common import c_to_oracle, device_states, make_hub, n_site, oracle_case  # noqa: E402
+from tests.helpers import normwise  # noqa: E402
+
+
+def _cfg(spin="collinear", nstates=5, cplx=True):
+    sites = [dict(R=np.array([0.0, 0.0, 0.0]), l=2, zeta=1.8, rc=3.3, species=0),
+             dict(R=np.array([3.1, 2.2, 4.05]), l=0, zeta=1.2, rc=2.0, species=1),
+             dict(R=np.array([1.3, 4.4, 1.9]), l=3, zeta=2.1, rc=2.6, species=2),
+             dict(R=np.array([4.7, 0.6, 2.8]), l=1, zeta=1.5, rc=2.2, species=1)]
+    kp = np.array([[0.25, -0.5, 0.125], [0.0, 0.25, 0.0]]) if cplx else np.zeros((1, 3))
+    return Config(name="edge", cell=(6.0, 5.5, 6.5), ngrid=(15, 14, 16), sites=sites, kpts=kp,
+                  kweights=np.full(len(kp), 1.0 / len(kp)), spin=spin, is_complex=cplx, nstates=nstates, seed=9)
+
+
+def _rand_psi(cfg, S, rng):
+    shape = (cfg.nk, cfg.G, S, 2) if cfg.spin == "spinor" else (cfg.nq, cfg.G, S)
+    a = rng.normal(size=shape)
+    if cfg.is_complex:
+        a = a + 1j * rng.normal(size=shape)
+    return a
+
+
+def _check(cfg, prec, psi, f, ld_pad=0):
+    hub = make_hub(cfg, prec, chunk=64)
+    S = cfg.nstates
+    if ld_pad:
+        ncol = hub.ncol(S)
+        full = np.zeros(psi.shape[:2] + (ncol + ld_pad,), dtype=psi.dtype)
+        full[..., :ncol] = psi.reshape(psi.shape[0], psi.shape[1], -1)
+        big, _ = device_states(hub, full)
+        psi_d = big[..., :ncol]
+        _, used = device_states(hub, psi)
+    else:
+        psi_d, used = device_states(hub, psi)
+    sys_, sps, tens, ref = oracle_case(cfg, used, f)
+    f_d = torch.from_numpy(f).cuda()
+    hub.coulomb(-1)
+    c = hub.project(psi_d, nstates=S)
+    n, pbar, nb = hub.occupations(c, f_d)
+    U, J, Ueff, st = hub.acbn0(n, pbar)
+    h = torch.zeros_like(psi_d)
+    hub.apply(Ueff, n, c, h, nstates=S)
+    torch.cuda.synchronize()
+    rc = ref["c"] if cfg.is_complex else ref["c"].real
+    assert normwise(c_to_oracle(hub, c), rc) < 1e-12
+    for I in range(hub.nsites):
+        assert normwise(n_site(hub, n, I, hub.site_L[I]), ref["n"][I]) < 1e-12
+    assert np.max(np.abs(U.cpu().numpy() - ref["U"])) < 1e-12 * max(1e-3, np.abs(ref["U"]).max())
+    hh = h.cpu().numpy()
+    if hh.ndim == 3 and cfg.spin == "spinor":
+        hh = hh.reshape(hh.shape[0], hh.shape[1], -1, 2)
+    rh = ref["hpsi"] if cfg.is_complex else ref["hpsi"].real
+    assert normwise(hh, rh) < (1e-12 if prec == "f64" else 2e-7)
+    return hub
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_state_and_mixed_shells(prec):
+    cfg = _cfg(nstates=1)
+    rng = np.random.default_rng(1)
+    hub = _check(cfg, prec, _rand_psi(cfg, 1, rng) * 0.1, rng.uniform(0, 1, size=(cfg.nq, 1)))
+    assert hub.nlayers >= 2                  # the corner d site overlaps its own images
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_padded_odd_leading_dimension(prec):
+    cfg = _cfg(nstates=7)
+    rng = np.random.default_rng(2)
+    _check(cfg, prec, _rand_psi(cfg, 7, rng) * 0.1, rng.uniform(0, 1, size=(cfg.nq, 7)), ld_pad=2)   # ld = 9
+
+
+def test_spinor_ragged_and_real_unpolarized():
+    rng = np.random.default_rng(3)
+    cfg = _cfg(spin="spinor", nstates=3)
+    _check(cfg, "f64", _rand_psi(cfg, 3, rng) * 0.1, rng.uniform(0, 1, size=(cfg.nk, 3)))
+    cfg2 = _cfg(spin="unpolarized", nstates=67, cplx=False)
+    _check(cfg2, "f32", _rand_psi(cfg2, 67, rng) * 0.1, rng.uniform(0, 1, size=(cfg2.nq, 67)))
+
+
+def test_argument_errors_raise_before_launch():
+    cfg = _cfg(nstates=4)
+    hub = make_hub(cfg, "f64")
+    psi = torch.zeros((cfg.nq, cfg.G, 4), dtype=torch.complex128, device="cuda")
+    with pytest.raises(TypeError):
+        hub.project(psi.to(torch.complex64))                  # wrong storage type
+    with pytest.raises(ValueError):
+        hub.project(psi[:1])                                  # wrong number of sets
+    with pytest.raises(H.HubError) as e:
+        hub.acbn0(hub.empty_n(), hub.empty_n())              # Coulomb tensors not computed yet
+    assert e.value.code == H.HUB_ESTATE
+    rc = H.lib().hub_project(hub._ctx, psi.data_ptr(), 2, 4, psi.data_ptr())   # ld < nstates
+    assert rc == H.HUB_EINVAL

@@ -165,3 +165,25 @@ def test_autograd_energy_gradients(case):
     d = OF.gradient_projections(sys_, case["psi_used"], sps)
     Fo = OF.forces_analytic(sys_, ref["c"], d, ref["V"], case["f"])
     assert normwise(-R.grad.cpu().numpy(), Fo) < 1e-11
+
+
+def test_tuning_variants_agree(case):
+    """Every kernel shape (columns per lane x waves per work-group) gives the
+    same projections and V_U psi up to summation order."""
+    hub = case["hub"]
+    psi_d = case["psi_d"]
+    try:
+        for cpl in (1, 2, 4):
+            for waves in (1, 2, 4):
+                hub.set_tuning(0, cpl, waves)
+                hub.set_tuning(1, cpl, waves)
+                c = hub.project(psi_d)
+                h = torch.zeros_like(psi_d)
+                hub.apply(case["Ueff"], case["n"], case["c"], h)
+                torch.cuda.synchronize()
+                assert normwise(c.cpu().numpy(), case["c"].cpu().numpy()) < 1e-13, (cpl, waves)
+                bar = 1e-13 if case["prec"] == "f64" else 1e-7
+                assert normwise(h.cpu().numpy(), case["hpsi"].cpu().numpy()) < bar, (cpl, waves)
+    finally:
+        hub.set_tuning(0, 0, 4)
+        hub.set_tuning(1, 0, 4)
