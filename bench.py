@@ -44,6 +44,12 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="time only the FP32 graph path")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
+    ap.add_argument("--chunk", type=int, default=None, help="sphere entries per work-list chunk")
+    ap.add_argument("--shapes", default=None,
+                    help="fixed kernel shapes PCPL,PWAVES,PLAYOUT,ACPL,AWAVES,ALAYOUT instead of autotuning "
+                         "(profiling runs use the shapes the autotuner picked)")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB three times (counter calibration)")
     return ap.parse_args()
 
 
@@ -141,7 +147,7 @@ def main():
 
     def ctx(prec):
         return H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
-                         is_complex=cfg.is_complex, precision=prec)
+                         is_complex=cfg.is_complex, precision=prec, chunk=args.chunk)
 
     hub32 = ctx("f32")
     psi32 = psi64.to(hub32.state_dtype)
@@ -170,7 +176,13 @@ def main():
     bufs32 = hub32.step_buffers(S)
     hpsi32 = torch.zeros_like(psi32)
     tuned = None
-    if not args.no_tune:
+    if args.shapes:
+        v = [int(x) for x in args.shapes.split(",")]
+        pc, pw, ps, ac, aw, asp = v if len(v) == 6 else (v[0], v[1], -1, v[2], v[3], -1)
+        hub32.set_tuning(0, pc, pw, ps)
+        hub32.set_tuning(1, ac, aw, asp)
+        log(f"fixed shapes: project {pc}x{pw} layout {ps}, apply {ac}x{aw} layout {asp}")
+    elif not args.no_tune:
         # setup: fill the step buffers once, then pick kernel shapes on them
         hub32.step(psi32, f_d, hpsi32, mode="batched", bufs=bufs32)
         tuned = autotune(hub32, psi32, bufs32["c"], bufs32["n"], bufs32["Ueff"])
@@ -180,7 +192,30 @@ def main():
     value = args.steps / hub_time
     log(f"f32 graph: {value:.1f} steps/s ({hub_time / args.steps * 1e3:.3f} ms/step, wall {wall:.3f} s)")
 
-    detail = {"coulomb_setup_ms": round(coulomb_s * 1e3, 2)}
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.calibrate_copy_mb} MiB")
+        del src, dst
+
+    # reference: a plain device-to-device copy of 2 GiB (read + write)
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_GBs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
+    detail = {"coulomb_setup_ms": round(coulomb_s * 1e3, 2), "device_copy_GBs": round(copy_GBs, 1)}
     if tuned is not None:
         detail["tuned_shapes"] = {"project": list(tuned["project"][0]), "apply": list(tuned["apply"][0]),
                                   "candidates_ms": tuned["table"]}

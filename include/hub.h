@@ -107,14 +107,17 @@ int hub_add_site(hub_ctx* ctx, const double R[3], int l, double zeta, double rc,
  * pass NaN to return the site to ACBN0 (the default).  Any time. */
 int hub_set_fixed_ueff(hub_ctx* ctx, int site, double ueff);
 
-/* Entries per work-list chunk (default 1024; 64..65536).  Before
+/* Entries per work-list chunk (default 512; 64..65536).  Before
  * hub_finalize*. */
 int hub_set_chunk(hub_ctx* ctx, int chunk_entries);
 
-/* Kernel shape: columns handled per lane (1, 2 or 4; 0 = automatic) and
- * waves per work-group (1, 2 or 4) for the projection (which = 0) and the
- * application (which = 1).  Any time after creation. */
-int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves);
+/* Kernel shape for the projection (which = 0) and the application
+ * (which = 1): columns handled per lane (1, 2 or 4; 0 = automatic), waves
+ * per work-group (1, 2 or 4), and the lane layout (1: every wave inside one
+ * state set; 0: narrow state sets packed across the lanes of a wave;
+ * -1: automatic).  Every shape computes the same result.  Any time after
+ * creation. */
+int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves, int layout);
 
 /* Build the sphere maps, orbital tables (grid-normalized, dV sum phi^2 = 1,
  * Sec. II), image/phase tables and the work list on the host.  Needs no GPU.

@@ -63,7 +63,7 @@ def lib():
         "hub_add_site": [P, DP, I, D, D, I, ctypes.POINTER(I)],
         "hub_set_fixed_ueff": [P, I, D],
         "hub_set_chunk": [P, I],
-        "hub_set_tuning": [P, I, I, I],
+        "hub_set_tuning": [P, I, I, I, I],
         "hub_finalize_host": [P],
         "hub_finalize": [P, P],
         "hub_set_stream": [P, P],
@@ -199,8 +199,11 @@ class Hubbard:
     def set_fixed_ueff(self, site, ueff):
         _check(lib().hub_set_fixed_ueff(self._ctx, int(site), float(ueff)), "hub_set_fixed_ueff")
 
-    def set_tuning(self, which, cols_per_lane, waves):
-        _check(lib().hub_set_tuning(self._ctx, int(which), int(cols_per_lane), int(waves)), "hub_set_tuning")
+    def set_tuning(self, which, cols_per_lane, waves, layout=-1):
+        """Kernel shape of the projection (which=0) or apply (1); layout 1 =
+        one state set per wave, 0 = sets packed across lanes, -1 = automatic."""
+        _check(lib().hub_set_tuning(self._ctx, int(which), int(cols_per_lane), int(waves), int(layout)),
+               "hub_set_tuning")
 
     def site_points(self, site):
         """Host copy of one site's sphere: (g, image3, phi, grad) numpy arrays."""

@@ -37,9 +37,10 @@ struct hub_ctx {
     int nk = 1;
     std::vector<double> kred{0.0, 0.0, 0.0}, kw{1.0};
     std::vector<SiteDef> sites;
-    int chunk_entries = 1024;
+    int chunk_entries = 512;
     int tune_cpl[2] = {0, 0};
     int tune_waves[2] = {4, 4};
+    int tune_layout[2] = {-1, -1};
     bool built_host = false, built_dev = false;
     HostTables T;
     int device = -1;
@@ -198,6 +199,13 @@ int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int which) {
     return 1;
 }
 
+// Lane layout: one state set per wave when a set fills whole waves (uniform
+// set index, scalar row bases), else sets packed across the lanes.
+int pick_wide(const hub_ctx* c, int ncol, int cpl, int which) {
+    if (c->tune_layout[which] >= 0) return c->tune_layout[which];
+    return ncol >= 64 * cpl ? 1 : 0;
+}
+
 bool built(const hub_ctx* c) { return c && c->built_dev; }
 
 ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad) {
@@ -250,6 +258,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     a.part = c->d_part;
     int cpl = pick_cpl(c, psi, ld, 0);
     if (grad && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();     // gradient tiles hold 3L functions
+    a.wide = pick_wide(c, ncol, cpl, 0);
     const int waves = c->tune_waves[0];
     {
     StageTimer tm(c, grad ? HUB_STAGE_GRADPROJ : HUB_STAGE_PROJECT);
@@ -376,6 +385,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.colscale = colscale;
     a.alpha = alpha;
     const int cpl = pick_cpl(c, hpsi, ld, 1);
+    a.wide = pick_wide(c, ncol, cpl, 1);
     const int waves = c->tune_waves[1];
     const int ns = c->T.nsites;
     StageTimer tm(c, HUB_STAGE_APPLY);
@@ -511,12 +521,14 @@ int hub_set_chunk(hub_ctx* c, int chunk_entries) {
     return HUB_OK;
 }
 
-int hub_set_tuning(hub_ctx* c, int which, int cpl, int waves) {
+int hub_set_tuning(hub_ctx* c, int which, int cpl, int waves, int layout) {
     if (!c || (which != 0 && which != 1)) return HUB_EINVAL;
     if (cpl != 0 && cpl != 1 && cpl != 2 && cpl != 4) return HUB_EINVAL;
     if (waves != 1 && waves != 2 && waves != 4) return HUB_EINVAL;
+    if (layout < -1 || layout > 1) return HUB_EINVAL;
     c->tune_cpl[which] = cpl;
     c->tune_waves[which] = waves;
+    c->tune_layout[which] = layout;
     drop_graph(c);
     return HUB_OK;
 }

@@ -14,10 +14,11 @@
 // element: no atomics, deterministic results.  Sums are FP64; the updated
 // element is rounded once to the storage type.
 //
-// Work mapping: blockIdx.x = chunk, blockIdx.y = tile of 64 lanes over the
-// flattened (state set, column group) space (as in the projection); each
-// wave of the work-group takes interleaved entries (no reduction needed; B
-// is recomputed per wave).
+// Work mapping: blockIdx.x = chunk, blockIdx.y = column tile, with the same
+// two lane layouts as the projection (WIDE: one state set per wave, so the
+// set's potential matrix and phase are uniform; packed: narrow sets share a
+// wave).  Each wave of the work-group takes interleaved entries (no
+// reduction needed; B is recomputed per wave).
 
 #include "kcommon.h"
 
@@ -113,7 +114,7 @@ __device__ __forceinline__ void coefficients(const ApplyArgs& a, const HubChunk&
     }
 }
 
-template <typename T, bool CPX, bool SPINOR, int CPL, int L>
+template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C, const int32_t* __restrict__ gidx,
                                            const double* __restrict__ tab, T* __restrict__ hpsi) {
     constexpr int NC = CPX ? 2 : 1;
@@ -124,10 +125,18 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
     const int nw = blockDim.x / HUB_WAVE;
     const int cg = (a.ncol + CPL - 1) / CPL;
-    const int t = blockIdx.y * HUB_WAVE + lane;
-    if (t >= a.nq * cg) return;
-    const int q = t / cg;
-    const int col0 = (t - q * cg) * CPL;
+    int q, col0;
+    if constexpr (WIDE) {
+        const int tps = (cg + HUB_WAVE - 1) / HUB_WAVE;          // tiles per set (q uniform)
+        q = blockIdx.y / tps;
+        col0 = ((blockIdx.y - q * tps) * HUB_WAVE + lane) * CPL;
+        if (col0 >= a.ncol) return;
+    } else {
+        const int t = blockIdx.y * HUB_WAVE + lane;
+        if (t >= a.nq * cg) return;
+        q = t / cg;
+        col0 = (t - q * cg) * CPL;
+    }
 
     double B[L][NV];
     coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
@@ -135,24 +144,21 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     T* __restrict__ h_q = hpsi + static_cast<int64_t>(q) * a.qstride;
     const int32_t* __restrict__ gi = gidx + C.e0;
     const double* __restrict__ tb = tab + C.phi0;
+    const int lofs = col0 * NC;
 
-    for (int e = wave; e < C.ne; e += nw * U) {
+    const int nj = (C.ne - wave + nw - 1) / nw;
+    int j = 0;
+    for (; j + U <= nj; j += U) {
         T row[U][NV];
-        int64_t off[U];
-        bool ok[U];
+        int64_t rbase[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = e + u * nw;
-            ok[u] = idx < C.ne;
-            const int ii = ok[u] ? idx : e;
-            off[u] = (static_cast<int64_t>(gi[ii]) * a.ld + col0) * NC;
-            load_vec<T, NV>(h_q + off[u], row[u]);
+            rbase[u] = static_cast<int64_t>(gi[wave + (j + u) * nw]) * a.ld * NC;
+            load_row<T, NV>(h_q + rbase[u] + lofs, row[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!ok[u]) continue;
-            const int ii = e + u * nw;
-            const double* __restrict__ w = tb + static_cast<int64_t>(ii) * L;
+            const double* __restrict__ w = tb + static_cast<int64_t>(wave + (j + u) * nw) * L;
             double add[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) add[v] = 0.0;
@@ -165,33 +171,59 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
             T out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) out[v] = static_cast<T>(static_cast<double>(row[u][v]) + add[v]);
-            store_vec<T, NV>(h_q + off[u], out);
+            store_row<T, NV>(h_q + rbase[u] + lofs, out);
         }
+    }
+    for (; j < nj; ++j) {
+        const int e = wave + j * nw;
+        const int64_t rb = static_cast<int64_t>(gi[e]) * a.ld * NC;
+        T row[NV];
+        load_row<T, NV>(h_q + rb + lofs, row);
+        const double* __restrict__ w = tb + static_cast<int64_t>(e) * L;
+        double add[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) add[v] = 0.0;
+#pragma unroll
+        for (int ai = 0; ai < L; ++ai) {
+            const double wa = w[ai];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) add[v] = fma(wa, B[ai][v], add[v]);
+        }
+        T out[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v] = static_cast<T>(static_cast<double>(row[v]) + add[v]);
+        store_row<T, NV>(h_q + rb + lofs, out);
     }
 }
 
 // The sphere tables and the output are separate restrict-qualified kernel
 // arguments: the stores into hpsi inside the entry loop then cannot alias the
 // table reads, and the uniform entry data stays on scalar loads.
-template <typename T, bool CPX, bool SPINOR, int CPL>
+template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE>
 __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t* __restrict__ gidx,
                                                const double* __restrict__ tab, T* __restrict__ hpsi) {
     const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
     switch (C.L) {
-    case 1: apply_body<T, CPX, SPINOR, CPL, 1>(a, C, gidx, tab, hpsi); break;
-    case 3: apply_body<T, CPX, SPINOR, CPL, 3>(a, C, gidx, tab, hpsi); break;
-    case 5: apply_body<T, CPX, SPINOR, CPL, 5>(a, C, gidx, tab, hpsi); break;
-    case 7: apply_body<T, CPX, SPINOR, CPL, 7>(a, C, gidx, tab, hpsi); break;
+    case 1: apply_body<T, CPX, SPINOR, CPL, 1, WIDE>(a, C, gidx, tab, hpsi); break;
+    case 3: apply_body<T, CPX, SPINOR, CPL, 3, WIDE>(a, C, gidx, tab, hpsi); break;
+    case 5: apply_body<T, CPX, SPINOR, CPL, 5, WIDE>(a, C, gidx, tab, hpsi); break;
+    case 7: apply_body<T, CPX, SPINOR, CPL, 7, WIDE>(a, C, gidx, tab, hpsi); break;
     default: break;
     }
 }
 
 template <typename T, bool CPX, bool SPINOR, int CPL>
 hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
-    const int64_t groups = static_cast<int64_t>(nq) * ((a.ncol + CPL - 1) / CPL);
-    dim3 grid(nchunks, static_cast<unsigned>((groups + HUB_WAVE - 1) / HUB_WAVE), 1);
-    hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL>), grid, dim3(HUB_WAVE * waves), 0, st, a, a.gidx, a.tab,
-                       reinterpret_cast<T*>(a.hpsi));
+    const int64_t cg = (a.ncol + CPL - 1) / CPL;
+    if (a.wide) {
+        const int64_t tiles = static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE);
+        hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, true>), dim3(nchunks, static_cast<unsigned>(tiles), 1),
+                           dim3(HUB_WAVE * waves), 0, st, a, a.gidx, a.tab, reinterpret_cast<T*>(a.hpsi));
+    } else {
+        const int64_t tiles = (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE;
+        hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, false>), dim3(nchunks, static_cast<unsigned>(tiles), 1),
+                           dim3(HUB_WAVE * waves), 0, st, a, a.gidx, a.tab, reinterpret_cast<T*>(a.hpsi));
+    }
     return hipGetLastError();
 }
 

@@ -8,16 +8,19 @@
 // reduction kernel.  Paper: the brackets of Eq. occ_matrices (Sec. II).
 //
 // Work mapping (gfx950, 64-wide waves): blockIdx.x = chunk, blockIdx.y =
-// tile of 64 lanes over the flattened (state set, column group) space, with
-// CG = ceil(ncol / CPL) groups per set.  Each lane owns CPL consecutive
-// columns of one set and reads them with 16- or 32-byte loads from the state
-// row of grid point g_e; when a set has fewer than 64*CPL columns one wave
-// covers several sets, so no lane idles and every load instruction moves a
-// full wave's worth of bytes.  Entry data (g, orbital values) is uniform across the wave and is
-// read through the scalar cache.  The waves of a work-group take interleaved
-// entries and are summed through LDS at the end.  Products and sums are FP64
-// for both storage precisions; for complex states the real orbital value
-// multiplies the real and imaginary parts separately (2 FMAs per column).
+// column tile.  Each lane owns CPL consecutive columns of one state set and
+// reads them with one or two vector loads from the state row of grid point
+// g_e.  Two lane layouts:
+//  * WIDE: every wave lies inside one state set (q is uniform), so a row
+//    address is a scalar base (set, grid point) plus a 32-bit lane offset;
+//  * packed: lanes tile the flattened (set, column group) space, so sets
+//    narrower than a wave share one (no idle lanes, per-lane addresses).
+// Entry data (g, orbital values) is uniform across the wave and comes
+// through scalar loads.  The waves of a work-group take interleaved entries
+// and are summed through LDS at the end; the unrolled main loop issues U row
+// loads back to back, a remainder loop takes the last entries.  Products and
+// sums are FP64 for both storage precisions; for complex states the real
+// orbital value multiplies the real and imaginary parts (2 FMAs per column).
 
 #include "kcommon.h"
 
@@ -28,10 +31,8 @@ struct ProjLds {
     double red[3][HUB_WAVE][NV];
 };
 
-template <typename T, int NV, int NF>
+template <typename T, int NV, int NF, bool WIDE>
 __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C, ProjLds<NV>& lds) {
-    constexpr int NC_MAX = 2;
-    (void)NC_MAX;
     constexpr int U = (NF > 9) ? 2 : ((NF > 5) ? 4 : 8);
     const int lane = threadIdx.x & (HUB_WAVE - 1);
     // wave index made provably uniform so entry data goes through scalar loads
@@ -40,14 +41,27 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     const int NC = a.ncplx;
     const int cpl = NV / NC;
     const int cg = (a.ncol + cpl - 1) / cpl;
-    const int t = blockIdx.y * HUB_WAVE + lane;
-    const bool active = t < a.nq * cg;
-    const int q = active ? t / cg : 0;
-    const int col0 = (t - (t / cg) * cg) * cpl;
 
+    int q, col0;
+    bool active;
+    if constexpr (WIDE) {
+        const int tps = (cg + HUB_WAVE - 1) / HUB_WAVE;          // tiles per set
+        q = blockIdx.y / tps;
+        col0 = ((blockIdx.y - q * tps) * HUB_WAVE + lane) * cpl;
+        active = col0 < a.ncol;
+    } else {
+        const int t = blockIdx.y * HUB_WAVE + lane;
+        active = t < a.nq * cg;
+        q = active ? t / cg : 0;
+        col0 = (t - (t / cg) * cg) * cpl;
+    }
+    // lanes past the last column or set read column 0 of their set (their
+    // sums are discarded), so every load is unconditional
+    const int colc = active ? col0 : 0;
     const T* __restrict__ psi_q = reinterpret_cast<const T*>(a.psi) + static_cast<int64_t>(q) * a.qstride;
     const int32_t* __restrict__ gi = a.gidx + C.e0;
     const double* __restrict__ tb = a.tab + C.phi0 * a.tabmult;
+    const int lofs = colc * NC;                                      // lane offset inside a row
 
     double acc[NF][NV];
 #pragma unroll
@@ -55,35 +69,38 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[f][v] = 0.0;
 
-    // Lanes past the last set read column 0 of set 0 (their sums are discarded)
-    // and entries past the end of the chunk re-read the first entry with a
-    // zero weight, so every load below is unconditional: no divergent branch
-    // separates the U loads, and all of them are in flight together.
-    const int colc = active ? col0 : 0;
-    for (int e = wave; e < C.ne; e += nw * U) {
+    // entries of this wave: wave, wave + nw, ...
+    const int nj = (C.ne - wave + nw - 1) / nw;
+    int j = 0;
+    for (; j + U <= nj; j += U) {
         T row[U][NV];
-        int ii[U];
-        double okf[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int idx = e + u * nw;
-            ii[u] = (idx < C.ne) ? idx : e;
-            okf[u] = (idx < C.ne) ? 1.0 : 0.0;
+            const int64_t g = gi[wave + (j + u) * nw];
+            load_row<T, NV>(psi_q + g * a.ld * NC + lofs, row[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t g = gi[ii[u]];
-            load_vec<T, NV>(psi_q + (g * a.ld + colc) * NC, row[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double* __restrict__ w = tb + static_cast<int64_t>(ii[u]) * NF;
+            const double* __restrict__ w = tb + static_cast<int64_t>(wave + (j + u) * nw) * NF;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const double wf = w[f] * okf[u];
+                const double wf = w[f];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) acc[f][v] = fma(wf, static_cast<double>(row[u][v]), acc[f][v]);
             }
+        }
+    }
+    for (; j < nj; ++j) {
+        T row[NV];
+        const int e = wave + j * nw;
+        const int64_t g = gi[e];
+        load_row<T, NV>(psi_q + g * a.ld * NC + lofs, row);
+        const double* __restrict__ w = tb + static_cast<int64_t>(e) * NF;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double wf = w[f];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[f][v] = fma(wf, static_cast<double>(row[v]), acc[f][v]);
         }
     }
 
@@ -118,25 +135,25 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 }
 
 // NV = scalars per lane (columns per lane times 1 or 2); GRAD selects the
-// gradient table (three functions per orbital).
-template <typename T, int NV, bool GRAD>
+// gradient table (three functions per orbital); WIDE the lane layout.
+template <typename T, int NV, bool GRAD, bool WIDE>
 __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
     __shared__ ProjLds<NV> lds;
     const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
     if constexpr (!GRAD) {
         switch (C.L) {
-        case 1: project_body<T, NV, 1>(a, C, lds); break;
-        case 3: project_body<T, NV, 3>(a, C, lds); break;
-        case 5: project_body<T, NV, 5>(a, C, lds); break;
-        case 7: project_body<T, NV, 7>(a, C, lds); break;
+        case 1: project_body<T, NV, 1, WIDE>(a, C, lds); break;
+        case 3: project_body<T, NV, 3, WIDE>(a, C, lds); break;
+        case 5: project_body<T, NV, 5, WIDE>(a, C, lds); break;
+        case 7: project_body<T, NV, 7, WIDE>(a, C, lds); break;
         default: break;
         }
     } else {
         switch (C.L) {
-        case 1: project_body<T, NV, 3>(a, C, lds); break;
-        case 3: project_body<T, NV, 9>(a, C, lds); break;
-        case 5: project_body<T, NV, 15>(a, C, lds); break;
-        case 7: project_body<T, NV, 21>(a, C, lds); break;
+        case 1: project_body<T, NV, 3, WIDE>(a, C, lds); break;
+        case 3: project_body<T, NV, 9, WIDE>(a, C, lds); break;
+        case 5: project_body<T, NV, 15, WIDE>(a, C, lds); break;
+        case 7: project_body<T, NV, 21, WIDE>(a, C, lds); break;
         default: break;
         }
     }
@@ -144,9 +161,16 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
 
 template <typename T, int NV, bool GRAD>
 hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
-    const int64_t groups = static_cast<int64_t>(nq) * ((a.ncol + cpl - 1) / cpl);
-    dim3 grid(nchunks, static_cast<unsigned>((groups + HUB_WAVE - 1) / HUB_WAVE), 1);
-    hipLaunchKernelGGL((k_project<T, NV, GRAD>), grid, dim3(HUB_WAVE * waves), 0, st, a);
+    const int64_t cg = (a.ncol + cpl - 1) / cpl;
+    if (a.wide) {
+        const int64_t tiles = static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE);
+        hipLaunchKernelGGL((k_project<T, NV, GRAD, true>), dim3(nchunks, static_cast<unsigned>(tiles), 1),
+                           dim3(HUB_WAVE * waves), 0, st, a);
+    } else {
+        const int64_t tiles = (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE;
+        hipLaunchKernelGGL((k_project<T, NV, GRAD, false>), dim3(nchunks, static_cast<unsigned>(tiles), 1),
+                           dim3(HUB_WAVE * waves), 0, st, a);
+    }
     return hipGetLastError();
 }
 

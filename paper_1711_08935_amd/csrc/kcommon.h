@@ -22,6 +22,7 @@ struct ProjArgs {
     const int32_t* gidx;
     const double* tab;        // orbital table (or gradient table)
     int tabmult;              // 1: phi, 3: grad phi
+    int wide;                 // 1: one state set per wave; 0: sets packed across lanes
     double* part;             // [nq][prows][ncol] (x2 complex)
     int64_t prows;            // rows per state set = part_rows * tabmult
 };
@@ -49,6 +50,7 @@ struct ApplyArgs {
     const double* ueff;       // [site]
     const double* colscale;   // [nq][nstates] or null
     double alpha;
+    int wide;                 // 1: one state set per wave; 0: sets packed across lanes
 };
 
 template <typename T, int N>
@@ -96,6 +98,49 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&v)[N]) {
     } else {
 #pragma unroll
         for (int i = 0; i < N; ++i) p[i] = v[i];
+    }
+}
+
+// State rows are streamed: each element is read (and, in the apply, written)
+// once per step, so the loads and stores carry the non-temporal hint when
+// HUB_STREAM_ROWS is set.
+#ifndef HUB_STREAM_ROWS
+#define HUB_STREAM_ROWS 0
+#endif
+
+typedef float hub_f4 __attribute__((ext_vector_type(4)));
+typedef double hub_d2 __attribute__((ext_vector_type(2)));
+
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[N]) {
+    if constexpr (HUB_STREAM_ROWS && sizeof(T) * N >= 16) {
+        constexpr int per = 16 / sizeof(T);
+        using V = typename std::conditional<sizeof(T) == 4, hub_f4, hub_d2>::type;
+#pragma unroll
+        for (int i = 0; i < N / per; ++i) {
+            const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(p + i * per));
+#pragma unroll
+            for (int k = 0; k < per; ++k) v[i * per + k] = t[k];
+        }
+    } else {
+        load_vec<T, N>(p, v);
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[N]) {
+    if constexpr (HUB_STREAM_ROWS && sizeof(T) * N >= 16) {
+        constexpr int per = 16 / sizeof(T);
+        using V = typename std::conditional<sizeof(T) == 4, hub_f4, hub_d2>::type;
+#pragma unroll
+        for (int i = 0; i < N / per; ++i) {
+            V t;
+#pragma unroll
+            for (int k = 0; k < per; ++k) t[k] = v[i * per + k];
+            __builtin_nontemporal_store(t, reinterpret_cast<V*>(p + i * per));
+        }
+    } else {
+        store_vec<T, N>(p, v);
     }
 }
 

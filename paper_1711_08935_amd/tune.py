@@ -1,7 +1,8 @@
 """Autotuner for the kernel shapes of the projection and apply kernels.
 
 For a given context and state layout it times every candidate shape
-(columns per lane x waves per work-group) with the library's per-stage HIP
+(columns per lane x waves per work-group x lane layout: one state set
+per wave, or narrow sets packed across the lanes) with the library's per-stage HIP
 event profiler on the caller's own buffers, and keeps the fastest for each
 kernel (``hub_set_tuning``).  Results depend only on timing, never on values:
 every shape computes the same sums (the GPU tests check this).
@@ -9,7 +10,7 @@ every shape computes the same sums (the GPU tests check this).
 
 import torch
 
-CANDIDATES = ((1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4))
+CANDIDATES = tuple((cpl, waves, layout) for layout in (0, 1) for cpl in (1, 2, 4) for waves in (1, 2, 4))
 
 
 def autotune(hub, psi, c, n, ueff, reps=5, candidates=CANDIDATES):
@@ -17,15 +18,15 @@ def autotune(hub, psi, c, n, ueff, reps=5, candidates=CANDIDATES):
 
     psi: the states the step will read; c, n, ueff: device buffers of the
     right shape (their values do not matter).  Returns
-    {"project": ((cpl, waves), ms), "apply": (...), "table": {...}}.
+    {"project": ((cpl, waves, layout), ms), "apply": (...), "table": {...}}.
     """
     scratch = torch.zeros_like(psi)
     table = {}
     best = {}
     for which, name in ((0, "project"), (1, "apply")):
         timings = {}
-        for cpl, waves in candidates:
-            hub.set_tuning(which, cpl, waves)
+        for cpl, waves, layout in candidates:
+            hub.set_tuning(which, cpl, waves, layout)
             # one untimed call compiles nothing but warms caches and sizes buffers
             if which == 0:
                 hub.project(psi, out=c)
@@ -40,11 +41,11 @@ def autotune(hub, psi, c, n, ueff, reps=5, candidates=CANDIDATES):
             prof = hub.profile_read()
             hub.profile(False)
             ms, cnt = prof[name]
-            timings[(cpl, waves)] = ms / max(cnt, 1)
+            timings[(cpl, waves, layout)] = ms / max(cnt, 1)
         shape = min(timings, key=timings.get)
         hub.set_tuning(which, *shape)
         best[name] = (shape, timings[shape])
-        table[name] = {f"{k[0]}x{k[1]}": round(v, 4) for k, v in timings.items()}
+        table[name] = {f"{k[0]}x{k[1]}{'w' if k[2] else 'p'}": round(v, 4) for k, v in timings.items()}
     torch.cuda.synchronize()
     best["table"] = table
     return best

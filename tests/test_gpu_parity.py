@@ -168,22 +168,23 @@ def test_autograd_energy_gradients(case):
 
 
 def test_tuning_variants_agree(case):
-    """Every kernel shape (columns per lane x waves per work-group) gives the
+    """Every kernel shape (columns per lane x waves per work-group x lane
+    layout) gives the
     same projections and V_U psi up to summation order."""
     hub = case["hub"]
     psi_d = case["psi_d"]
     try:
-        for cpl in (1, 2, 4):
-            for waves in (1, 2, 4):
-                hub.set_tuning(0, cpl, waves)
-                hub.set_tuning(1, cpl, waves)
+        for cpl, waves, layout in [(c, w, s) for s in (0, 1) for c in (1, 2, 4) for w in (1, 2, 4)]:
+            if True:
+                hub.set_tuning(0, cpl, waves, layout)
+                hub.set_tuning(1, cpl, waves, layout)
                 c = hub.project(psi_d)
                 h = torch.zeros_like(psi_d)
                 hub.apply(case["Ueff"], case["n"], case["c"], h)
                 torch.cuda.synchronize()
-                assert normwise(c.cpu().numpy(), case["c"].cpu().numpy()) < 1e-13, (cpl, waves)
+                assert normwise(c.cpu().numpy(), case["c"].cpu().numpy()) < 1e-13, (cpl, waves, layout)
                 bar = 1e-13 if case["prec"] == "f64" else 1e-7
-                assert normwise(h.cpu().numpy(), case["hpsi"].cpu().numpy()) < bar, (cpl, waves)
+                assert normwise(h.cpu().numpy(), case["hpsi"].cpu().numpy()) < bar, (cpl, waves, layout)
     finally:
-        hub.set_tuning(0, 0, 4)
-        hub.set_tuning(1, 0, 4)
+        hub.set_tuning(0, 0, 4, -1)
+        hub.set_tuning(1, 0, 4, -1)
