@@ -1,0 +1,110 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (default chunking, kernel shapes picked by the autotuner, the step run
+as a hipGraph).  The oracle runs on the states the device holds (the FP32
+storage rounded states, upcast).  Where the oracle can compute every output
+in seconds it does (NiO-like workload: all projections, matrices, U, J and
+V_U psi; forces workload: all forces); for the 1024-state batched workload it
+checks every projection and matrix and V_U psi on sampled state columns.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import forces as OF  # noqa: E402
+from oracle import occupations as OO  # noqa: E402
+from oracle import potential as OPOT  # noqa: E402
+from oracle import projection as OP  # noqa: E402
+from oracle import step as OS  # noqa: E402
+from paper_1711_08935_amd.tune import autotune  # noqa: E402
+from synth import make_config, make_occupations, make_states  # noqa: E402
+from tests.gpu_common import c_to_oracle, make_hub, n_site  # noqa: E402
+from tests.helpers import normwise, to_system  # noqa: E402
+
+
+def _setup(name, prec):
+    print(f"\n[fullsize] {name} {prec}", flush=True)
+    cfg = make_config(name)
+    psi64 = make_states(cfg, device="cuda")
+    f = make_occupations(cfg)
+    f_d = torch.from_numpy(f).cuda()
+    hub = make_hub(cfg, prec)
+    psi = psi64.to(hub.state_dtype)
+    del psi64
+    hub.coulomb(-1)
+    bufs = hub.step_buffers(cfg.nstates)
+    hpsi = torch.zeros_like(psi)
+    hub.step(psi, f_d, hpsi, mode="batched", bufs=bufs)
+    autotune(hub, psi, bufs["c"], bufs["n"], bufs["Ueff"], reps=2)
+    hpsi.zero_()
+    hub.step(psi, f_d, hpsi, mode="graph", bufs=bufs)
+    torch.cuda.synchronize()
+    return cfg, hub, psi, f, f_d, bufs, hpsi
+
+
+def _compare_matrices(hub, bufs, ref):
+    for I in range(hub.nsites):
+        L = hub.site_L[I]
+        assert normwise(n_site(hub, bufs["n"], I, L), ref["n"][I]) < 1e-12, I
+        assert normwise(n_site(hub, bufs["pbar"], I, L), ref["pbar"][I]) < 1e-12, I
+    assert normwise(bufs["nbar"].cpu().numpy(), ref["nbar"]) < 1e-12
+    U, J = bufs["U"].cpu().numpy(), bufs["J"].cpu().numpy()
+    assert np.max(np.abs(U - ref["U"])) <= 1e-12 * max(1e-3, np.abs(ref["U"]).max())
+    assert np.max(np.abs(J - ref["J"])) <= 1e-12 * max(1e-3, np.abs(ref["J"]).max())
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_nio_full_size_every_output(prec):
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("nio_afm", prec)
+    used = psi.cpu().numpy().astype(np.complex128)
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    ref = OS.hubbard_step(sys_, used, f, sps, OS.site_tensors(sys_, sps), form="sphere")
+    assert normwise(c_to_oracle(hub, bufs["c"]), ref["c"]) < 1e-12
+    _compare_matrices(hub, bufs, ref)
+    bar = 1e-12 if prec == "f64" else 2e-7
+    assert normwise(hpsi.cpu().numpy(), ref["hpsi"]) < bar
+
+
+@pytest.mark.timeout(900)
+def test_rt_batched_full_size_sampled():
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("rt_batched", "f32")
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    used = psi[0].cpu().numpy().astype(np.float64)[None]            # 1.7M x 1024 FP64 on the host
+    c_ref = OP.project_sphere(sys_, used, sps).real
+    assert normwise(bufs["c"].cpu().numpy(), c_ref) < 1e-12
+    n, pbar, nb = OO.occupations(sys_, c_ref, f)
+    tens = OS.site_tensors(sys_, sps)
+    ref = dict(n=n, pbar=pbar, nbar=nb, U=np.zeros(len(sps)), J=np.zeros(len(sps)))
+    from oracle import acbn0
+    for I in range(len(sps)):
+        U, J, _, _ = acbn0.uj_collinear(OO.channels(sys_, n[I]), OO.channels(sys_, pbar[I]), tens[I])
+        ref["U"][I], ref["J"][I] = U, J
+    _compare_matrices(hub, bufs, ref)
+    cols = np.random.default_rng(0).choice(cfg.nstates, size=8, replace=False)
+    V = [OPOT.potential_matrix(sys_, ref["U"][I] - ref["J"][I], n[I]) for I in range(len(sps))]
+    h_ref = OS.apply_sphere(sys_, c_ref[:, :, cols], V, sps).real
+    h = hpsi[0][:, torch.from_numpy(cols).cuda()].cpu().numpy()[None]
+    assert normwise(h, h_ref) < 2e-7
+
+
+@pytest.mark.timeout(900)
+def test_forces_full_size():
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("forces_fcc", "f32")
+    F = hub.forces(psi, bufs["c"], f_d, bufs["Ueff"], bufs["n"]).cpu().numpy()
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    used = psi.cpu().numpy().astype(np.float64)
+    c = OP.project_sphere(sys_, used, sps)
+    n, _, _ = OO.occupations(sys_, c, f, with_pbar=False)
+    ueff = bufs["Ueff"].cpu().numpy()
+    V = [OPOT.potential_matrix(sys_, ueff[I], n[I]) for I in range(len(sps))]
+    Fo = OF.forces_analytic(sys_, c, OF.gradient_projections(sys_, used, sps), V, f)
+    assert normwise(F, Fo) < 1e-11
