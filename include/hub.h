@@ -119,6 +119,17 @@ int hub_set_chunk(hub_ctx* ctx, int chunk_entries);
  * creation. */
 int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves, int layout);
 
+/* Work list of the batched launches (hub_project, hub_apply, and hub_step
+ * in the batched and graph modes): grouped_list = 1 (default) groups every
+ * grid point covered by any sphere with all its (site, lattice image) covers,
+ * so each state row is read once by the projection and written once by the
+ * apply; 0 uses one chunk per site and image, with overlapping sites applied
+ * in successive atomic-free layers.  The grouped list exists only when no grid
+ * point is covered by more than 16 orbitals in total; otherwise the per-site
+ * list is used.  Both give the same results up to summation order.  Any
+ * time. */
+int hub_set_worklist(hub_ctx* ctx, int grouped_list);
+
 /* Build the sphere maps, orbital tables (grid-normalized, dV sum phi^2 = 1,
  * Sec. II), image/phase tables and the work list on the host.  Needs no GPU.
  * Errors: HUB_EINVAL (no sites, or a sphere that holds no grid point),
@@ -136,7 +147,9 @@ int hub_set_stream(hub_ctx* ctx, void* stream);
 /* Integer properties after hub_finalize_host: what = 0 sites, 1 orbitals J,
  * 2 state sets (nq; spinor: nk), 3 apply layers, 4 sphere entries, 5 chunks,
  * 6 species, 7 k-points, 8 nblk of n/pbar, 9 bytes of device tables,
- * 10 projection workspace rows (sum of L over chunks). */
+ * 10 projection workspace rows (sum of L over chunks), 11 grouped chunks
+ * (0 when the grouped work list was not built), 12 largest number of
+ * orbitals covering one grid point. */
 int hub_query(const hub_ctx* ctx, int what, int64_t* value);
 
 /* Per-site data after hub_finalize_host: L = 2l+1, offset of its first

@@ -43,7 +43,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_set_tuning", "hub_finalize_host", "hub_finalize", "hub_set_stream", "hub_query",
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
-           "hub_strerror", "hub_profile", "hub_profile_read"]
+           "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -82,6 +82,7 @@ def lib():
         "hub_strerror": [I],
         "hub_profile": [P, I],
         "hub_profile_read": [P, P, P],
+        "hub_set_worklist": [P, I],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -151,6 +152,8 @@ class Hubbard:
         self.nspecies = self.query(6)
         self.nk = self.query(7)
         self.nblk = self.query(8)
+        self.ngrouped = self.query(11)
+        self.nfmax = self.query(12)
         self.site_L, self.site_orb0, self.site_npts, self.site_species = [], [], [], []
         for s in range(self.nsites):
             Lm, o, npts, sp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
@@ -198,6 +201,11 @@ class Hubbard:
 
     def set_fixed_ueff(self, site, ueff):
         _check(lib().hub_set_fixed_ueff(self._ctx, int(site), float(ueff)), "hub_set_fixed_ueff")
+
+    def set_worklist(self, grouped=True):
+        """Batched launches over the grouped (cover-signature) work list, or
+        over per-site chunks applied in layers."""
+        _check(lib().hub_set_worklist(self._ctx, int(bool(grouped))), "hub_set_worklist")
 
     def set_tuning(self, which, cols_per_lane, waves, layout=-1):
         """Kernel shape of the projection (which=0) or apply (1); layout 1 =

@@ -55,6 +55,12 @@ struct hub_ctx {
     int32_t *d_site_L = nullptr, *d_site_orb0 = nullptr, *d_site_species = nullptr;
     int32_t *d_species_orb_ptr = nullptr, *d_species_orb_ids = nullptr;
     double *d_kw = nullptr, *d_ueff_fixed = nullptr, *d_tensor = nullptr;
+    // grouped (cover-signature) work list
+    bool use_grouped = true;
+    HubChunk* d_gchunks = nullptr;
+    int32_t *d_gall = nullptr, *d_ggidx = nullptr, *d_gf_orb = nullptr, *d_gf_img = nullptr;
+    int32_t *d_gred_ptr = nullptr, *d_gred_row = nullptr, *d_gred_img = nullptr;
+    double* d_gtab = nullptr;
     std::vector<char> have_tensor;
     size_t table_bytes = 0;
 
@@ -118,6 +124,8 @@ void release(hub_ctx* c) {
     f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
     f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws);
+    f(c->d_gchunks); f(c->d_gall); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
+    f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -208,6 +216,16 @@ int pick_wide(const hub_ctx* c, int ncol, int cpl, int which) {
 
 bool built(const hub_ctx* c) { return c && c->built_dev; }
 
+// Batched launches use the grouped work list when it exists.
+bool grouped(const hub_ctx* c) { return c->use_grouped && c->T.grouped.ok; }
+
+// Columns per lane so that a lane's FP64 accumulators (functions x scalars)
+// stay within 96 values.
+int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
+    while (cpl > 1 && nf * cpl * c->ncplx() > 96) cpl /= 2;
+    return cpl;
+}
+
 ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad) {
     ProjArgs a{};
     a.psi = psi;
@@ -248,14 +266,51 @@ ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
 }
 
 // project + reduce into c (per_site: one projection launch per site)
+size_t part_need(const hub_ctx* c, int ncol, int mult) {
+    const int64_t rows = std::max<int64_t>(c->T.part_rows * mult, c->T.grouped.ok ? c->T.grouped.part_rows : 0);
+    return static_cast<size_t>(c->nsets()) * rows * ncol * c->ncplx();
+}
+
 int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site, bool grad) {
     const int ncol = c->ncol(nstates);
     const int mult = grad ? 3 : 1;
-    const size_t need = static_cast<size_t>(c->nsets()) * c->T.part_rows * mult * ncol * c->ncplx();
-    int st = ensure(&c->d_part, &c->part_cap, need, c);
+    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, mult), c);
     if (st) return st;
     ProjArgs a = proj_args(c, psi, ld, ncol, grad);
     a.part = c->d_part;
+    if (!per_site && !grad && grouped(c)) {
+        const GroupTables& GT = c->T.grouped;
+        a.chunks = c->d_gchunks;
+        a.chunk_list = c->d_gall;
+        a.gidx = c->d_ggidx;
+        a.tab = c->d_gtab;
+        a.prows = GT.part_rows;
+        const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), GT.nfmax);
+        a.wide = pick_wide(c, ncol, cpl, 0);
+        {
+            StageTimer tm(c, HUB_STAGE_PROJECT);
+            HUB_TRY(launch_project(a, static_cast<int>(GT.chunks.size()), c->nsets(), c->precision, c->is_complex, cpl,
+                                   c->tune_waves[0], c->stream));
+        }
+        ReduceGroupedArgs r{};
+        r.part = c->d_part;
+        r.prows = GT.part_rows;
+        r.out = out;
+        r.J = c->T.J;
+        r.ncol = ncol;
+        r.ncplx = c->ncplx();
+        r.red_ptr = c->d_gred_ptr;
+        r.red_row = c->d_gred_row;
+        r.red_img = c->d_gred_img;
+        r.phase = c->d_phase;
+        r.nimg = static_cast<int>(c->T.images.size() / 3);
+        r.nspin = c->nspin();
+        r.spinor = c->spin_mode == HUB_SPINOR;
+        r.dV = (c->cell[0] / c->ngrid[0]) * (c->cell[1] / c->ngrid[1]) * (c->cell[2] / c->ngrid[2]);
+        StageTimer tm(c, HUB_STAGE_REDUCE);
+        HUB_TRY(launch_reduce_grouped(r, c->nsets(), c->stream));
+        return HUB_OK;
+    }
     int cpl = pick_cpl(c, psi, ld, 0);
     if (grad && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();     // gradient tiles hold 3L functions
     a.wide = pick_wide(c, ncol, cpl, 0);
@@ -384,6 +439,24 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.ueff = Ueff;
     a.colscale = colscale;
     a.alpha = alpha;
+    a.orb_site = c->d_orb_site;
+    a.site_orb0 = c->d_site_orb0;
+    a.site_L = c->d_site_L;
+    if (!per_site && grouped(c)) {
+        const GroupTables& GT = c->T.grouped;
+        const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), GT.nfmax);
+        a.wide = 1;
+        a.chunks = c->d_gchunks;
+        a.chunk_list = c->d_gall;
+        a.gidx = c->d_ggidx;
+        a.tab = c->d_gtab;
+        a.f_orb = c->d_gf_orb;
+        a.f_img = c->d_gf_img;
+        StageTimer tm(c, HUB_STAGE_APPLY);
+        HUB_TRY(launch_apply_grouped(a, static_cast<int>(GT.chunks.size()), c->nsets(), c->precision, c->is_complex,
+                                     cpl, c->tune_waves[1], c->stream));
+        return HUB_OK;
+    }
     const int cpl = pick_cpl(c, hpsi, ld, 1);
     a.wide = pick_wide(c, ncol, cpl, 1);
     const int waves = c->tune_waves[1];
@@ -521,6 +594,13 @@ int hub_set_chunk(hub_ctx* c, int chunk_entries) {
     return HUB_OK;
 }
 
+int hub_set_worklist(hub_ctx* c, int grouped_list) {
+    if (!c || (grouped_list != 0 && grouped_list != 1)) return HUB_EINVAL;
+    c->use_grouped = grouped_list == 1;
+    drop_graph(c);
+    return HUB_OK;
+}
+
 int hub_set_tuning(hub_ctx* c, int which, int cpl, int waves, int layout) {
     if (!c || (which != 0 && which != 1)) return HUB_EINVAL;
     if (cpl != 0 && cpl != 1 && cpl != 2 && cpl != 4) return HUB_EINVAL;
@@ -595,6 +675,19 @@ int hub_finalize(hub_ctx* c, void* stream) {
     up(&c->d_species_orb_ids, T.species_orb_ids);
     up(&c->d_kw, c->kw);
     up(&c->d_ueff_fixed, fixed);
+    if (T.grouped.ok) {
+        std::vector<int32_t> gall(T.grouped.chunks.size());
+        for (size_t i = 0; i < gall.size(); ++i) gall[i] = static_cast<int32_t>(i);
+        up(&c->d_gchunks, T.grouped.chunks);
+        up(&c->d_gall, gall);
+        up(&c->d_ggidx, T.grouped.gidx);
+        up(&c->d_gtab, T.grouped.tab);
+        up(&c->d_gf_orb, T.grouped.f_orb);
+        up(&c->d_gf_img, T.grouped.f_img);
+        up(&c->d_gred_ptr, T.grouped.red_ptr);
+        up(&c->d_gred_row, T.grouped.red_row);
+        up(&c->d_gred_img, T.grouped.red_img);
+    }
     if (e == hipSuccess) {
         e = hipMalloc(reinterpret_cast<void**>(&c->d_tensor), c->sites.size() * 2401 * sizeof(double));
         b += c->sites.size() * 2401 * sizeof(double);
@@ -630,6 +723,8 @@ int hub_query(const hub_ctx* c, int what, int64_t* v) {
     case 8: *v = c->nblk(); break;
     case 9: *v = static_cast<int64_t>(c->table_bytes); break;
     case 10: *v = T.part_rows; break;
+    case 11: *v = T.grouped.ok ? static_cast<int64_t>(T.grouped.chunks.size()) : 0; break;
+    case 12: *v = T.grouped.nfmax; break;
     default: return HUB_EINVAL;
     }
     return HUB_OK;
@@ -801,8 +896,7 @@ int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
     // the step needs the projection workspace and the N-bar buffer; size them
     // before any capture so that the graph never sees a reallocation
     const int ncol = c->ncol(io->nstates);
-    int st = ensure(&c->d_part, &c->part_cap,
-                    static_cast<size_t>(c->nsets()) * c->T.part_rows * ncol * c->ncplx(), c);
+    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, 1), c);
     if (st) return st;
     if (!io->nbar) {
         st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);

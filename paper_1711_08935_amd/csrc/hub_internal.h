@@ -43,6 +43,29 @@ struct SiteSphere {
     std::vector<double> grad;    // [p][m][3]
 };
 
+// Largest number of functions (orbitals of all covering sites) a grouped
+// chunk may carry; beyond it the grouped work list is not built and the
+// layered per-site work list serves every launch.
+#define HUB_GF_MAX 16
+
+// Work list grouped by cover signature: every grid point covered by any
+// sphere appears in exactly one grouped chunk, together with all its
+// (site, image) covers in a fixed slot order, so the projection reads each
+// state row once and the apply writes it once (no layers).  The chunk's
+// functions are the concatenated orbitals of its slots.
+struct GroupTables {
+    bool ok = false;
+    int nfmax = 0;
+    std::vector<HubChunk> chunks;            // L = number of functions, e0/ne over points
+    std::vector<int32_t> gidx;               // per point
+    std::vector<double> tab;                 // per point, L values (slot-major)
+    std::vector<int32_t> f_orb;              // per chunk HUB_GF_MAX: global orbital j of function f
+    std::vector<int32_t> f_img;              // per chunk HUB_GF_MAX: lattice image of function f
+    std::vector<int32_t> red_ptr;            // CSR orbital j -> workspace rows
+    std::vector<int32_t> red_row, red_img;
+    int64_t part_rows = 0;
+};
+
 struct HostTables {
     int nsites = 0, J = 0, nlayers = 0, nspecies = 0;
     std::vector<int32_t> site_L, site_orb0, site_species;
@@ -61,6 +84,7 @@ struct HostTables {
     int64_t part_rows = 0;                   // sum of L over chunks
     int64_t nentries = 0;
     std::vector<SiteSphere> spheres;
+    GroupTables grouped;
 };
 
 // Host builder (sphere.cpp).  Returns HUB_OK or a negative status.

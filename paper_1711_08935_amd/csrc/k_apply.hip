@@ -114,7 +114,92 @@ __device__ __forceinline__ void coefficients(const ApplyArgs& a, const HubChunk&
     }
 }
 
-template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE>
+// Coefficients of a grouped chunk: function f is orbital a of site s(f)
+// seen through lattice image img(f); B_f = alpha scale exp(-i k.T_img(f))
+// sum_b V^{s(f)}_{a b} c_{s(f), b} (spinor: with the spin blocks).
+template <bool CPX, bool SPINOR, int CPL, int NF>
+__device__ __forceinline__ void coefficients_grouped(const ApplyArgs& a, int chunk, int q, int col0,
+                                                     double (&B)[NF][CPL * (CPX ? 2 : 1)]) {
+    constexpr int NC = CPX ? 2 : 1;
+    const int ch = SPINOR ? 0 : (q % a.nspin);
+    const int k = a.spinor ? q : q / a.nspin;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int j = a.f_orb[chunk * HUB_GF_MAX + f];
+        const int img = a.f_img[chunk * HUB_GF_MAX + f];
+        const int site = a.orb_site[j];
+        const int o0 = a.site_orb0[site];
+        const int L = a.site_L[site];
+        const int ai = j - o0;
+        const double U = a.ueff[site];
+        const double* __restrict__ nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
+        const double* __restrict__ cq = a.c + (static_cast<int64_t>(q) * a.J + o0) * a.ncol * NC;
+        double pr = 1.0, pi = 0.0;
+        if constexpr (CPX) {
+            pr = a.phase[(static_cast<int64_t>(k) * a.nimg + img) * 2];
+            pi = -a.phase[(static_cast<int64_t>(k) * a.nimg + img) * 2 + 1];
+        }
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+            const int col = col0 + cc;
+            const bool ok = col < a.ncol;
+            double sc = a.alpha;
+            if (a.colscale != nullptr && ok) {
+                const int s = SPINOR ? (col >> 1) : col;
+                sc *= a.colscale[static_cast<int64_t>(q) * a.nstates + s];
+            }
+            if (!ok) sc = 0.0;
+            const int colc = ok ? col : 0;
+            double br = 0.0, bi = 0.0;
+            if constexpr (!SPINOR) {
+                const double* __restrict__ nm = nb + ch * 98;
+#pragma unroll 1
+                for (int b = 0; b < 7; ++b) {
+                    if (b < L) {
+                        const double vr = U * ((ai == b ? 0.5 : 0.0) - nm[(b * 7 + ai) * 2]);
+                        const double cr = cq[(static_cast<int64_t>(b) * a.ncol + colc) * NC];
+                        if constexpr (CPX) {
+                            const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
+                            const double ci = cq[(static_cast<int64_t>(b) * a.ncol + colc) * NC + 1];
+                            br = fma(vr, cr, fma(-vi, ci, br));
+                            bi = fma(vr, ci, fma(vi, cr, bi));
+                        } else {
+                            br = fma(vr, cr, br);
+                        }
+                    }
+                }
+            } else {
+                const int sg = colc & 1;
+                const int base = colc - sg;
+#pragma unroll 1
+                for (int t = 0; t < 2; ++t) {
+                    const double* __restrict__ nm = nb + (2 * t + sg) * 98;
+#pragma unroll 1
+                    for (int b = 0; b < 7; ++b) {
+                        if (b < L) {
+                            const double vr = U * ((ai == b && t == sg) ? 0.5 : 0.0) - U * nm[(b * 7 + ai) * 2];
+                            const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
+                            const double cr = cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2];
+                            const double ci = cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2 + 1];
+                            br = fma(vr, cr, fma(-vi, ci, br));
+                            bi = fma(vr, ci, fma(vi, cr, bi));
+                        }
+                    }
+                }
+            }
+            br *= sc;
+            bi *= sc;
+            if constexpr (CPX) {
+                B[f][2 * cc] = pr * br - pi * bi;
+                B[f][2 * cc + 1] = pr * bi + pi * br;
+            } else {
+                B[f][cc] = br;
+            }
+        }
+    }
+}
+
+template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE, bool GROUPED = false>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C, const int32_t* __restrict__ gidx,
                                            const double* __restrict__ tab, T* __restrict__ hpsi) {
     constexpr int NC = CPX ? 2 : 1;
@@ -139,7 +224,10 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     }
 
     double B[L][NV];
-    coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
+    if constexpr (GROUPED)
+        coefficients_grouped<CPX, SPINOR, CPL, L>(a, a.chunk_list[blockIdx.x], q, col0, B);
+    else
+        coefficients<CPX, SPINOR, CPL, L>(a, C, q, col0, B);
 
     T* __restrict__ h_q = hpsi + static_cast<int64_t>(q) * a.qstride;
     const int32_t* __restrict__ gi = gidx + C.e0;
@@ -212,6 +300,48 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t*
     }
 }
 
+// Grouped chunks: L is the number of concatenated functions of the chunk's
+// covering sites; every grid point lies in one chunk, so one launch writes
+// every point once.
+template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE>
+__global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const int32_t* __restrict__ gidx,
+                                                       const double* __restrict__ tab, T* __restrict__ hpsi) {
+    const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
+    constexpr int NV = CPL * (CPX ? 2 : 1);
+#define HUB_ACASE(n)                                                                              \
+    case n:                                                                                       \
+        if constexpr (n * NV <= 96) apply_body<T, CPX, SPINOR, CPL, n, WIDE, true>(a, C, gidx, tab, hpsi); \
+        break;
+    switch (C.L) {
+        HUB_ACASE(1) HUB_ACASE(2) HUB_ACASE(3) HUB_ACASE(4) HUB_ACASE(5) HUB_ACASE(6) HUB_ACASE(7)
+        HUB_ACASE(8) HUB_ACASE(9) HUB_ACASE(10) HUB_ACASE(11) HUB_ACASE(12) HUB_ACASE(13)
+        HUB_ACASE(14) HUB_ACASE(15) HUB_ACASE(16)
+    default: break;
+    }
+#undef HUB_ACASE
+}
+
+// The grouped apply is built in the one-set-per-wave layout only (uniform
+// potential matrices; the packed layout never won the autotuner here).
+template <typename T, bool CPX, bool SPINOR, int CPL>
+hipError_t launch_tg(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
+    const int64_t cg = (a.ncol + CPL - 1) / CPL;
+    const int64_t tiles = static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE);
+    hipLaunchKernelGGL((k_apply_grouped<T, CPX, SPINOR, CPL, true>), dim3(nchunks, static_cast<unsigned>(tiles), 1),
+                       dim3(HUB_WAVE * waves), 0, st, a, a.gidx, a.tab, reinterpret_cast<T*>(a.hpsi));
+    return hipGetLastError();
+}
+
+template <typename T, bool CPX, bool SPINOR>
+hipError_t launch_cg(const ApplyArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
+    switch (cpl) {
+    case 1: return launch_tg<T, CPX, SPINOR, 1>(a, nchunks, nq, waves, st);
+    case 2: return launch_tg<T, CPX, SPINOR, 2>(a, nchunks, nq, waves, st);
+    case 4: return launch_tg<T, CPX, SPINOR, 4>(a, nchunks, nq, waves, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, bool CPX, bool SPINOR, int CPL>
 hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
     const int64_t cg = (a.ncol + CPL - 1) / CPL;
@@ -250,4 +380,17 @@ hipError_t launch_apply(const ApplyArgs& a, int nchunks, int nq, int prec, int c
     if (a.spinor) return launch_c<float, true, true>(a, nchunks, nq, cpl, waves, st);
     return cplx ? launch_c<float, true, false>(a, nchunks, nq, cpl, waves, st)
                 : launch_c<float, false, false>(a, nchunks, nq, cpl, waves, st);
+}
+
+hipError_t launch_apply_grouped(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                                hipStream_t st) {
+    if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    if (prec == HUB_F64) {
+        if (a.spinor) return launch_cg<double, true, true>(a, nchunks, nq, cpl, waves, st);
+        return cplx ? launch_cg<double, true, false>(a, nchunks, nq, cpl, waves, st)
+                    : launch_cg<double, false, false>(a, nchunks, nq, cpl, waves, st);
+    }
+    if (a.spinor) return launch_cg<float, true, true>(a, nchunks, nq, cpl, waves, st);
+    return cplx ? launch_cg<float, true, false>(a, nchunks, nq, cpl, waves, st)
+                : launch_cg<float, false, false>(a, nchunks, nq, cpl, waves, st);
 }

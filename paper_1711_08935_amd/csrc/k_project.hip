@@ -141,13 +141,19 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
     __shared__ ProjLds<NV> lds;
     const HubChunk C = a.chunks[a.chunk_list[blockIdx.x]];
     if constexpr (!GRAD) {
+        // per-site chunks carry L in {1,3,5,7}; grouped chunks carry the
+        // concatenated orbitals of their covering sites (up to HUB_GF_MAX)
+#define HUB_PCASE(n)                                                  \
+    case n:                                                           \
+        if constexpr (n * NV <= 96) project_body<T, NV, n, WIDE>(a, C, lds); \
+        break;
         switch (C.L) {
-        case 1: project_body<T, NV, 1, WIDE>(a, C, lds); break;
-        case 3: project_body<T, NV, 3, WIDE>(a, C, lds); break;
-        case 5: project_body<T, NV, 5, WIDE>(a, C, lds); break;
-        case 7: project_body<T, NV, 7, WIDE>(a, C, lds); break;
+            HUB_PCASE(1) HUB_PCASE(2) HUB_PCASE(3) HUB_PCASE(4) HUB_PCASE(5) HUB_PCASE(6) HUB_PCASE(7)
+            HUB_PCASE(8) HUB_PCASE(9) HUB_PCASE(10) HUB_PCASE(11) HUB_PCASE(12) HUB_PCASE(13)
+            HUB_PCASE(14) HUB_PCASE(15) HUB_PCASE(16)
         default: break;
         }
+#undef HUB_PCASE
     } else {
         switch (C.L) {
         case 1: project_body<T, NV, 3, WIDE>(a, C, lds); break;

@@ -42,6 +42,51 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
     if (NC == 2) o[1] = a.dV * s1;
 }
 
+// Grouped work list: out[q][j][col] = dV sum over the workspace rows that
+// belong to orbital j of exp(+i k.T_row) part[q][row][col].  Independent
+// partial sums keep several loads in flight.
+__global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs a) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int q = blockIdx.z;
+    if (col >= a.ncol) return;
+    const int NC = a.ncplx;
+    const int k = a.spinor ? q : q / a.nspin;
+    const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
+    const double* base = a.part + static_cast<int64_t>(q) * a.prows * a.ncol * NC + static_cast<int64_t>(col) * NC;
+    double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
+    const int t0 = a.red_ptr[j], t1 = a.red_ptr[j + 1];
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double* p = base + static_cast<int64_t>(a.red_row[t + u]) * a.ncol * NC;
+            if (NC == 2) {
+                const int im = a.red_img[t + u];
+                const double pr = ph[2 * im], pi = ph[2 * im + 1];
+                s0[u] += pr * p[0] - pi * p[1];
+                s1[u] += pr * p[1] + pi * p[0];
+            } else {
+                s0[u] += p[0];
+            }
+        }
+    }
+    for (; t < t1; ++t) {
+        const double* p = base + static_cast<int64_t>(a.red_row[t]) * a.ncol * NC;
+        if (NC == 2) {
+            const int im = a.red_img[t];
+            const double pr = ph[2 * im], pi = ph[2 * im + 1];
+            s0[0] += pr * p[0] - pi * p[1];
+            s1[0] += pr * p[1] + pi * p[0];
+        } else {
+            s0[0] += p[0];
+        }
+    }
+    double* o = a.out + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + col) * NC;
+    o[0] = a.dV * ((s0[0] + s0[1]) + (s0[2] + s0[3]));
+    if (NC == 2) o[1] = a.dV * ((s1[0] + s1[1]) + (s1[2] + s1[3]));
+}
+
 // ---------------------------------------------------------------- N-bar
 // nbar[q][T][s] = sum_{j in species T} sum_{columns of s} |c[q][j][col]|^2
 __global__ void __launch_bounds__(256) k_nbar(const NbarArgs a) {
@@ -394,6 +439,13 @@ hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st) {
     if (a.nrows <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
     dim3 grid((a.ncol + 255) / 256, a.nrows, nq);
     hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t st) {
+    if (a.J <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    dim3 grid((a.ncol + 255) / 256, a.J, nq);
+    hipLaunchKernelGGL(k_reduce_grouped, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

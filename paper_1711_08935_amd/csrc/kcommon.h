@@ -51,6 +51,12 @@ struct ApplyArgs {
     const double* colscale;   // [nq][nstates] or null
     double alpha;
     int wide;                 // 1: one state set per wave; 0: sets packed across lanes
+    // grouped chunks: per chunk HUB_GF_MAX (orbital j, image) pairs
+    const int32_t* f_orb;
+    const int32_t* f_img;
+    const int32_t* orb_site;
+    const int32_t* site_orb0;
+    const int32_t* site_L;
 };
 
 template <typename T, int N>
@@ -149,3 +155,5 @@ hipError_t launch_project(const ProjArgs& a, int nchunks, int nq, int prec, int 
                           hipStream_t st);
 hipError_t launch_apply(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
                         hipStream_t st);
+hipError_t launch_apply_grouped(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                                hipStream_t st);

@@ -16,6 +16,14 @@ struct ReduceArgs {
     double dV;
 };
 
+struct ReduceGroupedArgs {
+    const double* part; int64_t prows;
+    double* out; int J; int ncol; int ncplx;
+    const int32_t* red_ptr; const int32_t* red_row; const int32_t* red_img;
+    const double* phase; int nimg; int nspin; int spinor;
+    double dV;
+};
+
 struct NbarArgs {
     const double* c; double* nbar;
     int J; int ncol; int nstates; int ncplx; int spinor; int nspecies;
@@ -60,6 +68,7 @@ struct CoulombArgs {
 };
 
 hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st);
+hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t st);
 hipError_t launch_nbar(const NbarArgs& a, int nq, hipStream_t st);
 hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st);
 hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t st);

@@ -302,6 +302,117 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
     T.nentries = e;
     if (e > INT32_MAX) return HUB_EINVAL;
 
+    // ---- grouped work list (cover signatures)
+    {
+        GroupTables& GT = T.grouped;
+        struct Cover {
+            int32_t g, site, img;
+            uint32_t p;
+        };
+        std::vector<Cover> cov;
+        cov.reserve(static_cast<size_t>(e));
+        for (int s = 0; s < ns; ++s)
+            for (size_t p = 0; p < pts[s].size(); ++p) {
+                const Pt& q = pts[s][p];
+                cov.push_back({q.g, s, image_id[std::make_tuple(q.img[0], q.img[1], q.img[2])],
+                               static_cast<uint32_t>(p)});
+            }
+        std::sort(cov.begin(), cov.end(), [](const Cover& a, const Cover& b) {
+            return std::tie(a.g, a.site, a.img) < std::tie(b.g, b.site, b.img);
+        });
+        // signature -> points (each point: index of its first cover in cov)
+        std::map<std::vector<std::pair<int, int>>, std::vector<size_t>> groups;
+        std::vector<std::vector<std::pair<int, int>>> order;
+        bool ok = true;
+        int nfmax = 0;
+        for (size_t i = 0; i < cov.size();) {
+            size_t k = i;
+            std::vector<std::pair<int, int>> sig;
+            int nf = 0;
+            while (k < cov.size() && cov[k].g == cov[i].g) {
+                sig.push_back({cov[k].site, cov[k].img});
+                nf += T.site_L[cov[k].site];
+                ++k;
+            }
+            nfmax = std::max(nfmax, nf);
+            if (nf > HUB_GF_MAX) ok = false;
+            auto it = groups.find(sig);
+            if (it == groups.end()) {
+                order.push_back(sig);
+                groups[sig].push_back(i);
+            } else {
+                it->second.push_back(i);
+            }
+            i = k;
+        }
+        GT.nfmax = nfmax;
+        GT.ok = ok;
+        if (ok) {
+            const int chunk = std::max(1, chunk_entries);
+            int64_t rows = 0, tab0 = 0;
+            for (const auto& sig : order) {
+                const std::vector<size_t>& firsts = groups[sig];
+                int nf = 0;
+                for (const auto& sl : sig) nf += T.site_L[sl.first];
+                for (size_t b = 0; b < firsts.size(); b += chunk) {
+                    const size_t nb = std::min(firsts.size() - b, static_cast<size_t>(chunk));
+                    HubChunk C;
+                    C.site = sig[0].first;
+                    C.layer = 0;
+                    C.e0 = static_cast<int32_t>(GT.gidx.size());
+                    C.ne = static_cast<int32_t>(nb);
+                    C.L = nf;
+                    C.orb0 = -1;
+                    C.part0 = static_cast<int32_t>(rows);
+                    C.species = -1;
+                    C.phi0 = tab0;
+                    C.img = sig[0].second;
+                    C.pad = static_cast<int32_t>(sig.size());
+                    for (size_t t = 0; t < nb; ++t) {
+                        const size_t i0 = firsts[b + t];
+                        GT.gidx.push_back(cov[i0].g);
+                        for (size_t sl = 0; sl < sig.size(); ++sl) {
+                            const Cover& cv = cov[i0 + sl];
+                            const int L = T.site_L[cv.site];
+                            const double* src = &T.spheres[cv.site].phi[static_cast<size_t>(cv.p) * L];
+                            for (int m = 0; m < L; ++m) GT.tab.push_back(src[m]);
+                        }
+                    }
+                    for (int f = 0; f < HUB_GF_MAX; ++f) {
+                        GT.f_orb.push_back(-1);
+                        GT.f_img.push_back(0);
+                    }
+                    int f = 0;
+                    for (const auto& sl : sig)
+                        for (int m = 0; m < T.site_L[sl.first]; ++m, ++f) {
+                            GT.f_orb[GT.chunks.size() * HUB_GF_MAX + f] = T.site_orb0[sl.first] + m;
+                            GT.f_img[GT.chunks.size() * HUB_GF_MAX + f] = sl.second;
+                        }
+                    tab0 += static_cast<int64_t>(nb) * nf;
+                    rows += nf;
+                    GT.chunks.push_back(C);
+                }
+            }
+            GT.part_rows = rows;
+            if (rows > INT32_MAX) GT.ok = false;
+            // CSR orbital j -> (workspace row, image)
+            std::vector<std::vector<std::pair<int32_t, int32_t>>> red(J);
+            for (size_t c = 0; c < GT.chunks.size(); ++c)
+                for (int f = 0; f < GT.chunks[c].L; ++f) {
+                    const int j = GT.f_orb[c * HUB_GF_MAX + f];
+                    red[j].push_back({GT.chunks[c].part0 + f, GT.f_img[c * HUB_GF_MAX + f]});
+                }
+            GT.red_ptr.assign(J + 1, 0);
+            for (int j = 0; j < J; ++j) {
+                GT.red_ptr[j + 1] = GT.red_ptr[j] + static_cast<int32_t>(red[j].size());
+                for (const auto& it : red[j]) {
+                    GT.red_row.push_back(it.first);
+                    GT.red_img.push_back(it.second);
+                }
+            }
+        }
+    }
+
     // ---- CSR maps
     T.site_chunk_ptr.assign(ns + 1, 0);
     for (const HubChunk& C : T.chunks) T.site_chunk_ptr[C.site + 1]++;

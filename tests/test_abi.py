@@ -96,7 +96,11 @@ def test_layers_and_counts_full_size_geometry():
                     is_complex=True, finalize=False)
     assert hub.site_npts == [58893, 58893, 34049, 34049]
     assert hub.nlayers >= 2 and hub.nsets == 16 and hub.nspecies == 2
+    # grouped work list: each grid point once with all its covers; at most
+    # 5 + 5 + 3 orbitals cover one point (both Ni d shells and one O p shell)
+    assert hub.ngrouped > 0 and hub.nfmax == 13
     cfg3 = make_config("rt_batched")
     hub3 = H.Hubbard(cfg3.cell, cfg3.ngrid, cfg3.sites, spin=cfg3.spin, finalize=False)
     assert hub3.nlayers == 1                      # non-overlapping spheres: one layer
     assert hub3.nentries == 759292 and hub3.J == 272
+    assert hub3.ngrouped > 0 and hub3.nfmax == 7
