@@ -26,7 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-KERNEL_SOURCES = ["k_project.hip", "k_apply.hip", "kcommon.h"]
+# sources of the projection and apply kernels (the counter files record
+# their hash: traffic measured on other sources is not reported)
+KERNEL_SOURCES = ["kcommon.h", "k_project.h", "k_project_f32.hip", "k_project_f64.hip", "k_apply.h",
+                  "k_apply_f32.hip", "k_apply_f64.hip", "k_apply_grouped_f32.hip", "k_apply_grouped_f64.hip"]
 
 
 def log(msg):
@@ -45,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--chunk", type=int, default=None, help="sphere entries per work-list chunk")
+    ap.add_argument("--worklist", default="grouped", choices=["grouped", "persite"],
+                    help="batched work list: every grid point once with all its covers, or per-site layers")
     ap.add_argument("--shapes", default=None,
                     help="fixed kernel shapes PCPL,PWAVES,PLAYOUT,ACPL,AWAVES,ALAYOUT instead of autotuning "
                          "(profiling runs use the shapes the autotuner picked)")
@@ -146,8 +151,10 @@ def main():
     log(f"states generated in {time.perf_counter() - t0:.1f} s")
 
     def ctx(prec):
-        return H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
-                         is_complex=cfg.is_complex, precision=prec, chunk=args.chunk)
+        hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                        is_complex=cfg.is_complex, precision=prec, chunk=args.chunk)
+        hub.set_worklist(args.worklist == "grouped")
+        return hub
 
     hub32 = ctx("f32")
     psi32 = psi64.to(hub32.state_dtype)
@@ -297,6 +304,7 @@ def main():
         "data": "synthetic", "config": {"workload": cfg.name, "grid": list(cfg.ngrid), "sites": len(cfg.sites),
                                         "kpoints": cfg.nk, "spin": cfg.spin, "states": S,
                                         "mode": "hipGraph per step", "storage": "f32 states, f64 orbital table",
+                                        "worklist": args.worklist, "chunk": args.chunk or 512,
                                         "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "detail": detail,
     }

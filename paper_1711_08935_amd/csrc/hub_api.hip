@@ -57,6 +57,7 @@ struct hub_ctx {
     double *d_kw = nullptr, *d_ueff_fixed = nullptr, *d_tensor = nullptr;
     // grouped (cover-signature) work list
     bool use_grouped = true;
+    int gcls_ptr[HUB_NCLASS + 1] = {};       // d_gall[gcls_ptr[k-1], gcls_ptr[k]): chunks of class k
     HubChunk* d_gchunks = nullptr;
     int32_t *d_gall = nullptr, *d_ggidx = nullptr, *d_gf_orb = nullptr, *d_gf_img = nullptr;
     int32_t *d_gred_ptr = nullptr, *d_gred_row = nullptr, *d_gred_img = nullptr;
@@ -67,6 +68,8 @@ struct hub_ctx {
     // workspaces
     double* d_part = nullptr;
     size_t part_cap = 0;
+    double* d_sink = nullptr;                // one state row for the apply's padding entries
+    size_t sink_cap = 0;
     double* d_grad = nullptr;
     size_t grad_cap = 0;
     double* d_nbar_ws = nullptr;
@@ -123,7 +126,7 @@ void release(hub_ctx* c) {
     f(c->d_chunks); f(c->d_all); f(c->d_gidx); f(c->d_img); f(c->d_phi); f(c->d_gphi); f(c->d_phase);
     f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
     f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
-    f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws);
+    f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink);
     f(c->d_gchunks); f(c->d_gall); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -220,7 +223,7 @@ bool built(const hub_ctx* c) { return c && c->built_dev; }
 bool grouped(const hub_ctx* c) { return c->use_grouped && c->T.grouped.ok; }
 
 // Columns per lane so that a lane's FP64 accumulators (functions x scalars)
-// stay within 96 values.
+// stay within 96 values (nf: the largest function count launched).
 int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
     while (cpl > 1 && nf * cpl * c->ncplx() > 96) cpl /= 2;
     return cpl;
@@ -281,16 +284,22 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     if (!per_site && !grad && grouped(c)) {
         const GroupTables& GT = c->T.grouped;
         a.chunks = c->d_gchunks;
-        a.chunk_list = c->d_gall;
         a.gidx = c->d_ggidx;
         a.tab = c->d_gtab;
         a.prows = GT.part_rows;
-        const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), GT.nfmax);
-        a.wide = pick_wide(c, ncol, cpl, 0);
         {
             StageTimer tm(c, HUB_STAGE_PROJECT);
-            HUB_TRY(launch_project(a, static_cast<int>(GT.chunks.size()), c->nsets(), c->precision, c->is_complex, cpl,
-                                   c->tune_waves[0], c->stream));
+            // one launch per function-count class
+            for (int k = 1; k <= HUB_NCLASS; ++k) {
+                const int b0 = c->gcls_ptr[k - 1], b1 = c->gcls_ptr[k];
+                if (b1 <= b0) continue;
+                ProjArgs b = a;
+                b.chunk_list = c->d_gall + b0;
+                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), 4 * k);
+                b.wide = pick_wide(c, ncol, cpl, 0);
+                HUB_TRY(launch_project(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[0], k,
+                                       c->stream));
+            }
         }
         ReduceGroupedArgs r{};
         r.part = c->d_part;
@@ -319,13 +328,13 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     StageTimer tm(c, grad ? HUB_STAGE_GRADPROJ : HUB_STAGE_PROJECT);
     if (!per_site) {
         HUB_TRY(launch_project(a, static_cast<int>(c->T.chunks.size()), c->nsets(), c->precision, c->is_complex,
-                               cpl, waves, c->stream));
+                               cpl, waves, 0, c->stream));
     } else {
         for (int s = 0; s < c->T.nsites; ++s) {
             ProjArgs b = a;
             b.chunk_list = c->d_site_chunk_ids + c->T.site_chunk_ptr[s];
             HUB_TRY(launch_project(b, c->T.site_chunk_ptr[s + 1] - c->T.site_chunk_ptr[s], c->nsets(), c->precision,
-                                   c->is_complex, cpl, waves, c->stream));
+                                   c->is_complex, cpl, waves, 0, c->stream));
         }
     }
     }
@@ -418,8 +427,11 @@ int do_acbn0(hub_ctx* c, const double* n, const double* pbar, double* U, double*
 int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, int nstates, const double* colscale,
              double alpha, void* hpsi, int64_t ld, bool per_site) {
     const int ncol = c->ncol(nstates);
+    int st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(ld) * c->ncplx(), c);
+    if (st) return st;
     ApplyArgs a{};
     a.hpsi = hpsi;
+    a.sink = c->d_sink;
     a.ld = ld;
     a.qstride = c->G() * ld * c->ncplx();
     a.ncol = ncol;
@@ -443,18 +455,23 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.site_orb0 = c->d_site_orb0;
     a.site_L = c->d_site_L;
     if (!per_site && grouped(c)) {
-        const GroupTables& GT = c->T.grouped;
-        const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), GT.nfmax);
         a.wide = 1;
         a.chunks = c->d_gchunks;
-        a.chunk_list = c->d_gall;
         a.gidx = c->d_ggidx;
         a.tab = c->d_gtab;
         a.f_orb = c->d_gf_orb;
         a.f_img = c->d_gf_img;
         StageTimer tm(c, HUB_STAGE_APPLY);
-        HUB_TRY(launch_apply_grouped(a, static_cast<int>(GT.chunks.size()), c->nsets(), c->precision, c->is_complex,
-                                     cpl, c->tune_waves[1], c->stream));
+        // one launch per function-count class; the classes hold disjoint points
+        for (int k = 1; k <= HUB_NCLASS; ++k) {
+            const int b0 = c->gcls_ptr[k - 1], b1 = c->gcls_ptr[k];
+            if (b1 <= b0) continue;
+            ApplyArgs b = a;
+            b.chunk_list = c->d_gall + b0;
+            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), 4 * k);
+            HUB_TRY(launch_apply_grouped(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k,
+                                         c->stream));
+        }
         return HUB_OK;
     }
     const int cpl = pick_cpl(c, hpsi, ld, 1);
@@ -676,8 +693,15 @@ int hub_finalize(hub_ctx* c, void* stream) {
     up(&c->d_kw, c->kw);
     up(&c->d_ueff_fixed, fixed);
     if (T.grouped.ok) {
-        std::vector<int32_t> gall(T.grouped.chunks.size());
-        for (size_t i = 0; i < gall.size(); ++i) gall[i] = static_cast<int32_t>(i);
+        // launch order: chunks sorted by function-count class
+        std::vector<int32_t> gall;
+        gall.reserve(T.grouped.chunks.size());
+        c->gcls_ptr[0] = 0;
+        for (int k = 1; k <= HUB_NCLASS; ++k) {
+            for (size_t i = 0; i < T.grouped.chunks.size(); ++i)
+                if (hub_nf_class(T.grouped.chunks[i].L) == k) gall.push_back(static_cast<int32_t>(i));
+            c->gcls_ptr[k] = static_cast<int>(gall.size());
+        }
         up(&c->d_gchunks, T.grouped.chunks);
         up(&c->d_gall, gall);
         up(&c->d_ggidx, T.grouped.gidx);
@@ -902,6 +926,8 @@ int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
         st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);
         if (st) return st;
     }
+    st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(io->ldh) * c->ncplx(), c);
+    if (st) return st;
     if (mode != HUB_STEP_GRAPH) return run_step(c, io, mode == HUB_STEP_PERSITE);
 
     const bool same = c->gkey.valid && c->gkey.ncol == ncol && std::memcmp(&c->gkey.io, io, sizeof(hub_step_io)) == 0;

@@ -15,15 +15,21 @@ struct HubChunk {
     int32_t site;
     int32_t layer;
     int32_t e0;      // first entry
-    int32_t ne;      // number of entries
+    int32_t ne;      // entries, padded to a multiple of HUB_ENTRY_ALIGN
     int32_t L;       // orbitals of the site (2l+1)
     int32_t orb0;    // global index j of the site's first orbital
     int32_t part0;   // first row of this chunk in the projection workspace
     int32_t species;
     int64_t phi0;    // offset of the chunk's orbital values (entries * L)
     int32_t img;     // lattice image shared by every entry of the chunk
-    int32_t pad;
+    int32_t nreal;   // real entries; entries nreal..ne-1 repeat the last grid
+                     // point with zero orbital values
 };
+
+// Chunk entry lists are padded to a multiple of this many entries, so that
+// every wave's share (1, 2 or 4 waves per work-group) holds whole batches of
+// the kernels' entry loops (at most 8 entries).
+#define HUB_ENTRY_ALIGN 32
 
 struct SiteDef {
     double R[3];

@@ -1,0 +1,258 @@
+// Projection kernel: partial sums of <phi_j,k|psi> over one work-list chunk.
+//
+// part[q][row][col] = sum_{e in chunk} tab[e][f] psi_q[g_e][col]
+// for the chunk's functions f (orbitals, or their three gradient components),
+// row = chunk.part0 * tabmult + f.  Every entry of a chunk has the same
+// lattice image (a grouped chunk: the same covering (site, image) functions),
+// so the Bloch phase exp(+i k.T) of Fig. 1, the dV factor and the sum over
+// the chunks of a site are applied once per chunk row by the reduction
+// kernel.  Paper: the brackets of Eq. occ_matrices (Sec. II).
+//
+// Work mapping (gfx950, 64-wide waves): a 1-D grid of (chunk, column tile)
+// work-groups, the tiles of a chunk consecutive on one XCD (hub_slot).  Each
+// lane owns CPL consecutive columns of one state set and reads them with one
+// or two vector loads from the state row of grid point g_e.  Two lane layouts:
+//  * WIDE: every wave lies inside one state set (q is uniform), so a row
+//    address is a scalar base (set, grid point) plus a 32-bit lane offset;
+//  * packed: lanes tile the flattened (set, column group) space, so sets
+//    narrower than a wave share one (no idle lanes, per-lane addresses).
+// Entry data (g, orbital values) is uniform across the wave and comes
+// through scalar loads.  Each wave of a work-group takes a contiguous range
+// of the chunk's entries (so the indexes and orbital values of a batch are
+// one contiguous block, read with wide scalar loads); the waves are summed
+// through LDS at the end.  The entry loop is software pipelined: rows are
+// loaded in batches of U into two register buffers and the loads of the next
+// batch are in flight while a batch is contracted.  Products and sums are
+// FP64 for both storage precisions; for complex states the real orbital
+// value multiplies the real and imaginary parts (2 FMAs per column).
+//
+// This header holds the kernel templates; each storage precision is
+// instantiated in a translation unit of its own.
+
+#pragma once
+
+#include "kcommon.h"
+
+namespace {
+
+template <int NV>
+struct ProjLds {
+    double red[3][HUB_WAVE][NV];
+};
+
+template <typename T, int NV, int NF, bool WIDE>
+__device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C, int tile, ProjLds<NV>& lds) {
+    constexpr int U = hub_batch_rows(NV, NF);
+    const int lane = threadIdx.x & (HUB_WAVE - 1);
+    // wave index made provably uniform so entry data goes through scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
+    const int nw = blockDim.x / HUB_WAVE;
+    const int NC = a.ncplx;
+    const int cpl = NV / NC;
+    const int cg = (a.ncol + cpl - 1) / cpl;
+
+    int q, col0;
+    bool active;
+    if constexpr (WIDE) {
+        const int tps = (cg + HUB_WAVE - 1) / HUB_WAVE;          // tiles per set
+        q = tile / tps;
+        col0 = ((tile - q * tps) * HUB_WAVE + lane) * cpl;
+        active = col0 < a.ncol;
+    } else {
+        const int t = tile * HUB_WAVE + lane;
+        active = t < a.nq * cg;
+        q = active ? t / cg : 0;
+        col0 = (t - (t / cg) * cg) * cpl;
+    }
+    // lanes past the last column or set read column 0 of their set (their
+    // sums are discarded), so every load is unconditional
+    const int colc = active ? col0 : 0;
+    const T* __restrict__ psi_q = reinterpret_cast<const T*>(a.psi) + static_cast<int64_t>(q) * a.qstride;
+    // this wave's entries: e0 + [lo, lo + nj) of the chunk
+    int lo, nj;
+    hub_wave_range(C.ne, nw, wave, lo, nj);
+    const int32_t* __restrict__ gi = a.gidx + C.e0 + lo;
+    const double* __restrict__ tb = a.tab + (C.phi0 * a.tabmult + static_cast<int64_t>(lo) * NF);
+    const int lofs = colc * NC;                                      // lane offset inside a row
+
+    double acc[NF][NV];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[f][v] = 0.0;
+
+    // whole batches of U entries (chunk lengths are multiples of
+    // HUB_ENTRY_ALIGN, so every wave's share is); padding entries carry zero
+    // orbital values
+    const int nbt = nj / U;
+    auto load_batch = [&](int b, T (&r)[U][NV]) {
+        const int32_t* __restrict__ gb = gi + b * U;
+#pragma unroll
+        for (int u = 0; u < U; ++u) load_row<T, NV>(psi_q + static_cast<int64_t>(gb[u]) * a.ld * NC + lofs, r[u]);
+    };
+    auto read_tab = [&](int b, double (&w)[U][NF]) {
+        const double* __restrict__ wb = tb + static_cast<int64_t>(b) * U * NF;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) w[u][f] = wb[u * NF + f];
+    };
+    auto fma_batch = [&](const double (&w)[U][NF], const T (&r)[U][NV]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[f][v] = fma(w[u][f], static_cast<double>(r[u][v]), acc[f][v]);
+    };
+    // Two-stage pipeline with a branch-free body (a conditional use of a
+    // buffer would let the compiler sink its loads next to the use); the
+    // batch after the last reloads the last one, whose copy is never used.
+    // A batch's orbital values are read before the next batch's indexes, so
+    // the two scalar reads overlap, and the scheduling barriers keep the row
+    // loads ahead of the contraction.
+    if (nbt > 0) {
+        T ra[U][NV], rb[U][NV];
+        double w[U][NF];
+        load_batch(0, ra);
+        int b = 0;
+        for (; b + 2 <= nbt; b += 2) {
+            read_tab(b, w);
+            load_batch(b + 1, rb);
+            __builtin_amdgcn_sched_barrier(0);
+            fma_batch(w, ra);
+            read_tab(b + 1, w);
+            load_batch(b + 2 < nbt ? b + 2 : nbt - 1, ra);
+            __builtin_amdgcn_sched_barrier(0);
+            fma_batch(w, rb);
+        }
+        if (b < nbt) {
+            read_tab(b, w);
+            fma_batch(w, ra);
+        }
+    }
+
+    // sum the waves of the work-group, one function at a time
+    if (nw > 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (wave > 0) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) lds.red[wave - 1][lane][v] = acc[f][v];
+            }
+            __syncthreads();
+            if (wave == 0) {
+                for (int w = 1; w < nw; ++w)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[f][v] += lds.red[w - 1][lane][v];
+            }
+            __syncthreads();
+        }
+    }
+    if (wave != 0 || !active) return;
+    double* __restrict__ out = a.part + (static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.tabmult) *
+                                            a.ncol * NC;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int col = col0 + v / NC;
+            if (col < a.ncol) out[(static_cast<int64_t>(f) * a.ncol + col0) * NC + v] = acc[f][v];
+        }
+    }
+}
+
+// NV = scalars per lane (columns per lane times 1 or 2); GRAD selects the
+// gradient table (three functions per orbital); WIDE the lane layout; CLS
+// the function-count class of the launched chunks (0: per-site chunks).
+template <typename T, int NV, bool GRAD, bool WIDE, int CLS>
+__global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
+    __shared__ ProjLds<NV> lds;
+    const HubSlot slot = hub_slot(a.tiles);
+    if (slot.chunk >= a.nchunks) return;
+    const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
+    const int tile = slot.tile;
+    if constexpr (GRAD) {
+        switch (C.L) {
+        case 1: project_body<T, NV, 3, WIDE>(a, C, tile, lds); break;
+        case 3: project_body<T, NV, 9, WIDE>(a, C, tile, lds); break;
+        case 5: project_body<T, NV, 15, WIDE>(a, C, tile, lds); break;
+        case 7: project_body<T, NV, 21, WIDE>(a, C, tile, lds); break;
+        default: break;
+        }
+    } else if constexpr (CLS == 0) {
+        switch (C.L) {
+        case 1: project_body<T, NV, 1, WIDE>(a, C, tile, lds); break;
+        case 3: project_body<T, NV, 3, WIDE>(a, C, tile, lds); break;
+        case 5: project_body<T, NV, 5, WIDE>(a, C, tile, lds); break;
+        case 7: project_body<T, NV, 7, WIDE>(a, C, tile, lds); break;
+        default: break;
+        }
+    } else {
+        // grouped chunks: the concatenated orbitals of the covering sites
+        constexpr int B = 4 * (CLS - 1);
+        switch (C.L - B) {
+        case 1: project_body<T, NV, B + 1, WIDE>(a, C, tile, lds); break;
+        case 2: project_body<T, NV, B + 2, WIDE>(a, C, tile, lds); break;
+        case 3: project_body<T, NV, B + 3, WIDE>(a, C, tile, lds); break;
+        case 4: project_body<T, NV, B + 4, WIDE>(a, C, tile, lds); break;
+        default: break;
+        }
+    }
+}
+
+// Largest function count of a class (class 0: per-site chunks, L <= 7; the
+// gradient table holds 3L functions).
+constexpr int proj_nf_max(bool grad, int cls) { return grad ? 21 : (cls == 0 ? 7 : 4 * cls); }
+
+template <typename T, int NV, bool GRAD, int CLS>
+hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
+    // a lane's FP64 accumulators (functions x scalars) stay within 96 values
+    if constexpr (proj_nf_max(GRAD, CLS) * NV > (GRAD ? 84 : 96)) {
+        return hipErrorInvalidValue;
+    } else {
+        const int64_t cg = (a.ncol + cpl - 1) / cpl;
+        ProjArgs b = a;
+        b.nchunks = nchunks;
+        b.tiles = static_cast<int>(a.wide ? static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE)
+                                          : (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE);
+        const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
+        if (a.wide)
+            hipLaunchKernelGGL((k_project<T, NV, GRAD, true, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b);
+        else
+            hipLaunchKernelGGL((k_project<T, NV, GRAD, false, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b);
+        return hipGetLastError();
+    }
+}
+
+template <typename T, bool GRAD, int CLS>
+hipError_t launch_g(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, hipStream_t st) {
+    const int nv = cpl * (cplx ? 2 : 1);
+    switch (nv) {
+    case 1: return launch_t<T, 1, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 2: return launch_t<T, 2, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 4: return launch_t<T, 4, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 8: return launch_t<T, 8, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Launch the projection for storage type T (orbital or gradient table) over
+// chunks of function-count class cls.
+template <typename T>
+hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
+                               hipStream_t st) {
+    if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    if (a.tabmult == 3) return cls == 0 ? launch_g<T, true, 0>(a, nchunks, nq, cplx, cpl, waves, st)
+                                        : hipErrorInvalidValue;
+    switch (cls) {
+    case 0: return launch_g<T, false, 0>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 1: return launch_g<T, false, 1>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 2: return launch_g<T, false, 2>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 3: return launch_g<T, false, 3>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 4: return launch_g<T, false, 4>(a, nchunks, nq, cplx, cpl, waves, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace

@@ -23,6 +23,8 @@ struct ProjArgs {
     const double* tab;        // orbital table (or gradient table)
     int tabmult;              // 1: phi, 3: grad phi
     int wide;                 // 1: one state set per wave; 0: sets packed across lanes
+    int nchunks;              // chunks in chunk_list (set by the launcher)
+    int tiles;                // column tiles per chunk (set by the launcher)
     double* part;             // [nq][prows][ncol] (x2 complex)
     int64_t prows;            // rows per state set = part_rows * tabmult
 };
@@ -51,12 +53,17 @@ struct ApplyArgs {
     const double* colscale;   // [nq][nstates] or null
     double alpha;
     int wide;                 // 1: one state set per wave; 0: sets packed across lanes
+    int nchunks;              // chunks in chunk_list (set by the launcher)
+    int tiles;                // column tiles per chunk (set by the launcher)
     // grouped chunks: per chunk HUB_GF_MAX (orbital j, image) pairs
     const int32_t* f_orb;
     const int32_t* f_img;
     const int32_t* orb_site;
     const int32_t* site_orb0;
     const int32_t* site_L;
+    // one row (ld x ncplx values) of scratch that the padding entries of a
+    // chunk read and write instead of a state row; its contents are garbage
+    void* sink;
 };
 
 template <typename T, int N>
@@ -150,10 +157,78 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[N]) {
     }
 }
 
-// Launchers (defined in the .hip files).
-hipError_t launch_project(const ProjArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
-                          hipStream_t st);
-hipError_t launch_apply(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
-                        hipStream_t st);
-hipError_t launch_apply_grouped(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
-                                hipStream_t st);
+// Rows per batch of the software-pipelined entry loops: the two batches of
+// U rows of NV values per lane stay within 32 values, and the orbital values
+// of one batch (U x NF doubles, uniform, held in scalar registers) within 32.
+__host__ __device__ constexpr int hub_batch_rows(int nv, int nf) {
+    int u = 8;
+    while (u > 1 && (u * nv > 16 || u * nf > 32)) u /= 2;
+    return u;
+}
+
+// Function-count classes of the grouped work list: class k (1..HUB_NCLASS)
+// holds the chunks with 4(k-1) < NF <= 4k and is launched on its own, so a
+// kernel's registers follow the largest NF of its class.  Class 0 is the
+// per-site work list (L in {1, 3, 5, 7}).
+#define HUB_NCLASS 4
+static_assert(HUB_GF_MAX == 4 * HUB_NCLASS, "the classes cover every grouped function count");
+__host__ __device__ constexpr int hub_nf_class(int nf) { return (nf + 3) / 4; }
+
+// Work-groups are dispatched to the XCDs round-robin (work-group w runs on
+// XCD w mod 8), and each XCD has its own L2.  The 1-D launch grid maps w to
+// (chunk slot, column tile) so that the tiles of one chunk are consecutive
+// work-groups of one XCD: the chunk's indexes and orbital values are read
+// from HBM once and from that XCD's L2 by the other tiles.
+#define HUB_NXCD 8
+struct HubSlot {
+    int chunk;                // index into the launch's chunk list
+    int tile;                 // column tile
+};
+__device__ __forceinline__ HubSlot hub_slot(int tiles) {
+    const int w = blockIdx.x;
+    const int wl = w / HUB_NXCD;
+    return {(wl / tiles) * HUB_NXCD + (w - wl * HUB_NXCD), wl % tiles};
+}
+// work-groups of such a launch (chunk slots past nchunks exit at once)
+inline int64_t hub_slot_grid(int nchunks, int64_t tiles) {
+    return static_cast<int64_t>((nchunks + HUB_NXCD - 1) / HUB_NXCD) * HUB_NXCD * tiles;
+}
+
+// Splits [0, n) into nw contiguous ranges; range w is [lo, lo + len).
+__device__ __forceinline__ void hub_wave_range(int n, int nw, int w, int& lo, int& len) {
+    const int per = (n + nw - 1) / nw;
+    lo = w * per;
+    const int hi = lo + per < n ? lo + per : n;
+    len = hi > lo ? hi - lo : 0;
+}
+
+// Launchers, one translation unit per storage precision (and work list).
+hipError_t launch_project_f32(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
+                              hipStream_t st);
+hipError_t launch_project_f64(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
+                              hipStream_t st);
+hipError_t launch_apply_f32(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
+                            hipStream_t st);
+hipError_t launch_apply_f64(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
+                            hipStream_t st);
+hipError_t launch_apply_grouped_f32(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
+                                    int cls, hipStream_t st);
+hipError_t launch_apply_grouped_f64(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
+                                    int cls, hipStream_t st);
+
+// cls: function-count class of the chunks in a.chunk_list (0: per-site list)
+inline hipError_t launch_project(const ProjArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                                 int cls, hipStream_t st) {
+    return prec == HUB_F64 ? launch_project_f64(a, nchunks, nq, cplx, cpl, waves, cls, st)
+                           : launch_project_f32(a, nchunks, nq, cplx, cpl, waves, cls, st);
+}
+inline hipError_t launch_apply(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl, int waves,
+                               hipStream_t st) {
+    return prec == HUB_F64 ? launch_apply_f64(a, nchunks, nq, cplx, cpl, waves, st)
+                           : launch_apply_f32(a, nchunks, nq, cplx, cpl, waves, st);
+}
+inline hipError_t launch_apply_grouped(const ApplyArgs& a, int nchunks, int nq, int prec, int cplx, int cpl,
+                                       int waves, int cls, hipStream_t st) {
+    return prec == HUB_F64 ? launch_apply_grouped_f64(a, nchunks, nq, cplx, cpl, waves, cls, st)
+                           : launch_apply_grouped_f32(a, nchunks, nq, cplx, cpl, waves, cls, st);
+}

@@ -247,7 +247,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
     const int chunk = std::max(1, chunk_entries);
     T.layer_chunk_ptr.assign(nlayers + 1, 0);
     T.layer_site_ptr.assign(static_cast<size_t>(nlayers) * ns + 1, 0);
-    int64_t e = 0, phi0 = 0;
+    int64_t e = 0, phi0 = 0, nreal = 0;
     int part_rows = 0;
     for (int lay = 0; lay < nlayers; ++lay) {
         T.layer_chunk_ptr[lay] = static_cast<int32_t>(T.chunks.size());
@@ -267,13 +267,14 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                 const int im = img_of(mine[b]);
                 size_t nb = 0;
                 while (b + nb < mine.size() && nb < static_cast<size_t>(chunk) && img_of(mine[b + nb]) == im) ++nb;
+                const size_t np = (nb + HUB_ENTRY_ALIGN - 1) / HUB_ENTRY_ALIGN * HUB_ENTRY_ALIGN;
                 HubChunk C;
                 C.img = im;
-                C.pad = 0;
+                C.nreal = static_cast<int32_t>(nb);
                 C.site = s;
                 C.layer = lay;
                 C.e0 = static_cast<int32_t>(e);
-                C.ne = static_cast<int32_t>(nb);
+                C.ne = static_cast<int32_t>(np);
                 C.L = L;
                 C.orb0 = T.site_orb0[s];
                 C.part0 = part_rows;
@@ -288,8 +289,16 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     for (int m = 0; m < L; ++m)
                         for (int i = 0; i < 3; ++i) T.gphi.push_back(sp.grad[(p * L + m) * 3 + i]);
                 }
-                e += static_cast<int64_t>(nb);
-                phi0 += static_cast<int64_t>(nb) * L;
+                // padding entries: the last grid point again, zero values
+                for (size_t t = nb; t < np; ++t) {
+                    T.gidx.push_back(T.gidx.back());
+                    T.img.push_back(T.img.back());
+                    T.phi.insert(T.phi.end(), L, 0.0);
+                    T.gphi.insert(T.gphi.end(), 3 * L, 0.0);
+                }
+                e += static_cast<int64_t>(np);
+                nreal += static_cast<int64_t>(nb);
+                phi0 += static_cast<int64_t>(np) * L;
                 part_rows += L;
                 T.chunks.push_back(C);
                 b += nb;
@@ -299,7 +308,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
     T.layer_chunk_ptr[nlayers] = static_cast<int32_t>(T.chunks.size());
     T.layer_site_ptr[static_cast<size_t>(nlayers) * ns] = static_cast<int32_t>(T.chunks.size());
     T.part_rows = part_rows;
-    T.nentries = e;
+    T.nentries = nreal;
     if (e > INT32_MAX) return HUB_EINVAL;
 
     // ---- grouped work list (cover signatures)
@@ -310,7 +319,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
             uint32_t p;
         };
         std::vector<Cover> cov;
-        cov.reserve(static_cast<size_t>(e));
+        cov.reserve(static_cast<size_t>(nreal));
         for (int s = 0; s < ns; ++s)
             for (size_t p = 0; p < pts[s].size(); ++p) {
                 const Pt& q = pts[s][p];
@@ -356,18 +365,19 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                 for (const auto& sl : sig) nf += T.site_L[sl.first];
                 for (size_t b = 0; b < firsts.size(); b += chunk) {
                     const size_t nb = std::min(firsts.size() - b, static_cast<size_t>(chunk));
+                    const size_t np = (nb + HUB_ENTRY_ALIGN - 1) / HUB_ENTRY_ALIGN * HUB_ENTRY_ALIGN;
                     HubChunk C;
                     C.site = sig[0].first;
                     C.layer = 0;
                     C.e0 = static_cast<int32_t>(GT.gidx.size());
-                    C.ne = static_cast<int32_t>(nb);
+                    C.ne = static_cast<int32_t>(np);
+                    C.nreal = static_cast<int32_t>(nb);
                     C.L = nf;
                     C.orb0 = -1;
                     C.part0 = static_cast<int32_t>(rows);
                     C.species = -1;
                     C.phi0 = tab0;
                     C.img = sig[0].second;
-                    C.pad = static_cast<int32_t>(sig.size());
                     for (size_t t = 0; t < nb; ++t) {
                         const size_t i0 = firsts[b + t];
                         GT.gidx.push_back(cov[i0].g);
@@ -377,6 +387,10 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                             const double* src = &T.spheres[cv.site].phi[static_cast<size_t>(cv.p) * L];
                             for (int m = 0; m < L; ++m) GT.tab.push_back(src[m]);
                         }
+                    }
+                    for (size_t t = nb; t < np; ++t) {
+                        GT.gidx.push_back(GT.gidx.back());
+                        GT.tab.insert(GT.tab.end(), nf, 0.0);
                     }
                     for (int f = 0; f < HUB_GF_MAX; ++f) {
                         GT.f_orb.push_back(-1);
@@ -388,7 +402,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                             GT.f_orb[GT.chunks.size() * HUB_GF_MAX + f] = T.site_orb0[sl.first] + m;
                             GT.f_img[GT.chunks.size() * HUB_GF_MAX + f] = sl.second;
                         }
-                    tab0 += static_cast<int64_t>(nb) * nf;
+                    tab0 += static_cast<int64_t>(np) * nf;
                     rows += nf;
                     GT.chunks.push_back(C);
                 }
