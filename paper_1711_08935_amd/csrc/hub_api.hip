@@ -46,6 +46,10 @@ struct hub_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    // side streams (default priority) for the concurrent per-class launches
+    hipStream_t side[HUB_NCLASS] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[HUB_NCLASS] = {};
 
     // device tables
     HubChunk* d_chunks = nullptr;
@@ -70,6 +74,8 @@ struct hub_ctx {
     size_t part_cap = 0;
     double* d_sink = nullptr;                // one state row for the apply's padding entries
     size_t sink_cap = 0;
+    double* d_occ_ws = nullptr;              // partial occupation sums
+    size_t occ_cap = 0;
     double* d_grad = nullptr;
     size_t grad_cap = 0;
     double* d_nbar_ws = nullptr;
@@ -126,12 +132,21 @@ void release(hub_ctx* c) {
     f(c->d_chunks); f(c->d_all); f(c->d_gidx); f(c->d_img); f(c->d_phi); f(c->d_gphi); f(c->d_phase);
     f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
     f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
-    f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink);
+    f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
     f(c->d_gchunks); f(c->d_gall); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (int k = 0; k < HUB_NCLASS; ++k) {
+        if (c->side[k]) (void)hipStreamDestroy(c->side[k]);
+        if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
+        c->side[k] = nullptr;
+        c->join_ev[k] = nullptr;
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    c->fork_ev = nullptr;
+    c->cap_stream = nullptr;
     c->gexec = nullptr;
     c->graph = nullptr;
 }
@@ -229,6 +244,30 @@ int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
     return cpl;
 }
 
+// Runs launch(k, stream) for every non-empty function-count class k of the
+// grouped work list.  With several classes the launches go to side streams
+// forked from the context's stream and joined back to it: the classes write
+// disjoint outputs, so their kernels run concurrently (parallel branches of
+// a captured graph).
+template <typename F>
+int run_classes(hub_ctx* c, F&& launch) {
+    int used[HUB_NCLASS], nu = 0;
+    for (int k = 1; k <= HUB_NCLASS; ++k)
+        if (c->gcls_ptr[k] > c->gcls_ptr[k - 1]) used[nu++] = k;
+    if (nu == 1) {
+        HUB_TRY(launch(used[0], c->stream));
+        return HUB_OK;
+    }
+    HUB_TRY(hipEventRecord(c->fork_ev, c->stream));
+    for (int i = 0; i < nu; ++i) {
+        HUB_TRY(hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
+        HUB_TRY(launch(used[i], c->side[i]));
+        HUB_TRY(hipEventRecord(c->join_ev[i], c->side[i]));
+    }
+    for (int i = 0; i < nu; ++i) HUB_TRY(hipStreamWaitEvent(c->stream, c->join_ev[i], 0));
+    return HUB_OK;
+}
+
 ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad) {
     ProjArgs a{};
     a.psi = psi;
@@ -290,16 +329,16 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         {
             StageTimer tm(c, HUB_STAGE_PROJECT);
             // one launch per function-count class
-            for (int k = 1; k <= HUB_NCLASS; ++k) {
+            const int st = run_classes(c, [&](int k, hipStream_t s) {
                 const int b0 = c->gcls_ptr[k - 1], b1 = c->gcls_ptr[k];
-                if (b1 <= b0) continue;
                 ProjArgs b = a;
                 b.chunk_list = c->d_gall + b0;
                 const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), 4 * k);
                 b.wide = pick_wide(c, ncol, cpl, 0);
-                HUB_TRY(launch_project(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[0], k,
-                                       c->stream));
-            }
+                return launch_project(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[0], k,
+                                      s);
+            });
+            if (st) return st;
         }
         ReduceGroupedArgs r{};
         r.part = c->d_part;
@@ -344,12 +383,19 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     return HUB_OK;
 }
 
+size_t occ_need(const hub_ctx* c, int nstates) {
+    const int nchan = c->spin_mode == HUB_SPINOR ? 1 : c->nspin();
+    return static_cast<size_t>(c->T.nsites) * nchan * hub_occ_splits(c->nk, nstates) * HUB_OCC_PAIRS * 4;
+}
+
 int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, double* n, double* pbar, double* nbar,
                    bool per_site) {
     const int ncol = c->ncol(nstates);
+    int st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, nstates), c);
+    if (st) return st;
     if (pbar && !nbar) {
         const size_t need = static_cast<size_t>(c->nsets()) * c->T.nspecies * nstates;
-        int st = ensure(&c->d_nbar_ws, &c->nbar_cap, need, c);
+        st = ensure(&c->d_nbar_ws, &c->nbar_cap, need, c);
         if (st) return st;
         nbar = c->d_nbar_ws;
     }
@@ -387,6 +433,8 @@ int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, d
     o.nk = c->nk;
     o.nblk = c->nblk();
     o.nspecies = c->T.nspecies;
+    o.nsplit = hub_occ_splits(c->nk, nstates);
+    o.ws = c->d_occ_ws;
     StageTimer tm(c, HUB_STAGE_OCC);
     if (!per_site) {
         HUB_TRY(launch_occ(o, 0, c->T.nsites, c->stream));
@@ -463,16 +511,14 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
         a.f_img = c->d_gf_img;
         StageTimer tm(c, HUB_STAGE_APPLY);
         // one launch per function-count class; the classes hold disjoint points
-        for (int k = 1; k <= HUB_NCLASS; ++k) {
+        return run_classes(c, [&](int k, hipStream_t s) {
             const int b0 = c->gcls_ptr[k - 1], b1 = c->gcls_ptr[k];
-            if (b1 <= b0) continue;
             ApplyArgs b = a;
             b.chunk_list = c->d_gall + b0;
             const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), 4 * k);
-            HUB_TRY(launch_apply_grouped(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k,
-                                         c->stream));
-        }
-        return HUB_OK;
+            return launch_apply_grouped(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k,
+                                        s);
+        });
     }
     const int cpl = pick_cpl(c, hpsi, ld, 1);
     a.wide = pick_wide(c, ncol, cpl, 1);
@@ -717,6 +763,11 @@ int hub_finalize(hub_ctx* c, void* stream) {
         b += c->sites.size() * 2401 * sizeof(double);
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    for (int k = 0; k < HUB_NCLASS && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         release(c);
         return map_err(e);
@@ -927,6 +978,8 @@ int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
         if (st) return st;
     }
     st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(io->ldh) * c->ncplx(), c);
+    if (st) return st;
+    st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, io->nstates), c);
     if (st) return st;
     if (mode != HUB_STEP_GRAPH) return run_step(c, io, mode == HUB_STEP_PERSITE);
 

@@ -8,7 +8,7 @@
 namespace {
 
 constexpr int NB = 256;   // threads of the per-site kernels
-constexpr int TILE = 128; // states staged per LDS tile in k_occ
+constexpr int TILE = 64;  // (k-point, state) pairs staged per LDS tile in k_occ_part
 
 // ---------------------------------------------------------------- reduction
 // out[q][r][col] = dV * sum over the chunks of the row's site of
@@ -43,26 +43,33 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
 }
 
 // Grouped work list: out[q][j][col] = dV sum over the workspace rows that
-// belong to orbital j of exp(+i k.T_row) part[q][row][col].  Independent
-// partial sums keep several loads in flight.
+// belong to orbital j of exp(+i k.T_row) part[q][row][col].  A work-group
+// serves 64 columns of one (j, q); its four waves take interleaved rows with
+// four independent partial sums each (many loads in flight), and the sixteen
+// partial sums are combined in a fixed order.
 __global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs a) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int NW = 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + lane;
     const int j = blockIdx.y;
     const int q = blockIdx.z;
-    if (col >= a.ncol) return;
+    const bool active = col < a.ncol;
     const int NC = a.ncplx;
     const int k = a.spinor ? q : q / a.nspin;
     const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
-    const double* base = a.part + static_cast<int64_t>(q) * a.prows * a.ncol * NC + static_cast<int64_t>(col) * NC;
+    const double* base =
+        a.part + static_cast<int64_t>(q) * a.prows * a.ncol * NC + static_cast<int64_t>(active ? col : 0) * NC;
     double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
     const int t0 = a.red_ptr[j], t1 = a.red_ptr[j + 1];
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
+    int t = t0 + wave;
+    for (; t + 3 * NW < t1; t += 4 * NW) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const double* p = base + static_cast<int64_t>(a.red_row[t + u]) * a.ncol * NC;
+            const int tt = t + u * NW;
+            const double* p = base + static_cast<int64_t>(a.red_row[tt]) * a.ncol * NC;
             if (NC == 2) {
-                const int im = a.red_img[t + u];
+                const int im = a.red_img[tt];
                 const double pr = ph[2 * im], pi = ph[2 * im + 1];
                 s0[u] += pr * p[0] - pi * p[1];
                 s1[u] += pr * p[1] + pi * p[0];
@@ -71,7 +78,7 @@ __global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs 
             }
         }
     }
-    for (; t < t1; ++t) {
+    for (; t < t1; t += NW) {
         const double* p = base + static_cast<int64_t>(a.red_row[t]) * a.ncol * NC;
         if (NC == 2) {
             const int im = a.red_img[t];
@@ -82,9 +89,14 @@ __global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs 
             s0[0] += p[0];
         }
     }
+    __shared__ double red[NW][64][2];
+    red[wave][lane][0] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+    red[wave][lane][1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    __syncthreads();
+    if (wave != 0 || !active) return;
     double* o = a.out + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + col) * NC;
-    o[0] = a.dV * ((s0[0] + s0[1]) + (s0[2] + s0[3]));
-    if (NC == 2) o[1] = a.dV * ((s1[0] + s1[1]) + (s1[2] + s1[3]));
+    o[0] = a.dV * ((red[0][lane][0] + red[1][lane][0]) + (red[2][lane][0] + red[3][lane][0]));
+    if (NC == 2) o[1] = a.dV * ((red[0][lane][1] + red[1][lane][1]) + (red[2][lane][1] + red[3][lane][1]));
 }
 
 // ---------------------------------------------------------------- N-bar
@@ -109,14 +121,18 @@ __global__ void __launch_bounds__(256) k_nbar(const NbarArgs a) {
 }
 
 // ---------------------------------------------------------------- occupations
-// One work-group per site.  For every block (spin channel, or spinor block
-// sigma sigma'), n_ab = sum_k w_k sum_s f_s conj(c_a) c_b (Eq. occ_matrices)
-// and pbar_ab = the same with the extra weight N-bar_s of the site's species
-// (Eq. notation_Pbar).  States are staged through LDS in tiles of NB; the
-// (a, b) pairs are spread over the threads with several state slices each,
-// and the slices are summed in a fixed order at the end.
-__global__ void __launch_bounds__(NB) k_occ(const OccArgs a) {
+// n_ab = sum_k w_k sum_s f_s conj(c_a) c_b (Eq. occ_matrices) for every
+// block (spin channel, or spinor block sigma sigma') and P-bar_ab, the same
+// with the extra weight N-bar_s of the site's species (Eq. notation_Pbar).
+// Pass 1: work-group (site, channel, split) sums the (k-point, state) pairs
+// of its split: the states are staged through LDS, the (a, b) pairs of the
+// combined matrix are spread over the threads with several state slices
+// each, and the slices are summed in a fixed order into the workspace.
+// Pass 2 sums the splits in order and writes n and P-bar.
+__global__ void __launch_bounds__(NB) k_occ_part(const OccArgs a) {
     const int site = blockIdx.x;
+    const int ch = blockIdx.y;
+    const int split = blockIdx.z;
     const int L = a.site_L[site];
     const int orb0 = a.site_orb0[site];
     const int T = a.site_species[site];
@@ -135,77 +151,95 @@ __global__ void __launch_bounds__(NB) k_occ(const OccArgs a) {
     __shared__ double wt[TILE], wtn[TILE];
     __shared__ double red[NB][4];
 
-    const int nchan = a.spinor ? 1 : a.nspin;
-    for (int ch = 0; ch < nchan; ++ch) {
-        double nr = 0.0, ni = 0.0, pr = 0.0, pi = 0.0;
-        for (int k = 0; k < a.nk; ++k) {
+    // this split's (k, state) pairs, flattened as k * nstates + s
+    const int np = a.nk * a.nstates;
+    const int per = (np + a.nsplit - 1) / a.nsplit;
+    const int p0 = split * per;
+    const int p1 = min(np, p0 + per);
+    double nr = 0.0, ni = 0.0, pr = 0.0, pi = 0.0;
+    for (int t0 = p0; t0 < p1; t0 += TILE) {
+        const int pp = t0 + tid;
+        if (tid >= TILE) {
+        } else if (pp < p1) {
+            const int k = pp / a.nstates, s = pp - k * a.nstates;
             const int q = a.spinor ? k : k * a.nspin + ch;
             const double wk = a.kweights[k];
-            for (int s0 = 0; s0 < a.nstates; s0 += TILE) {
-                const int s = s0 + tid;
-                if (tid >= TILE) {
-                } else if (s < a.nstates) {
-                    const double f = a.f[static_cast<int64_t>(q) * a.nstates + s];
-                    const double nb = (a.nbar != nullptr)
-                                          ? a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s]
-                                          : 0.0;
-                    wt[tid] = wk * f;
-                    wtn[tid] = wk * f * nb;
-                    for (int x = 0; x < nsig; ++x)
-                        for (int m = 0; m < L; ++m) {
-                            const double* p =
-                                a.c + ((static_cast<int64_t>(q) * a.J + orb0 + m) * a.ncol + s * nsig + x) * NC;
-                            cs[x][m][tid][0] = p[0];
-                            cs[x][m][tid][1] = (NC == 2) ? p[1] : 0.0;
-                        }
-                } else {
-                    wt[tid] = 0.0;
-                    wtn[tid] = 0.0;
-                    for (int x = 0; x < nsig; ++x)
-                        for (int m = 0; m < L; ++m) cs[x][m][tid][0] = cs[x][m][tid][1] = 0.0;
+            const double f = a.f[static_cast<int64_t>(q) * a.nstates + s];
+            const double nb =
+                (a.nbar != nullptr) ? a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s] : 0.0;
+            wt[tid] = wk * f;
+            wtn[tid] = wk * f * nb;
+            for (int x = 0; x < nsig; ++x)
+                for (int m = 0; m < L; ++m) {
+                    const double* p = a.c + ((static_cast<int64_t>(q) * a.J + orb0 + m) * a.ncol + s * nsig + x) * NC;
+                    cs[x][m][tid][0] = p[0];
+                    cs[x][m][tid][1] = (NC == 2) ? p[1] : 0.0;
                 }
-                __syncthreads();
-                if (worker) {
-                    const int xa = ra / L, ma = ra % L, xb = rb / L, mb = rb % L;
-                    const int nt = min(TILE, a.nstates - s0);
-                    for (int t = slice; t < nt; t += nslice) {
-                        // conj(c_a) c_b
-                        const double ar = cs[xa][ma][t][0], ai = cs[xa][ma][t][1];
-                        const double br = cs[xb][mb][t][0], bi = cs[xb][mb][t][1];
-                        const double re = ar * br + ai * bi;
-                        const double im = ar * bi - ai * br;
-                        nr = fma(wt[t], re, nr);
-                        ni = fma(wt[t], im, ni);
-                        pr = fma(wtn[t], re, pr);
-                        pi = fma(wtn[t], im, pi);
-                    }
-                }
-                __syncthreads();
-            }
+        } else {
+            wt[tid] = 0.0;
+            wtn[tid] = 0.0;
+            for (int x = 0; x < nsig; ++x)
+                for (int m = 0; m < L; ++m) cs[x][m][tid][0] = cs[x][m][tid][1] = 0.0;
         }
-        red[tid][0] = nr; red[tid][1] = ni; red[tid][2] = pr; red[tid][3] = pi;
         __syncthreads();
-        // write all blocks of this channel (zeros outside the L x L corner)
-        const int nblk_here = a.spinor ? 4 : 1;
-        for (int o = tid; o < nblk_here * 49; o += NB) {
-            const int blk = o / 49, e = o % 49, i = e / 7, j = e % 7;
-            double v[4] = {0.0, 0.0, 0.0, 0.0};
-            if (i < L && j < L) {
-                const int x = a.spinor ? blk / 2 : 0, y = a.spinor ? blk % 2 : 0;
-                const int p = (x * L + i) * ncp + (y * L + j);
-                for (int z = 0; z < nslice; ++z)
-                    for (int r = 0; r < 4; ++r) v[r] += red[z * npairs + p][r];
-            }
-            const int oblk = a.spinor ? blk : ch;
-            const int64_t base = ((static_cast<int64_t>(site) * a.nblk + oblk) * 49 + e) * 2;
-            a.n[base] = v[0];
-            a.n[base + 1] = v[1];
-            if (a.pbar != nullptr) {
-                a.pbar[base] = v[2];
-                a.pbar[base + 1] = v[3];
+        if (worker) {
+            const int xa = ra / L, ma = ra % L, xb = rb / L, mb = rb % L;
+            const int nt = min(TILE, p1 - t0);
+            for (int t = slice; t < nt; t += nslice) {
+                // conj(c_a) c_b
+                const double ar = cs[xa][ma][t][0], ai = cs[xa][ma][t][1];
+                const double br = cs[xb][mb][t][0], bi = cs[xb][mb][t][1];
+                const double re = ar * br + ai * bi;
+                const double im = ar * bi - ai * br;
+                nr = fma(wt[t], re, nr);
+                ni = fma(wt[t], im, ni);
+                pr = fma(wtn[t], re, pr);
+                pi = fma(wtn[t], im, pi);
             }
         }
         __syncthreads();
+    }
+    red[tid][0] = nr;
+    red[tid][1] = ni;
+    red[tid][2] = pr;
+    red[tid][3] = pi;
+    __syncthreads();
+    const int nchan = gridDim.y;
+    double* w = a.ws + ((static_cast<int64_t>(site) * nchan + ch) * a.nsplit + split) * (HUB_OCC_PAIRS * 4);
+    for (int o = tid; o < npairs; o += NB) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int z = 0; z < nslice; ++z)
+            for (int r = 0; r < 4; ++r) v[r] += red[z * npairs + o][r];
+        for (int r = 0; r < 4; ++r) w[o * 4 + r] = v[r];
+    }
+}
+
+__global__ void __launch_bounds__(NB) k_occ_final(const OccArgs a) {
+    const int site = blockIdx.x;
+    const int ch = blockIdx.y;
+    const int nchan = gridDim.y;
+    const int L = a.site_L[site];
+    const int ncp = a.spinor ? 2 * L : L;
+    const double* w = a.ws + (static_cast<int64_t>(site) * nchan + ch) * a.nsplit * (HUB_OCC_PAIRS * 4);
+    // write all blocks of this channel (zeros outside the L x L corner)
+    const int nblk_here = a.spinor ? 4 : 1;
+    for (int o = threadIdx.x; o < nblk_here * 49; o += NB) {
+        const int blk = o / 49, e = o % 49, i = e / 7, j = e % 7;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < L && j < L) {
+            const int x = a.spinor ? blk / 2 : 0, y = a.spinor ? blk % 2 : 0;
+            const int p = (x * L + i) * ncp + (y * L + j);
+            for (int z = 0; z < a.nsplit; ++z)
+                for (int r = 0; r < 4; ++r) v[r] += w[(static_cast<int64_t>(z) * HUB_OCC_PAIRS + p) * 4 + r];
+        }
+        const int oblk = a.spinor ? blk : ch;
+        const int64_t base = ((static_cast<int64_t>(site) * a.nblk + oblk) * 49 + e) * 2;
+        a.n[base] = v[0];
+        a.n[base + 1] = v[1];
+        if (a.pbar != nullptr) {
+            a.pbar[base] = v[2];
+            a.pbar[base + 1] = v[3];
+        }
     }
 }
 
@@ -444,7 +478,7 @@ hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st) {
 
 hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t st) {
     if (a.J <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
-    dim3 grid((a.ncol + 255) / 256, a.J, nq);
+    dim3 grid((a.ncol + 63) / 64, a.J, nq);
     hipLaunchKernelGGL(k_reduce_grouped, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -462,7 +496,9 @@ hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st) {
     b.site_species += site0;
     b.n += static_cast<int64_t>(site0) * a.nblk * 98;
     if (b.pbar) b.pbar += static_cast<int64_t>(site0) * a.nblk * 98;
-    hipLaunchKernelGGL(k_occ, dim3(nsites), dim3(NB), 0, st, b);
+    const int nchan = a.spinor ? 1 : a.nspin;
+    hipLaunchKernelGGL(k_occ_part, dim3(nsites, nchan, a.nsplit), dim3(NB), 0, st, b);
+    hipLaunchKernelGGL(k_occ_final, dim3(nsites, nchan), dim3(NB), 0, st, b);
     return hipGetLastError();
 }
 

@@ -30,13 +30,25 @@ struct NbarArgs {
     const int32_t* species_orb_ptr; const int32_t* species_orb_ids;
 };
 
+// pairs (a, b) of a site's combined occupation matrix (2L x 2L, L <= 7)
+#define HUB_OCC_PAIRS 196
+
 struct OccArgs {
     const double* c; const double* f; const double* nbar;
     double* n; double* pbar;
     const double* kweights;
     const int32_t* site_L; const int32_t* site_orb0; const int32_t* site_species;
     int J; int ncol; int nstates; int ncplx; int spinor; int nspin; int nk; int nblk; int nspecies;
+    int nsplit;               // (k-point, state) splits of the first pass
+    double* ws;               // [site][channel][nsplit][HUB_OCC_PAIRS][4] partial sums
 };
+
+// (k-point, state) splits of the occupation sums: about 64 pairs each
+inline int hub_occ_splits(int nk, int nstates) {
+    const int np = nk * nstates;
+    const int s = (np + 63) / 64;
+    return s < 1 ? 1 : (s > 64 ? 64 : s);
+}
 
 struct Acbn0Args {
     const double* n; const double* pbar; const double* tensor;   // tensor: [site][2401]
