@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--chunk", type=int, default=None, help="sphere entries per work-list chunk")
+    ap.add_argument("--classes", default="merged", choices=["merged", "sequential", "concurrent"],
+                    help="launch policy of the grouped work list's function-count classes")
     ap.add_argument("--worklist", default="grouped", choices=["grouped", "persite"],
                     help="batched work list: every grid point once with all its covers, or per-site layers")
     ap.add_argument("--shapes", default=None,
@@ -154,6 +156,7 @@ def main():
         hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
                         is_complex=cfg.is_complex, precision=prec, chunk=args.chunk)
         hub.set_worklist(args.worklist == "grouped")
+        hub.set_class_launch(args.classes)
         return hub
 
     hub32 = ctx("f32")
@@ -305,6 +308,7 @@ def main():
                                         "kpoints": cfg.nk, "spin": cfg.spin, "states": S,
                                         "mode": "hipGraph per step", "storage": "f32 states, f64 orbital table",
                                         "worklist": args.worklist, "chunk": args.chunk or 512,
+                                        "classes": args.classes,
                                         "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "detail": detail,
     }

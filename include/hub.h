@@ -130,6 +130,24 @@ int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves, int la
  * time. */
 int hub_set_worklist(hub_ctx* ctx, int grouped_list);
 
+/* Launch policy of the grouped work list, whose chunks fall in four classes
+ * by function count (1-4, 5-8, 9-12, 13-16):
+ *   HUB_CLASSES_MERGED      (default) one launch over every chunk, with a
+ *                           kernel that covers every function count
+ *                           (registers sized for the largest); chunks with
+ *                           the longest entry loops are dispatched first;
+ *   HUB_CLASSES_SEQUENTIAL  one launch per class, one after another, each
+ *                           kernel's registers sized for its class;
+ *   HUB_CLASSES_CONCURRENT  one launch per class on side streams forked from
+ *                           and joined back to the context's stream
+ *                           (parallel branches of a captured graph).
+ * Results are identical.  Any time; a captured step graph is rebuilt on the
+ * next graph-mode hub_step. */
+#define HUB_CLASSES_MERGED 0
+#define HUB_CLASSES_SEQUENTIAL 1
+#define HUB_CLASSES_CONCURRENT 2
+int hub_set_class_launch(hub_ctx* ctx, int policy);
+
 /* Build the sphere maps, orbital tables (grid-normalized, dV sum phi^2 = 1,
  * Sec. II), image/phase tables and the work list on the host.  Needs no GPU.
  * Errors: HUB_EINVAL (no sites, or a sphere that holds no grid point),

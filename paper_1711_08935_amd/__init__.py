@@ -43,7 +43,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_set_tuning", "hub_finalize_host", "hub_finalize", "hub_set_stream", "hub_query",
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
-           "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist"]
+           "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -83,6 +83,7 @@ def lib():
         "hub_profile": [P, I],
         "hub_profile_read": [P, P, P],
         "hub_set_worklist": [P, I],
+        "hub_set_class_launch": [P, I],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -206,6 +207,13 @@ class Hubbard:
         """Batched launches over the grouped (cover-signature) work list, or
         over per-site chunks applied in layers."""
         _check(lib().hub_set_worklist(self._ctx, int(bool(grouped))), "hub_set_worklist")
+
+    CLASS_POLICIES = {"merged": 0, "sequential": 1, "concurrent": 2}
+
+    def set_class_launch(self, policy="merged"):
+        """Launch policy of the grouped work list's function-count classes:
+        'merged' (one launch), 'sequential' or 'concurrent' (side streams)."""
+        _check(lib().hub_set_class_launch(self._ctx, self.CLASS_POLICIES[policy]), "hub_set_class_launch")
 
     def set_tuning(self, which, cols_per_lane, waves, layout=-1):
         """Kernel shape of the projection (which=0) or apply (1); layout 1 =

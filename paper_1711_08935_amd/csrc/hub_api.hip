@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -61,6 +62,8 @@ struct hub_ctx {
     double *d_kw = nullptr, *d_ueff_fixed = nullptr, *d_tensor = nullptr;
     // grouped (cover-signature) work list
     bool use_grouped = true;
+    int class_policy = HUB_CLASSES_MERGED;
+    int32_t* d_gall_m = nullptr;             // chunk list of the merged launch
     int gcls_ptr[HUB_NCLASS + 1] = {};       // d_gall[gcls_ptr[k-1], gcls_ptr[k]): chunks of class k
     HubChunk* d_gchunks = nullptr;
     int32_t *d_gall = nullptr, *d_ggidx = nullptr, *d_gf_orb = nullptr, *d_gf_img = nullptr;
@@ -133,7 +136,7 @@ void release(hub_ctx* c) {
     f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
     f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
-    f(c->d_gchunks); f(c->d_gall); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
+    f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -244,24 +247,37 @@ int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
     return cpl;
 }
 
-// Runs launch(k, stream) for every non-empty function-count class k of the
-// grouped work list.  With several classes the launches go to side streams
+// Runs launch(k, list, nchunks, stream) over the grouped work list: once
+// with k = HUB_NCLASS + 1 and the merged chunk list, or once per non-empty
+// function-count class k.  Concurrent class launches go to side streams
 // forked from the context's stream and joined back to it: the classes write
 // disjoint outputs, so their kernels run concurrently (parallel branches of
 // a captured graph).
 template <typename F>
 int run_classes(hub_ctx* c, F&& launch) {
+    if (c->class_policy == HUB_CLASSES_MERGED) {
+        HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m, c->gcls_ptr[HUB_NCLASS], c->stream));
+        return HUB_OK;
+    }
+    auto one = [&](int k, hipStream_t s) {
+        return launch(k, c->d_gall + c->gcls_ptr[k - 1], c->gcls_ptr[k] - c->gcls_ptr[k - 1], s);
+    };
+    // classes with fewer chunks first: their work-groups get CUs before the
+    // largest class fills the chip, so their short grids overlap with it
     int used[HUB_NCLASS], nu = 0;
     for (int k = 1; k <= HUB_NCLASS; ++k)
         if (c->gcls_ptr[k] > c->gcls_ptr[k - 1]) used[nu++] = k;
-    if (nu == 1) {
-        HUB_TRY(launch(used[0], c->stream));
+    std::stable_sort(used, used + nu, [c](int x, int y) {
+        return c->gcls_ptr[x] - c->gcls_ptr[x - 1] < c->gcls_ptr[y] - c->gcls_ptr[y - 1];
+    });
+    if (nu == 1 || c->class_policy == HUB_CLASSES_SEQUENTIAL) {
+        for (int i = 0; i < nu; ++i) HUB_TRY(one(used[i], c->stream));
         return HUB_OK;
     }
     HUB_TRY(hipEventRecord(c->fork_ev, c->stream));
     for (int i = 0; i < nu; ++i) {
         HUB_TRY(hipStreamWaitEvent(c->side[i], c->fork_ev, 0));
-        HUB_TRY(launch(used[i], c->side[i]));
+        HUB_TRY(one(used[i], c->side[i]));
         HUB_TRY(hipEventRecord(c->join_ev[i], c->side[i]));
     }
     for (int i = 0; i < nu; ++i) HUB_TRY(hipStreamWaitEvent(c->stream, c->join_ev[i], 0));
@@ -329,14 +345,12 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         {
             StageTimer tm(c, HUB_STAGE_PROJECT);
             // one launch per function-count class
-            const int st = run_classes(c, [&](int k, hipStream_t s) {
-                const int b0 = c->gcls_ptr[k - 1], b1 = c->gcls_ptr[k];
+            const int st = run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
                 ProjArgs b = a;
-                b.chunk_list = c->d_gall + b0;
-                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), 4 * k);
+                b.chunk_list = list;
+                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), std::min(4 * k, HUB_GF_MAX));
                 b.wide = pick_wide(c, ncol, cpl, 0);
-                return launch_project(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[0], k,
-                                      s);
+                return launch_project(b, nch, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[0], k, s);
             });
             if (st) return st;
         }
@@ -511,13 +525,11 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
         a.f_img = c->d_gf_img;
         StageTimer tm(c, HUB_STAGE_APPLY);
         // one launch per function-count class; the classes hold disjoint points
-        return run_classes(c, [&](int k, hipStream_t s) {
-            const int b0 = c->gcls_ptr[k - 1], b1 = c->gcls_ptr[k];
+        return run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
             ApplyArgs b = a;
-            b.chunk_list = c->d_gall + b0;
-            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), 4 * k);
-            return launch_apply_grouped(b, b1 - b0, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k,
-                                        s);
+            b.chunk_list = list;
+            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), std::min(4 * k, HUB_GF_MAX));
+            return launch_apply_grouped(b, nch, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
         });
     }
     const int cpl = pick_cpl(c, hpsi, ld, 1);
@@ -664,6 +676,13 @@ int hub_set_worklist(hub_ctx* c, int grouped_list) {
     return HUB_OK;
 }
 
+int hub_set_class_launch(hub_ctx* c, int policy) {
+    if (!c || policy < HUB_CLASSES_MERGED || policy > HUB_CLASSES_CONCURRENT) return HUB_EINVAL;
+    if (c->class_policy != policy) drop_graph(c);
+    c->class_policy = policy;
+    return HUB_OK;
+}
+
 int hub_set_tuning(hub_ctx* c, int which, int cpl, int waves, int layout) {
     if (!c || (which != 0 && which != 1)) return HUB_EINVAL;
     if (cpl != 0 && cpl != 1 && cpl != 2 && cpl != 4) return HUB_EINVAL;
@@ -750,6 +769,15 @@ int hub_finalize(hub_ctx* c, void* stream) {
         }
         up(&c->d_gchunks, T.grouped.chunks);
         up(&c->d_gall, gall);
+        // merged launch: chunks with more functions (fewer entries per batch,
+        // longer entry loops) and more entries first
+        std::vector<int32_t> gm(gall);
+        std::stable_sort(gm.begin(), gm.end(), [&T](int32_t x, int32_t y) {
+            const HubChunk &X = T.grouped.chunks[x], &Y = T.grouped.chunks[y];
+            const int kx = hub_nf_class(X.L) > 2, ky = hub_nf_class(Y.L) > 2;
+            return kx != ky ? kx > ky : X.ne > Y.ne;
+        });
+        up(&c->d_gall_m, gm);
         up(&c->d_ggidx, T.grouped.gidx);
         up(&c->d_gtab, T.grouped.tab);
         up(&c->d_gf_orb, T.grouped.f_orb);

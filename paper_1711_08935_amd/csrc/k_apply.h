@@ -265,22 +265,39 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t*
 // Grouped chunks: L is the number of concatenated functions of the chunk's
 // covering sites, 4(CLS-1) < L <= 4 CLS; every grid point lies in one chunk,
 // so the launches of the classes write disjoint points.
+// CLS = HUB_NCLASS + 1: merged launch over every function count.
 template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, int CLS>
 __global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const int32_t* __restrict__ gidx,
                                                        const double* __restrict__ tab, T* __restrict__ hpsi) {
     constexpr int NV = CPL * (CPX ? 2 : 1);
-    __shared__ double Bs[4 * CLS * NV * HUB_WAVE];
+    constexpr int NFMAX = CLS > HUB_NCLASS ? HUB_GF_MAX : 4 * CLS;
+    __shared__ double Bs[NFMAX * NV * HUB_WAVE];
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
     const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
-    constexpr int B = 4 * (CLS - 1);
-    switch (C.L - B) {
-    case 1: apply_body<T, CPX, SPINOR, CPL, B + 1, WIDE, true>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    case 2: apply_body<T, CPX, SPINOR, CPL, B + 2, WIDE, true>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    case 3: apply_body<T, CPX, SPINOR, CPL, B + 3, WIDE, true>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    case 4: apply_body<T, CPX, SPINOR, CPL, B + 4, WIDE, true>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    default: break;
+#define HUB_ACALL(n) \
+    apply_body<T, CPX, SPINOR, CPL, (n), WIDE, true>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs)
+#define HUB_ACASE(n) \
+    case n: HUB_ACALL(n); break;
+    if constexpr (CLS > HUB_NCLASS) {
+        switch (C.L) {
+            HUB_ACASE(1) HUB_ACASE(2) HUB_ACASE(3) HUB_ACASE(4) HUB_ACASE(5) HUB_ACASE(6) HUB_ACASE(7)
+            HUB_ACASE(8) HUB_ACASE(9) HUB_ACASE(10) HUB_ACASE(11) HUB_ACASE(12) HUB_ACASE(13) HUB_ACASE(14)
+            HUB_ACASE(15) HUB_ACASE(16)
+        default: break;
+        }
+    } else {
+        constexpr int B = 4 * (CLS - 1);
+        switch (C.L - B) {
+        case 1: HUB_ACALL(B + 1); break;
+        case 2: HUB_ACALL(B + 2); break;
+        case 3: HUB_ACALL(B + 3); break;
+        case 4: HUB_ACALL(B + 4); break;
+        default: break;
+        }
     }
+#undef HUB_ACASE
+#undef HUB_ACALL
 }
 
 // The grouped apply is built in the one-set-per-wave layout only (uniform
@@ -288,7 +305,7 @@ __global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const 
 template <typename T, bool CPX, bool SPINOR, int CPL, int CLS>
 hipError_t launch_tg(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
     // a lane's FP64 coefficients (functions x scalars) stay within 96 values
-    if constexpr (4 * CLS * CPL * (CPX ? 2 : 1) > 96) {
+    if constexpr ((CLS > HUB_NCLASS ? HUB_GF_MAX : 4 * CLS) * CPL * (CPX ? 2 : 1) > 96) {
         return hipErrorInvalidValue;
     } else {
         const int64_t cg = (a.ncol + CPL - 1) / CPL;
@@ -366,6 +383,7 @@ hipError_t launch_apply_grouped_prec(const ApplyArgs& a, int nchunks, int nq, in
     case 2: return launch_kg<T, 2>(a, nchunks, nq, cplx, cpl, waves, st);
     case 3: return launch_kg<T, 3>(a, nchunks, nq, cplx, cpl, waves, st);
     case 4: return launch_kg<T, 4>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_NCLASS + 1: return launch_kg<T, HUB_NCLASS + 1>(a, nchunks, nq, cplx, cpl, waves, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -41,7 +41,9 @@ struct ProjLds {
 };
 
 template <typename T, int NV, int NF, bool WIDE>
-__device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C, int tile, ProjLds<NV>& lds) {
+__device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C, int tile,
+                                             const int32_t* __restrict__ gidx, const double* __restrict__ tab,
+                                             double* __restrict__ part, ProjLds<NV>& lds) {
     constexpr int U = hub_batch_rows(NV, NF);
     const int lane = threadIdx.x & (HUB_WAVE - 1);
     // wave index made provably uniform so entry data goes through scalar loads
@@ -71,8 +73,8 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     // this wave's entries: e0 + [lo, lo + nj) of the chunk
     int lo, nj;
     hub_wave_range(C.ne, nw, wave, lo, nj);
-    const int32_t* __restrict__ gi = a.gidx + C.e0 + lo;
-    const double* __restrict__ tb = a.tab + (C.phi0 * a.tabmult + static_cast<int64_t>(lo) * NF);
+    const int32_t* __restrict__ gi = gidx + C.e0 + lo;
+    const double* __restrict__ tb = tab + (C.phi0 * a.tabmult + static_cast<int64_t>(lo) * NF);
     const int lofs = colc * NC;                                      // lane offset inside a row
 
     double acc[NF][NV];
@@ -150,7 +152,7 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
         }
     }
     if (wave != 0 || !active) return;
-    double* __restrict__ out = a.part + (static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.tabmult) *
+    double* __restrict__ out = part + (static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.tabmult) *
                                             a.ncol * NC;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -165,8 +167,12 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 // NV = scalars per lane (columns per lane times 1 or 2); GRAD selects the
 // gradient table (three functions per orbital); WIDE the lane layout; CLS
 // the function-count class of the launched chunks (0: per-site chunks).
+// The tables and the output are separate restrict-qualified arguments, so
+// the compiler can keep the uniform table reads on scalar loads (a store
+// through a pointer that may alias them would force per-lane loads).
 template <typename T, int NV, bool GRAD, bool WIDE, int CLS>
-__global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
+__global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t* __restrict__ gidx,
+                                                 const double* __restrict__ tab, double* __restrict__ part) {
     __shared__ ProjLds<NV> lds;
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
@@ -174,28 +180,40 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
     const int tile = slot.tile;
     if constexpr (GRAD) {
         switch (C.L) {
-        case 1: project_body<T, NV, 3, WIDE>(a, C, tile, lds); break;
-        case 3: project_body<T, NV, 9, WIDE>(a, C, tile, lds); break;
-        case 5: project_body<T, NV, 15, WIDE>(a, C, tile, lds); break;
-        case 7: project_body<T, NV, 21, WIDE>(a, C, tile, lds); break;
+        case 1: project_body<T, NV, 3, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 3: project_body<T, NV, 9, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 5: project_body<T, NV, 15, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 7: project_body<T, NV, 21, WIDE>(a, C, tile, gidx, tab, part, lds); break;
         default: break;
         }
     } else if constexpr (CLS == 0) {
         switch (C.L) {
-        case 1: project_body<T, NV, 1, WIDE>(a, C, tile, lds); break;
-        case 3: project_body<T, NV, 3, WIDE>(a, C, tile, lds); break;
-        case 5: project_body<T, NV, 5, WIDE>(a, C, tile, lds); break;
-        case 7: project_body<T, NV, 7, WIDE>(a, C, tile, lds); break;
+        case 1: project_body<T, NV, 1, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 3: project_body<T, NV, 3, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 5: project_body<T, NV, 5, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 7: project_body<T, NV, 7, WIDE>(a, C, tile, gidx, tab, part, lds); break;
         default: break;
         }
+    } else if constexpr (CLS > HUB_NCLASS) {
+        // merged launch: every function count of the grouped list
+#define HUB_PCASE(n) \
+    case n: project_body<T, NV, n, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        switch (C.L) {
+            HUB_PCASE(1) HUB_PCASE(2) HUB_PCASE(3) HUB_PCASE(4) HUB_PCASE(5) HUB_PCASE(6) HUB_PCASE(7)
+            HUB_PCASE(8) HUB_PCASE(9) HUB_PCASE(10) HUB_PCASE(11) HUB_PCASE(12) HUB_PCASE(13) HUB_PCASE(14)
+            HUB_PCASE(15) HUB_PCASE(16)
+        default: break;
+        }
+#undef HUB_PCASE
     } else {
-        // grouped chunks: the concatenated orbitals of the covering sites
+        // grouped chunks of one class: the concatenated orbitals of the
+        // covering sites
         constexpr int B = 4 * (CLS - 1);
         switch (C.L - B) {
-        case 1: project_body<T, NV, B + 1, WIDE>(a, C, tile, lds); break;
-        case 2: project_body<T, NV, B + 2, WIDE>(a, C, tile, lds); break;
-        case 3: project_body<T, NV, B + 3, WIDE>(a, C, tile, lds); break;
-        case 4: project_body<T, NV, B + 4, WIDE>(a, C, tile, lds); break;
+        case 1: project_body<T, NV, B + 1, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 2: project_body<T, NV, B + 2, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 3: project_body<T, NV, B + 3, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 4: project_body<T, NV, B + 4, WIDE>(a, C, tile, gidx, tab, part, lds); break;
         default: break;
         }
     }
@@ -203,7 +221,9 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a) {
 
 // Largest function count of a class (class 0: per-site chunks, L <= 7; the
 // gradient table holds 3L functions).
-constexpr int proj_nf_max(bool grad, int cls) { return grad ? 21 : (cls == 0 ? 7 : 4 * cls); }
+constexpr int proj_nf_max(bool grad, int cls) {
+    return grad ? 21 : (cls == 0 ? 7 : (cls > HUB_NCLASS ? HUB_GF_MAX : 4 * cls));
+}
 
 template <typename T, int NV, bool GRAD, int CLS>
 hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
@@ -218,9 +238,11 @@ hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, 
                                           : (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE);
         const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
         if (a.wide)
-            hipLaunchKernelGGL((k_project<T, NV, GRAD, true, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b);
+            hipLaunchKernelGGL((k_project<T, NV, GRAD, true, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
+                               b.tab, b.part);
         else
-            hipLaunchKernelGGL((k_project<T, NV, GRAD, false, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b);
+            hipLaunchKernelGGL((k_project<T, NV, GRAD, false, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
+                               b.tab, b.part);
         return hipGetLastError();
     }
 }
@@ -238,7 +260,7 @@ hipError_t launch_g(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, i
 }
 
 // Launch the projection for storage type T (orbital or gradient table) over
-// chunks of function-count class cls.
+// chunks of function-count class cls (HUB_NCLASS + 1: every class).
 template <typename T>
 hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
                                hipStream_t st) {
@@ -251,6 +273,7 @@ hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx,
     case 2: return launch_g<T, false, 2>(a, nchunks, nq, cplx, cpl, waves, st);
     case 3: return launch_g<T, false, 3>(a, nchunks, nq, cplx, cpl, waves, st);
     case 4: return launch_g<T, false, 4>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_NCLASS + 1: return launch_g<T, false, HUB_NCLASS + 1>(a, nchunks, nq, cplx, cpl, waves, st);
     default: return hipErrorInvalidValue;
     }
 }

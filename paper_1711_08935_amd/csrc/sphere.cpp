@@ -357,12 +357,15 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
         GT.nfmax = nfmax;
         GT.ok = ok;
         if (ok) {
-            const int chunk = std::max(1, chunk_entries);
             int64_t rows = 0, tab0 = 0;
             for (const auto& sig : order) {
                 const std::vector<size_t>& firsts = groups[sig];
                 int nf = 0;
                 for (const auto& sl : sig) nf += T.site_L[sl.first];
+                // more than 8 functions: the kernels take half as many entries
+                // per batch, so half-length chunks keep the per-wave chains
+                // (and the launches' latency) comparable
+                const int chunk = std::max(1, nf > 8 ? std::max(64, chunk_entries / 2) : chunk_entries);
                 for (size_t b = 0; b < firsts.size(); b += chunk) {
                     const size_t nb = std::min(firsts.size() - b, static_cast<size_t>(chunk));
                     const size_t np = (nb + HUB_ENTRY_ALIGN - 1) / HUB_ENTRY_ALIGN * HUB_ENTRY_ALIGN;
