@@ -217,3 +217,26 @@ def test_worklists_agree(case):
     # the layered apply rounds FP32 output once per layer (up to 3 here)
     bar = 1e-13 if case["prec"] == "f64" else 4 * 2.0 ** -24 * 1.5
     assert normwise(h.cpu().numpy(), case["hpsi"].cpu().numpy()) < bar
+
+
+def test_class_launch_policies_agree(case):
+    """Merged, sequential and concurrent launches of the grouped work list's
+    function-count classes perform the same arithmetic per column (entry
+    order, wave split and reduction order do not depend on the policy)."""
+    hub = case["hub"]
+    psi_d = case["psi_d"]
+    outs = {}
+    try:
+        for pol in ("sequential", "concurrent", "merged"):
+            hub.set_class_launch(pol)
+            c = hub.project(psi_d)
+            h = torch.zeros_like(psi_d)
+            hub.apply(case["Ueff"], case["n"], case["c"], h)
+            torch.cuda.synchronize()
+            outs[pol] = (c, h)
+    finally:
+        hub.set_class_launch("merged")
+    for pol in ("sequential", "concurrent"):
+        assert torch.equal(outs[pol][0], outs["merged"][0]), pol
+        assert torch.equal(outs[pol][1], outs["merged"][1]), pol
+    assert torch.equal(outs["merged"][0], case["c"])
