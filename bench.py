@@ -202,6 +202,24 @@ def main():
     value = args.steps / hub_time
     log(f"f32 graph: {value:.1f} steps/s ({hub_time / args.steps * 1e3:.3f} ms/step, wall {wall:.3f} s)")
 
+    forces_on = None
+    if cfg.name == "forces_fcc":
+        # Hubbard forces (Sec. IV) after every step: gradient projections
+        # <grad phi|psi> and the force contraction, eager launches
+        for _ in range(2):
+            hub32.step(psi32, f_d, hpsi32, mode="graph", bufs=bufs32)
+            hub32.forces(psi32, bufs32["c"], f_d, bufs32["Ueff"], bufs32["n"])
+        torch.cuda.synchronize()
+        fe0, fe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fe0.record()
+        for _ in range(args.steps):
+            hub32.step(psi32, f_d, hpsi32, mode="graph", bufs=bufs32)
+            hub32.forces(psi32, bufs32["c"], f_d, bufs32["Ueff"], bufs32["n"])
+        fe1.record()
+        torch.cuda.synchronize()
+        forces_on = args.steps / (fe0.elapsed_time(fe1) * 1e-3)
+        log(f"f32 graph step + forces: {forces_on:.1f} steps/s")
+
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -226,6 +244,9 @@ def main():
     del src, dst
 
     detail = {"coulomb_setup_ms": round(coulomb_s * 1e3, 2), "device_copy_GBs": round(copy_GBs, 1)}
+    if forces_on is not None:
+        detail["forces_off_steps_per_s"] = round(value, 2)
+        detail["forces_on_steps_per_s"] = round(forces_on, 2)
     if tuned is not None:
         detail["tuned_shapes"] = {"project": list(tuned["project"][0]), "apply": list(tuned["apply"][0]),
                                   "candidates_ms": tuned["table"]}

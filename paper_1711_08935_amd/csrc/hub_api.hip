@@ -364,6 +364,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         r.red_ptr = c->d_gred_ptr;
         r.red_row = c->d_gred_row;
         r.red_img = c->d_gred_img;
+        r.rows_per_orbital = GT.red_ptr.empty() ? 0 : GT.red_ptr.back() / std::max(1, c->T.J);
         r.phase = c->d_phase;
         r.nimg = static_cast<int>(c->T.images.size() / 3);
         r.nspin = c->nspin();

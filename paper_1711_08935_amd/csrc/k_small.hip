@@ -44,11 +44,12 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
 
 // Grouped work list: out[q][j][col] = dV sum over the workspace rows that
 // belong to orbital j of exp(+i k.T_row) part[q][row][col].  A work-group
-// serves 64 columns of one (j, q); its four waves take interleaved rows with
-// four independent partial sums each (many loads in flight), and the sixteen
-// partial sums are combined in a fixed order.
-__global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs a) {
-    constexpr int NW = 4;
+// serves 64 columns of one (j, q); its RW waves take interleaved rows with
+// four independent partial sums each (many loads in flight), and the partial
+// sums are combined in a fixed order.  RW follows the rows per orbital.
+constexpr int RW = 16;   // waves of the N-bar kernel and of the wide reduction
+template <int RW>
+__global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = blockIdx.x * 64 + lane;
@@ -63,10 +64,10 @@ __global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs 
     double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
     const int t0 = a.red_ptr[j], t1 = a.red_ptr[j + 1];
     int t = t0 + wave;
-    for (; t + 3 * NW < t1; t += 4 * NW) {
+    for (; t + 3 * RW < t1; t += 4 * RW) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int tt = t + u * NW;
+            const int tt = t + u * RW;
             const double* p = base + static_cast<int64_t>(a.red_row[tt]) * a.ncol * NC;
             if (NC == 2) {
                 const int im = a.red_img[tt];
@@ -78,7 +79,7 @@ __global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs 
             }
         }
     }
-    for (; t < t1; t += NW) {
+    for (; t < t1; t += RW) {
         const double* p = base + static_cast<int64_t>(a.red_row[t]) * a.ncol * NC;
         if (NC == 2) {
             const int im = a.red_img[t];
@@ -89,35 +90,59 @@ __global__ void __launch_bounds__(256) k_reduce_grouped(const ReduceGroupedArgs 
             s0[0] += p[0];
         }
     }
-    __shared__ double red[NW][64][2];
+    __shared__ double red[RW][64][2];
     red[wave][lane][0] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
     red[wave][lane][1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
     __syncthreads();
     if (wave != 0 || !active) return;
+    double r0 = 0.0, r1 = 0.0;
+    for (int w = 0; w < RW; ++w) {
+        r0 += red[w][lane][0];
+        r1 += red[w][lane][1];
+    }
     double* o = a.out + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + col) * NC;
-    o[0] = a.dV * ((red[0][lane][0] + red[1][lane][0]) + (red[2][lane][0] + red[3][lane][0]));
-    if (NC == 2) o[1] = a.dV * ((red[0][lane][1] + red[1][lane][1]) + (red[2][lane][1] + red[3][lane][1]));
+    o[0] = a.dV * r0;
+    if (NC == 2) o[1] = a.dV * r1;
 }
 
 // ---------------------------------------------------------------- N-bar
-// nbar[q][T][s] = sum_{j in species T} sum_{columns of s} |c[q][j][col]|^2
-__global__ void __launch_bounds__(256) k_nbar(const NbarArgs a) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// nbar[q][T][s] = sum_{j in species T} sum_{columns of s} |c[q][j][col]|^2.
+// A work-group serves 64 states of one (T, q); its RW waves take
+// interleaved orbitals with four independent sums each, combined in order.
+__global__ void __launch_bounds__(RW * 64) k_nbar(const NbarArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int s = blockIdx.x * 64 + lane;
     const int T = blockIdx.y;
     const int q = blockIdx.z;
-    if (s >= a.nstates) return;
+    const bool active = s < a.nstates;
     const int NC = a.ncplx;
     const int cps = a.spinor ? 2 : 1;
-    double acc = 0.0;
-    for (int t = a.species_orb_ptr[T]; t < a.species_orb_ptr[T + 1]; ++t) {
-        const int j = a.species_orb_ids[t];
+    const double* cq = a.c + static_cast<int64_t>(q) * a.J * a.ncol * NC + static_cast<int64_t>(active ? s : 0) * cps * NC;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int t0 = a.species_orb_ptr[T], t1 = a.species_orb_ptr[T + 1];
+    int t = t0 + wave;
+    auto term = [&](int tt) {
+        const double* p = cq + static_cast<int64_t>(a.species_orb_ids[tt]) * a.ncol * NC;
+        double v = 0.0;
         for (int x = 0; x < cps; ++x) {
-            const double* p = a.c + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + s * cps + x) * NC;
-            acc = fma(p[0], p[0], acc);
-            if (NC == 2) acc = fma(p[1], p[1], acc);
+            v = fma(p[x * NC], p[x * NC], v);
+            if (NC == 2) v = fma(p[x * NC + 1], p[x * NC + 1], v);
         }
+        return v;
+    };
+    for (; t + 3 * RW < t1; t += 4 * RW) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += term(t + u * RW);
     }
-    a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s] = acc;
+    for (; t < t1; t += RW) acc[0] += term(t);
+    __shared__ double red[RW][64];
+    red[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (wave != 0 || !active) return;
+    double r = 0.0;
+    for (int w = 0; w < RW; ++w) r += red[w][lane];
+    a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s] = r;
 }
 
 // ---------------------------------------------------------------- occupations
@@ -479,13 +504,18 @@ hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st) {
 hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t st) {
     if (a.J <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
     dim3 grid((a.ncol + 63) / 64, a.J, nq);
-    hipLaunchKernelGGL(k_reduce_grouped, grid, dim3(256), 0, st, a);
+    // many rows per orbital (overlapping spheres, small chunks): 16 waves
+    if (a.rows_per_orbital >= 64)
+        hipLaunchKernelGGL(k_reduce_grouped<16>, grid, dim3(16 * 64), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_reduce_grouped<4>, grid, dim3(4 * 64), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_nbar(const NbarArgs& a, int nq, hipStream_t st) {
-    dim3 grid((a.nstates + 255) / 256, a.nspecies, nq);
-    hipLaunchKernelGGL(k_nbar, grid, dim3(256), 0, st, a);
+    if (a.nstates <= 0 || nq <= 0) return hipSuccess;
+    dim3 grid((a.nstates + 63) / 64, a.nspecies, nq);
+    hipLaunchKernelGGL(k_nbar, grid, dim3(RW * 64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -159,10 +159,14 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[N]) {
 
 // Rows per batch of the software-pipelined entry loops: the two batches of
 // U rows of NV values per lane stay within 32 values, and the orbital values
-// of one batch (U x NF doubles, uniform, held in scalar registers) within 32.
+// of one batch (U x NF doubles, uniform, held in scalar registers) within
+// HUB_TAB_BUDGET.
+#ifndef HUB_TAB_BUDGET
+#define HUB_TAB_BUDGET 32
+#endif
 __host__ __device__ constexpr int hub_batch_rows(int nv, int nf) {
     int u = 8;
-    while (u > 1 && (u * nv > 16 || u * nf > 32)) u /= 2;
+    while (u > 1 && (u * nv > 16 || u * nf > HUB_TAB_BUDGET)) u /= 2;
     return u;
 }
 

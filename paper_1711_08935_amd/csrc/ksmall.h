@@ -22,6 +22,7 @@ struct ReduceGroupedArgs {
     const int32_t* red_ptr; const int32_t* red_row; const int32_t* red_img;
     const double* phase; int nimg; int nspin; int spinor;
     double dV;
+    int rows_per_orbital;     // average workspace rows per orbital (host)
 };
 
 struct NbarArgs {
