@@ -236,6 +236,29 @@ int hub_energy(hub_ctx* ctx, const double* Ueff, const double* n, double* EU);
 int hub_forces(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
                const double* f, const double* Ueff, const double* n, double* F);
 
+/* Velocity gauge (Sec. V): with a uniform vector potential A (host array of
+ * 3, bohr^-1; NULL switches the field off), the projections and the apply
+ * of every later call and graph replay use V^A = exp(-i A.r) V_U exp(i A.r):
+ * the phase of sphere point p is exp(i (k+A).T_p) exp(i A.r_g), r_g the
+ * cell grid point and T_p its lattice image (r_p = r_g + T_p, the unfolded
+ * point).  Complex contexts only (HUB_EINVAL otherwise).  The device tables
+ * are updated on the context's stream, so a captured step graph stays valid
+ * while the field is on; switching it on or off rebuilds the graph at the
+ * next graph-mode hub_step.  With a field the grouped work list is launched
+ * merged, and hub_forces uses the same phases. */
+int hub_set_vector_potential(hub_ctx* ctx, const double* A);
+
+/* DFT+U current correction of the velocity gauge (Sec. V, read with the
+ * factor i of the velocity operator i[H, r] restored), per site and
+ * Cartesian component: J[I][i] = g_s * 2 Im sum_q w_k sum_s f_s sum_a
+ * conj(rho_{a,i}) sum_b V_ab c_b = sum w f <psi| i[V^A, r] |psi> restricted
+ * to site I, with the position moments about the site centre
+ * rho_{a,i} = dV sum_p exp(i k.T_p) exp(i A.r_p) (r_p - R_I)_i phi_a(p)
+ * psi[g(p)] and c from hub_project under the same field; g_s = 2 for
+ * unpolarized contexts, else 1.  psi, c, f, Ueff, n, J: device. */
+int hub_current(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
+                const double* f, const double* Ueff, const double* n, double* J);
+
 /* One whole Hubbard step (the metric's unit of work): project -> occupations
  * (n, N-bar, P-bar) -> U-bar, J-bar, U_eff (or fixed U) -> hpsi += alpha V_U psi.
  * All pointers are device pointers owned by the caller; see the layouts

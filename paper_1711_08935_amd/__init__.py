@@ -43,7 +43,8 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_set_tuning", "hub_finalize_host", "hub_finalize", "hub_set_stream", "hub_query",
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
-           "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch"]
+           "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
+           "hub_set_vector_potential", "hub_current"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -77,6 +78,7 @@ def lib():
         "hub_apply": [P, P, P, P, I, P, D, P, I64],
         "hub_energy": [P, P, P, P],
         "hub_forces": [P, P, I64, I, P, P, P, P, P],
+        "hub_current": [P, P, I64, I, P, P, P, P, P],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -84,6 +86,7 @@ def lib():
         "hub_profile_read": [P, P, P],
         "hub_set_worklist": [P, I],
         "hub_set_class_launch": [P, I],
+        "hub_set_vector_potential": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -333,6 +336,27 @@ class Hubbard:
         self._stream()
         _check(lib().hub_energy(self._ctx, _dptr(Ueff), _dptr(n), _dptr(EU)), "hub_energy")
         return EU
+
+    def set_vector_potential(self, A=None):
+        """Uniform vector potential A (3 floats, bohr^-1) of the velocity
+        gauge for later projections, applies and steps; None switches the
+        field off."""
+        if A is None:
+            self._stream()
+            _check(lib().hub_set_vector_potential(self._ctx, None), "hub_set_vector_potential")
+            return
+        arr = (ctypes.c_double * 3)(*[float(x) for x in A])
+        self._stream()
+        _check(lib().hub_set_vector_potential(self._ctx, arr), "hub_set_vector_potential")
+
+    def current(self, psi, c, f, Ueff, n, nstates=None):
+        """Velocity-gauge DFT+U current correction per site, (n_sites, 3) FP64."""
+        ld, S = self._states(psi, nstates)
+        J = torch.empty((self.nsites, 3), dtype=torch.float64, device="cuda")
+        self._stream()
+        _check(lib().hub_current(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)), _dptr(Ueff),
+                                 _dptr(n), _dptr(J)), "hub_current")
+        return J
 
     def forces(self, psi, c, f, Ueff, n, nstates=None):
         ld, S = self._states(psi, nstates)

@@ -79,6 +79,14 @@ struct hub_ctx {
     size_t sink_cap = 0;
     double* d_occ_ws = nullptr;              // partial occupation sums
     size_t occ_cap = 0;
+    // velocity gauge (uniform vector potential A, Sec. V); off by default
+    bool gauge = false;
+    double A[3] = {0.0, 0.0, 0.0};
+    double* d_pg = nullptr;                  // [G] exp(i A.r_g)
+    double* d_mphi = nullptr;                // per-site position-moment table
+    int32_t* d_images = nullptr;             // lattice images (3 ints each)
+    double* d_kred = nullptr;                // reduced k-points (3 each)
+    std::vector<double> phase_host;          // exp(i k.T) without a field
     double* d_grad = nullptr;
     size_t grad_cap = 0;
     double* d_nbar_ws = nullptr;
@@ -136,6 +144,8 @@ void release(hub_ctx* c) {
     f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
     f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
+    f(c->d_pg); f(c->d_mphi); f(c->d_images); f(c->d_kred);
+    c->d_pg = nullptr;
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -255,7 +265,8 @@ int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
 // a captured graph).
 template <typename F>
 int run_classes(hub_ctx* c, F&& launch) {
-    if (c->class_policy == HUB_CLASSES_MERGED) {
+    // the velocity-gauge kernels are built for the merged launch only
+    if (c->class_policy == HUB_CLASSES_MERGED || c->gauge) {
         HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m, c->gcls_ptr[HUB_NCLASS], c->stream));
         return HUB_OK;
     }
@@ -284,7 +295,12 @@ int run_classes(hub_ctx* c, F&& launch) {
     return HUB_OK;
 }
 
-ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad) {
+// Orbital table of a projection: values, gradients (forces) or position
+// moments about the site centre (velocity-gauge current).
+enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2 };
+
+ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table) {
+    const bool grad = table != TAB_PHI;
     ProjArgs a{};
     a.psi = psi;
     a.ld = ld;
@@ -295,9 +311,10 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, bool grad)
     a.chunks = c->d_chunks;
     a.chunk_list = c->d_all;
     a.gidx = c->d_gidx;
-    a.tab = grad ? c->d_gphi : c->d_phi;
+    a.tab = table == TAB_GRAD ? c->d_gphi : (table == TAB_MOMENT ? c->d_mphi : c->d_phi);
     a.tabmult = grad ? 3 : 1;
     a.prows = c->T.part_rows * a.tabmult;
+    a.pg = c->gauge ? c->d_pg : nullptr;
     return a;
 }
 
@@ -329,12 +346,14 @@ size_t part_need(const hub_ctx* c, int ncol, int mult) {
     return static_cast<size_t>(c->nsets()) * rows * ncol * c->ncplx();
 }
 
-int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site, bool grad) {
+int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site,
+               int table = TAB_PHI) {
+    const bool grad = table != TAB_PHI;
     const int ncol = c->ncol(nstates);
     const int mult = grad ? 3 : 1;
     int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, mult), c);
     if (st) return st;
-    ProjArgs a = proj_args(c, psi, ld, ncol, grad);
+    ProjArgs a = proj_args(c, psi, ld, ncol, table);
     a.part = c->d_part;
     if (!per_site && !grad && grouped(c)) {
         const GroupTables& GT = c->T.grouped;
@@ -495,6 +514,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     ApplyArgs a{};
     a.hpsi = hpsi;
     a.sink = c->d_sink;
+    a.pg = c->gauge ? c->d_pg : nullptr;
     a.ld = ld;
     a.qstride = c->G() * ld * c->ncplx();
     a.ncol = ncol;
@@ -560,7 +580,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
 }
 
 int run_step(hub_ctx* c, const hub_step_io* io, bool per_site) {
-    int st = do_project(c, io->psi, io->ld, io->nstates, io->c, per_site, false);
+    int st = do_project(c, io->psi, io->ld, io->nstates, io->c, per_site);
     if (st) return st;
     st = do_occupations(c, io->c, io->nstates, io->f, io->n, io->pbar, io->nbar, per_site);
     if (st) return st;
@@ -714,6 +734,10 @@ int hub_finalize_host(hub_ctx* c) {
     return HUB_OK;
 }
 
+namespace {
+int gauge_tables(hub_ctx* c);
+}  // namespace
+
 int hub_finalize(hub_ctx* c, void* stream) {
     if (!c) return HUB_EINVAL;
     int st = hub_finalize_host(c);
@@ -747,6 +771,9 @@ int hub_finalize(hub_ctx* c, void* stream) {
     up(&c->d_img, T.img);
     up(&c->d_phi, T.phi);
     up(&c->d_gphi, T.gphi);
+    up(&c->d_mphi, T.mphi);
+    up(&c->d_images, T.images);
+    up(&c->d_kred, c->kred);
     up(&c->d_phase, phase);
     up(&c->d_site_chunk_ptr, T.site_chunk_ptr);
     up(&c->d_site_chunk_ids, T.site_chunk_ids);
@@ -801,7 +828,9 @@ int hub_finalize(hub_ctx* c, void* stream) {
         release(c);
         return map_err(e);
     }
+    c->phase_host = phase;
     c->built_dev = true;
+    if (c->gauge) return gauge_tables(c);
     return HUB_OK;
 }
 
@@ -861,7 +890,7 @@ int hub_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* co
     if (!c || !cout) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
-    return do_project(c, psi, ld, nstates, cout, false, false);
+    return do_project(c, psi, ld, nstates, cout, false);
 }
 
 int hub_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, double* n, double* pbar,
@@ -953,16 +982,21 @@ int hub_energy(hub_ctx* c, const double* Ueff, const double* n, double* EU) {
     return HUB_OK;
 }
 
-int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
-               const double* Ueff, const double* n, double* F) {
-    if (!c || !cc || !f || !Ueff || !n || !F) return HUB_EINVAL;
+namespace {
+
+// Forces (table TAB_GRAD, real part) or velocity-gauge current (TAB_MOMENT,
+// imaginary part): out[site][i] = 2 g sum w f Re/Im sum_a conj(d_{a,i}) B_a,
+// with d the projections of the psi on the table's 3L functions per site.
+int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
+                     const double* Ueff, const double* n, double* out, int table) {
+    if (!c || !cc || !f || !Ueff || !n || !out) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
     const int ncol = c->ncol(nstates);
     const size_t need = static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx();
     int st = ensure(&c->d_grad, &c->grad_cap, need, c);
     if (st) return st;
-    st = do_project(c, psi, ld, nstates, c->d_grad, false, true);
+    st = do_project(c, psi, ld, nstates, c->d_grad, false, table);
     if (st) return st;
     ForceArgs a{};
     a.c = cc;
@@ -971,7 +1005,7 @@ int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const doubl
     a.n = n;
     a.ueff = Ueff;
     a.kweights = c->d_kw;
-    a.F = F;
+    a.F = out;
     a.site_L = c->d_site_L;
     a.site_orb0 = c->d_site_orb0;
     a.nsites = c->T.nsites;
@@ -983,9 +1017,63 @@ int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const doubl
     a.nspin = c->nspin();
     a.nq = c->nsets();
     a.nblk = c->nblk();
+    a.imag = table == TAB_MOMENT;
     StageTimer tm(c, HUB_STAGE_FORCES);
     HUB_TRY(launch_forces(a, c->stream));
     return HUB_OK;
+}
+
+// Gauge tables on the device: with a field, the image phases at k + A and
+// the grid-point phases; without one, the plain image phases again.
+int gauge_tables(hub_ctx* c) {
+    if (!c->gauge) {
+        HUB_TRY(hipMemcpyAsync(c->d_phase, c->phase_host.data(), c->phase_host.size() * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+        return HUB_OK;
+    }
+    if (!c->d_pg) HUB_TRY(hipMalloc(reinterpret_cast<void**>(&c->d_pg), static_cast<size_t>(c->G()) * 2 * sizeof(double)));
+    GaugeArgs g{};
+    for (int i = 0; i < 3; ++i) {
+        g.A[i] = c->A[i];
+        g.cell[i] = c->cell[i];
+        g.h[i] = c->cell[i] / c->ngrid[i];
+        g.ngrid[i] = c->ngrid[i];
+    }
+    g.images = c->d_images;
+    g.nimg = static_cast<int>(c->T.images.size() / 3);
+    g.kred = c->d_kred;
+    g.nk = c->nk;
+    g.phase = c->d_phase;
+    g.pg = c->d_pg;
+    HUB_TRY(launch_gauge_tables(g, c->stream));
+    return HUB_OK;
+}
+
+}  // namespace
+
+int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
+               const double* Ueff, const double* n, double* F) {
+    return contract_moments(c, psi, ld, nstates, cc, f, Ueff, n, F, TAB_GRAD);
+}
+
+int hub_current(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
+                const double* Ueff, const double* n, double* J) {
+    return contract_moments(c, psi, ld, nstates, cc, f, Ueff, n, J, TAB_MOMENT);
+}
+
+int hub_set_vector_potential(hub_ctx* c, const double* A) {
+    if (!c) return HUB_EINVAL;
+    if (A) {
+        if (!c->is_complex) return HUB_EINVAL;
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(A[i])) return HUB_EINVAL;
+    }
+    const bool on = A != nullptr;
+    if (on != c->gauge) drop_graph(c);
+    c->gauge = on;
+    for (int i = 0; i < 3; ++i) c->A[i] = on ? A[i] : 0.0;
+    if (!c->built_dev) return HUB_OK;
+    return gauge_tables(c);
 }
 
 int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {

@@ -79,6 +79,7 @@ struct HostTables {
     std::vector<int32_t> gidx, img;          // per entry
     std::vector<double> phi;                 // per entry, L values
     std::vector<double> gphi;                // per entry, 3L values [m][i]
+    std::vector<double> mphi;                // per entry, 3L values [m][i]: (r_p - R)_i phi_m
     std::vector<int32_t> images;             // unique lattice images, 3 per image
     std::vector<int32_t> site_chunk_ptr;     // CSR site -> chunk ids
     std::vector<int32_t> site_chunk_ids;

@@ -14,6 +14,9 @@
 // grid point in one chunk with all its covering functions), so no two lanes
 // in flight update the same element: no atomics, deterministic results.
 // Sums are FP64; the updated element is rounded once to the storage type.
+// Velocity gauge (GAUGE, Sec. V): the entry's update is rotated by the
+// conjugate grid-point phase exp(-i A.r_g); the image part of the field's
+// phase is in the coefficients' Bloch phase exp(-i (k+A).T).
 //
 // Work mapping: a 1-D grid of (chunk, column tile) work-groups, the tiles of
 // a chunk consecutive on one XCD (hub_slot), with the same two lane layouts
@@ -113,10 +116,10 @@ __device__ __forceinline__ void coefficient(const ApplyArgs& a, int site, int ai
 
 // Bs: LDS of the work-group, at least L * NV * HUB_WAVE doubles.
 // chunk: the chunk's index in the work-group's launch list; tile: column tile
-template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE, bool GROUPED>
+template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE, bool GROUPED, bool GAUGE>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C, int chunk_slot, int tile,
                                            const int32_t* __restrict__ gidx, const double* __restrict__ tab,
-                                           T* __restrict__ hpsi, double* Bs) {
+                                           const double* __restrict__ pg, T* __restrict__ hpsi, double* Bs) {
     constexpr int NC = CPX ? 2 : 1;
     constexpr int NV = CPL * NC;
     constexpr int U = hub_batch_rows(NV, L);
@@ -185,12 +188,18 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
         return j < nreal ? h_q + static_cast<int64_t>(g) * a.ld * NC + lofs : sink;
     };
     T* rp[2][U];                                                     // row addresses of the two buffers
-    auto load_batch = [&](int b, T (&r)[U][NV], T* (&p)[U]) {
+    // grid-point phases of a batch (velocity gauge; unused otherwise)
+    double ph[2][U][2];
+    auto load_batch = [&](int b, T (&r)[U][NV], T* (&p)[U], double (&phb)[U][2]) {
         const int32_t* __restrict__ gb = gi + b * U;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             p[u] = row_ptr(b * U + u, gb[u]);
             load_row<T, NV>(p[u], r[u]);
+            if constexpr (GAUGE) {
+                phb[u][0] = pg[2 * static_cast<int64_t>(gb[u])];
+                phb[u][1] = pg[2 * static_cast<int64_t>(gb[u]) + 1];
+            }
         }
     };
     auto read_tab = [&](int b, double (&w)[U][L]) {
@@ -200,7 +209,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
 #pragma unroll
             for (int ai = 0; ai < L; ++ai) w[u][ai] = wb[u * L + ai];
     };
-    auto update_batch = [&](const double (&w)[U][L], const T (&r)[U][NV], T* const (&p)[U]) {
+    auto update_batch = [&](const double (&w)[U][L], const T (&r)[U][NV], T* const (&p)[U],
+                            const double (&phb)[U][2]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double add[NV];
@@ -210,6 +220,14 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
             for (int ai = 0; ai < L; ++ai)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) add[v] = fma(w[u][ai], B[ai][v], add[v]);
+            if constexpr (GAUGE) {
+#pragma unroll
+                for (int v = 0; v + 1 < NV; v += 2) {
+                    const double xr = add[v], xi = add[v + 1];
+                    add[v] = xr * phb[u][0] + xi * phb[u][1];
+                    add[v + 1] = xi * phb[u][0] - xr * phb[u][1];
+                }
+            }
             T out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) out[v] = static_cast<T>(static_cast<double>(r[u][v]) + add[v]);
@@ -223,21 +241,21 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     if (nbt > 0) {
         T ra[U][NV], rb[U][NV];
         double w[U][L];
-        load_batch(0, ra, rp[0]);
+        load_batch(0, ra, rp[0], ph[0]);
         int b = 0;
         for (; b + 2 <= nbt; b += 2) {
             read_tab(b, w);
-            load_batch(b + 1, rb, rp[1]);
+            load_batch(b + 1, rb, rp[1], ph[1]);
             __builtin_amdgcn_sched_barrier(0);
-            update_batch(w, ra, rp[0]);
+            update_batch(w, ra, rp[0], ph[0]);
             read_tab(b + 1, w);
-            load_batch(b + 2 < nbt ? b + 2 : nbt - 1, ra, rp[0]);
+            load_batch(b + 2 < nbt ? b + 2 : nbt - 1, ra, rp[0], ph[0]);
             __builtin_amdgcn_sched_barrier(0);
-            update_batch(w, rb, rp[1]);
+            update_batch(w, rb, rp[1], ph[1]);
         }
         if (b < nbt) {
             read_tab(b, w);
-            update_batch(w, ra, rp[0]);
+            update_batch(w, ra, rp[0], ph[0]);
         }
     }
 }
@@ -245,19 +263,23 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
 // The sphere tables and the output are separate restrict-qualified kernel
 // arguments: the stores into hpsi inside the entry loop then cannot alias the
 // table reads, and the uniform entry data stays on scalar loads.
-template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE>
+template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, bool GAUGE>
 __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t* __restrict__ gidx,
-                                               const double* __restrict__ tab, T* __restrict__ hpsi) {
+                                               const double* __restrict__ tab, const double* __restrict__ pg,
+                                               T* __restrict__ hpsi) {
     constexpr int NV = CPL * (CPX ? 2 : 1);
     __shared__ double Bs[7 * NV * HUB_WAVE];
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
     const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
     switch (C.L) {
-    case 1: apply_body<T, CPX, SPINOR, CPL, 1, WIDE, false>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    case 3: apply_body<T, CPX, SPINOR, CPL, 3, WIDE, false>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    case 5: apply_body<T, CPX, SPINOR, CPL, 5, WIDE, false>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
-    case 7: apply_body<T, CPX, SPINOR, CPL, 7, WIDE, false>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs); break;
+#define HUB_PCALL(n) \
+    apply_body<T, CPX, SPINOR, CPL, n, WIDE, false, GAUGE>(a, C, slot.chunk, slot.tile, gidx, tab, pg, hpsi, Bs)
+    case 1: HUB_PCALL(1); break;
+    case 3: HUB_PCALL(3); break;
+    case 5: HUB_PCALL(5); break;
+    case 7: HUB_PCALL(7); break;
+#undef HUB_PCALL
     default: break;
     }
 }
@@ -266,9 +288,10 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t*
 // covering sites, 4(CLS-1) < L <= 4 CLS; every grid point lies in one chunk,
 // so the launches of the classes write disjoint points.
 // CLS = HUB_NCLASS + 1: merged launch over every function count.
-template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, int CLS>
+template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, int CLS, bool GAUGE>
 __global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const int32_t* __restrict__ gidx,
-                                                       const double* __restrict__ tab, T* __restrict__ hpsi) {
+                                                       const double* __restrict__ tab, const double* __restrict__ pg,
+                                                       T* __restrict__ hpsi) {
     constexpr int NV = CPL * (CPX ? 2 : 1);
     constexpr int NFMAX = CLS > HUB_NCLASS ? HUB_GF_MAX : 4 * CLS;
     __shared__ double Bs[NFMAX * NV * HUB_WAVE];
@@ -276,7 +299,7 @@ __global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const 
     if (slot.chunk >= a.nchunks) return;
     const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
 #define HUB_ACALL(n) \
-    apply_body<T, CPX, SPINOR, CPL, (n), WIDE, true>(a, C, slot.chunk, slot.tile, gidx, tab, hpsi, Bs)
+    apply_body<T, CPX, SPINOR, CPL, (n), WIDE, true, GAUGE>(a, C, slot.chunk, slot.tile, gidx, tab, pg, hpsi, Bs)
 #define HUB_ACASE(n) \
     case n: HUB_ACALL(n); break;
     if constexpr (CLS > HUB_NCLASS) {
@@ -312,9 +335,18 @@ hipError_t launch_tg(const ApplyArgs& a, int nchunks, int nq, int waves, hipStre
         ApplyArgs b = a;
         b.nchunks = nchunks;
         b.tiles = static_cast<int>(static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE));
-        hipLaunchKernelGGL((k_apply_grouped<T, CPX, SPINOR, CPL, true, CLS>),
-                           dim3(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles))), dim3(HUB_WAVE * waves), 0,
-                           st, b, b.gidx, b.tab, reinterpret_cast<T*>(b.hpsi));
+        const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
+        if (a.pg) {
+            // velocity gauge: complex states, merged launch only
+            if constexpr (CPX && CLS > HUB_NCLASS)
+                hipLaunchKernelGGL((k_apply_grouped<T, CPX, SPINOR, CPL, true, CLS, true>), grid,
+                                   dim3(HUB_WAVE * waves), 0, st, b, b.gidx, b.tab, b.pg, reinterpret_cast<T*>(b.hpsi));
+            else
+                return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_apply_grouped<T, CPX, SPINOR, CPL, true, CLS, false>), grid, dim3(HUB_WAVE * waves),
+                               0, st, b, b.gidx, b.tab, b.pg, reinterpret_cast<T*>(b.hpsi));
+        }
         return hipGetLastError();
     }
 }
@@ -344,12 +376,26 @@ hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStrea
     b.tiles = static_cast<int>(a.wide ? static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE)
                                       : (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE);
     const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
-    if (a.wide)
-        hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, true>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx, b.tab,
-                           reinterpret_cast<T*>(b.hpsi));
-    else
-        hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, false>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
-                           b.tab, reinterpret_cast<T*>(b.hpsi));
+    T* h = reinterpret_cast<T*>(b.hpsi);
+    if (a.pg) {
+        // velocity gauge: complex states only
+        if constexpr (CPX) {
+            if (a.wide)
+                hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, true, true>), grid, dim3(HUB_WAVE * waves), 0, st, b,
+                                   b.gidx, b.tab, b.pg, h);
+            else
+                hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, false, true>), grid, dim3(HUB_WAVE * waves), 0, st, b,
+                                   b.gidx, b.tab, b.pg, h);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (a.wide) {
+        hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, true, false>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
+                           b.tab, b.pg, h);
+    } else {
+        hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, false, false>), grid, dim3(HUB_WAVE * waves), 0, st, b,
+                           b.gidx, b.tab, b.pg, h);
+    }
     return hipGetLastError();
 }
 

@@ -25,6 +25,9 @@
 // batch are in flight while a batch is contracted.  Products and sums are
 // FP64 for both storage precisions; for complex states the real orbital
 // value multiplies the real and imaginary parts (2 FMAs per column).
+// Velocity gauge (GAUGE, Sec. V): each complex row value is first rotated by
+// the entry's grid-point phase exp(i A.r_g); the image part exp(i A.T) of
+// the field's phase is in the reduction's Bloch phase exp(i (k+A).T).
 //
 // This header holds the kernel templates; each storage precision is
 // instantiated in a translation unit of its own.
@@ -40,10 +43,11 @@ struct ProjLds {
     double red[3][HUB_WAVE][NV];
 };
 
-template <typename T, int NV, int NF, bool WIDE>
+template <typename T, int NV, int NF, bool WIDE, bool GAUGE>
 __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& C, int tile,
                                              const int32_t* __restrict__ gidx, const double* __restrict__ tab,
-                                             double* __restrict__ part, ProjLds<NV>& lds) {
+                                             const double* __restrict__ pg, double* __restrict__ part,
+                                             ProjLds<NV>& lds) {
     constexpr int U = hub_batch_rows(NV, NF);
     const int lane = threadIdx.x & (HUB_WAVE - 1);
     // wave index made provably uniform so entry data goes through scalar loads
@@ -87,10 +91,17 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     // HUB_ENTRY_ALIGN, so every wave's share is); padding entries carry zero
     // orbital values
     const int nbt = nj / U;
-    auto load_batch = [&](int b, T (&r)[U][NV]) {
+    // grid-point phases of a batch (velocity gauge; unused otherwise)
+    auto load_batch = [&](int b, T (&r)[U][NV], double (&ph)[U][2]) {
         const int32_t* __restrict__ gb = gi + b * U;
 #pragma unroll
-        for (int u = 0; u < U; ++u) load_row<T, NV>(psi_q + static_cast<int64_t>(gb[u]) * a.ld * NC + lofs, r[u]);
+        for (int u = 0; u < U; ++u) {
+            load_row<T, NV>(psi_q + static_cast<int64_t>(gb[u]) * a.ld * NC + lofs, r[u]);
+            if constexpr (GAUGE) {
+                ph[u][0] = pg[2 * static_cast<int64_t>(gb[u])];
+                ph[u][1] = pg[2 * static_cast<int64_t>(gb[u]) + 1];
+            }
+        }
     };
     auto read_tab = [&](int b, double (&w)[U][NF]) {
         const double* __restrict__ wb = tb + static_cast<int64_t>(b) * U * NF;
@@ -99,13 +110,25 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 #pragma unroll
             for (int f = 0; f < NF; ++f) w[u][f] = wb[u * NF + f];
     };
-    auto fma_batch = [&](const double (&w)[U][NF], const T (&r)[U][NV]) {
+    auto fma_batch = [&](const double (&w)[U][NF], const T (&r)[U][NV], const double (&ph)[U][2]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            double x[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) x[v] = static_cast<double>(r[u][v]);
+            if constexpr (GAUGE) {
+#pragma unroll
+                for (int v = 0; v + 1 < NV; v += 2) {
+                    const double xr = x[v], xi = x[v + 1];
+                    x[v] = xr * ph[u][0] - xi * ph[u][1];
+                    x[v + 1] = xr * ph[u][1] + xi * ph[u][0];
+                }
+            }
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) acc[f][v] = fma(w[u][f], static_cast<double>(r[u][v]), acc[f][v]);
+                for (int v = 0; v < NV; ++v) acc[f][v] = fma(w[u][f], x[v], acc[f][v]);
+        }
     };
     // Two-stage pipeline with a branch-free body (a conditional use of a
     // buffer would let the compiler sink its loads next to the use); the
@@ -115,22 +138,23 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     // loads ahead of the contraction.
     if (nbt > 0) {
         T ra[U][NV], rb[U][NV];
+        double pa[U][2], pb[U][2];
         double w[U][NF];
-        load_batch(0, ra);
+        load_batch(0, ra, pa);
         int b = 0;
         for (; b + 2 <= nbt; b += 2) {
             read_tab(b, w);
-            load_batch(b + 1, rb);
+            load_batch(b + 1, rb, pb);
             __builtin_amdgcn_sched_barrier(0);
-            fma_batch(w, ra);
+            fma_batch(w, ra, pa);
             read_tab(b + 1, w);
-            load_batch(b + 2 < nbt ? b + 2 : nbt - 1, ra);
+            load_batch(b + 2 < nbt ? b + 2 : nbt - 1, ra, pa);
             __builtin_amdgcn_sched_barrier(0);
-            fma_batch(w, rb);
+            fma_batch(w, rb, pb);
         }
         if (b < nbt) {
             read_tab(b, w);
-            fma_batch(w, ra);
+            fma_batch(w, ra, pa);
         }
     }
 
@@ -170,9 +194,10 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 // The tables and the output are separate restrict-qualified arguments, so
 // the compiler can keep the uniform table reads on scalar loads (a store
 // through a pointer that may alias them would force per-lane loads).
-template <typename T, int NV, bool GRAD, bool WIDE, int CLS>
+template <typename T, int NV, bool GRAD, bool WIDE, int CLS, bool GAUGE>
 __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t* __restrict__ gidx,
-                                                 const double* __restrict__ tab, double* __restrict__ part) {
+                                                 const double* __restrict__ tab, const double* __restrict__ pg,
+                                                 double* __restrict__ part) {
     __shared__ ProjLds<NV> lds;
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
@@ -180,24 +205,24 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
     const int tile = slot.tile;
     if constexpr (GRAD) {
         switch (C.L) {
-        case 1: project_body<T, NV, 3, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 3: project_body<T, NV, 9, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 5: project_body<T, NV, 15, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 7: project_body<T, NV, 21, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 1: project_body<T, NV, 3, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 3: project_body<T, NV, 9, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 5: project_body<T, NV, 15, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 7: project_body<T, NV, 21, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
         default: break;
         }
     } else if constexpr (CLS == 0) {
         switch (C.L) {
-        case 1: project_body<T, NV, 1, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 3: project_body<T, NV, 3, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 5: project_body<T, NV, 5, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 7: project_body<T, NV, 7, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 1: project_body<T, NV, 1, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 3: project_body<T, NV, 3, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 5: project_body<T, NV, 5, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 7: project_body<T, NV, 7, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
         default: break;
         }
     } else if constexpr (CLS > HUB_NCLASS) {
         // merged launch: every function count of the grouped list
 #define HUB_PCASE(n) \
-    case n: project_body<T, NV, n, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+    case n: project_body<T, NV, n, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
         switch (C.L) {
             HUB_PCASE(1) HUB_PCASE(2) HUB_PCASE(3) HUB_PCASE(4) HUB_PCASE(5) HUB_PCASE(6) HUB_PCASE(7)
             HUB_PCASE(8) HUB_PCASE(9) HUB_PCASE(10) HUB_PCASE(11) HUB_PCASE(12) HUB_PCASE(13) HUB_PCASE(14)
@@ -210,10 +235,10 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
         // covering sites
         constexpr int B = 4 * (CLS - 1);
         switch (C.L - B) {
-        case 1: project_body<T, NV, B + 1, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 2: project_body<T, NV, B + 2, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 3: project_body<T, NV, B + 3, WIDE>(a, C, tile, gidx, tab, part, lds); break;
-        case 4: project_body<T, NV, B + 4, WIDE>(a, C, tile, gidx, tab, part, lds); break;
+        case 1: project_body<T, NV, B + 1, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 2: project_body<T, NV, B + 2, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 3: project_body<T, NV, B + 3, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 4: project_body<T, NV, B + 4, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
         default: break;
         }
     }
@@ -223,6 +248,16 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
 // gradient table holds 3L functions).
 constexpr int proj_nf_max(bool grad, int cls) {
     return grad ? 21 : (cls == 0 ? 7 : (cls > HUB_NCLASS ? HUB_GF_MAX : 4 * cls));
+}
+
+template <typename T, int NV, bool GRAD, int CLS, bool GAUGE>
+void launch_k(const ProjArgs& b, dim3 grid, int waves, hipStream_t st) {
+    if (b.wide)
+        hipLaunchKernelGGL((k_project<T, NV, GRAD, true, CLS, GAUGE>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
+                           b.tab, b.pg, b.part);
+    else
+        hipLaunchKernelGGL((k_project<T, NV, GRAD, false, CLS, GAUGE>), grid, dim3(HUB_WAVE * waves), 0, st, b,
+                           b.gidx, b.tab, b.pg, b.part);
 }
 
 template <typename T, int NV, bool GRAD, int CLS>
@@ -237,12 +272,15 @@ hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, 
         b.tiles = static_cast<int>(a.wide ? static_cast<int64_t>(nq) * ((cg + HUB_WAVE - 1) / HUB_WAVE)
                                           : (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE);
         const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
-        if (a.wide)
-            hipLaunchKernelGGL((k_project<T, NV, GRAD, true, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
-                               b.tab, b.part);
-        else
-            hipLaunchKernelGGL((k_project<T, NV, GRAD, false, CLS>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
-                               b.tab, b.part);
+        if (a.pg) {
+            // velocity gauge: complex states, per-site or merged chunk lists
+            if constexpr (NV % 2 == 0 && (CLS == 0 || CLS > HUB_NCLASS))
+                launch_k<T, NV, GRAD, CLS, true>(b, grid, waves, st);
+            else
+                return hipErrorInvalidValue;
+        } else {
+            launch_k<T, NV, GRAD, CLS, false>(b, grid, waves, st);
+        }
         return hipGetLastError();
     }
 }

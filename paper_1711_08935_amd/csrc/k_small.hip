@@ -3,6 +3,8 @@
 // U-bar/J-bar, Dudarev energy and Hubbard forces.  All reductions run in a
 // fixed order (no atomics), so results are bitwise reproducible.
 
+#include <algorithm>
+
 #include "ksmall.h"
 
 namespace {
@@ -474,7 +476,7 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
             for (int i = 0; i < 3; ++i) {
                 const double* dp = a.d + ((static_cast<int64_t>(q) * a.J * 3 + (orb0 + ai) * 3 + i) * a.ncol + col) * NC;
                 const double dr = dp[0], di = (NC == 2) ? dp[1] : 0.0;
-                acc[i] += wf * (dr * br + di * bi);           // Re(conj(d) B)
+                acc[i] += wf * (a.imag ? (dr * bi - di * br) : (dr * br + di * bi));   // Re or Im of conj(d) B
             }
         }
     }
@@ -492,7 +494,48 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- gauge
+// Tables of the velocity-gauge phases (Sec. V): the image phases with the
+// crystal momentum shifted by A and the phase of every cell grid point.
+__global__ void __launch_bounds__(256) k_gauge_tables(const GaugeArgs a) {
+    const int64_t G = static_cast<int64_t>(a.ngrid[0]) * a.ngrid[1] * a.ngrid[2];
+    const int64_t nph = static_cast<int64_t>(a.nk) * a.nimg;
+    const double two_pi = 6.283185307179586;
+    for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < G + nph;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double t;
+        double* out;
+        if (o < G) {
+            const int64_t iz = o % a.ngrid[2];
+            const int64_t iy = (o / a.ngrid[2]) % a.ngrid[1];
+            const int64_t ix = o / (static_cast<int64_t>(a.ngrid[2]) * a.ngrid[1]);
+            t = (a.A[0] * (ix * a.h[0]) + a.A[1] * (iy * a.h[1])) + a.A[2] * (iz * a.h[2]);
+            out = a.pg + 2 * o;
+        } else {
+            const int64_t j = o - G;
+            const int k = static_cast<int>(j / a.nimg), im = static_cast<int>(j % a.nimg);
+            const int32_t* n = a.images + 3 * im;
+            const double* kr = a.kred + 3 * k;
+            t = 0.0;
+            for (int i = 0; i < 3; ++i) t += two_pi * (kr[i] * n[i]) + a.A[i] * (n[i] * a.cell[i]);
+            out = a.phase + 2 * j;
+        }
+        double sv, cv;
+        sincos(t, &sv, &cv);
+        out[0] = cv;
+        out[1] = sv;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gauge_tables(const GaugeArgs& a, hipStream_t st) {
+    const int64_t total = static_cast<int64_t>(a.ngrid[0]) * a.ngrid[1] * a.ngrid[2] +
+                          static_cast<int64_t>(a.nk) * a.nimg;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_gauge_tables, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st) {
     if (a.nrows <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;

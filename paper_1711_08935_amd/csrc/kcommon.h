@@ -21,10 +21,11 @@ struct ProjArgs {
     const int32_t* chunk_list;
     const int32_t* gidx;
     const double* tab;        // orbital table (or gradient table)
-    int tabmult;              // 1: phi, 3: grad phi
+    int tabmult;              // 1: phi, 3: grad phi or position moments
     int wide;                 // 1: one state set per wave; 0: sets packed across lanes
     int nchunks;              // chunks in chunk_list (set by the launcher)
     int tiles;                // column tiles per chunk (set by the launcher)
+    const double* pg;         // velocity gauge: [G] exp(i A.r_g) (re, im), or null
     double* part;             // [nq][prows][ncol] (x2 complex)
     int64_t prows;            // rows per state set = part_rows * tabmult
 };
@@ -55,6 +56,7 @@ struct ApplyArgs {
     int wide;                 // 1: one state set per wave; 0: sets packed across lanes
     int nchunks;              // chunks in chunk_list (set by the launcher)
     int tiles;                // column tiles per chunk (set by the launcher)
+    const double* pg;         // velocity gauge: [G] exp(i A.r_g) (re, im), or null
     // grouped chunks: per chunk HUB_GF_MAX (orbital j, image) pairs
     const int32_t* f_orb;
     const int32_t* f_img;

@@ -68,6 +68,20 @@ struct ForceArgs {
     const double* kweights; double* F;
     const int32_t* site_L; const int32_t* site_orb0;
     int nsites; int J; int ncol; int nstates; int ncplx; int spinor; int nspin; int nq; int nblk;
+    int imag;                 // 0: 2 Re sum conj(d) B (forces); 1: 2 Im (current)
+};
+
+// Velocity-gauge tables for a uniform vector potential A:
+// phase[k][img] = exp(i (k + A).T_img), pg[g] = exp(i A.r_g).
+struct GaugeArgs {
+    double A[3];
+    double cell[3];
+    double h[3];
+    int ngrid[3];
+    const int32_t* images; int nimg;     // lattice images (3 ints each)
+    const double* kred; int nk;          // reduced k-points (3 each)
+    double* phase;                       // [nk][nimg] (re, im)
+    double* pg;                          // [G] (re, im)
 };
 
 struct CoulombArgs {
@@ -87,4 +101,5 @@ hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st);
 hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t st);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
 hipError_t launch_forces(const ForceArgs& a, hipStream_t st);
+hipError_t launch_gauge_tables(const GaugeArgs& a, hipStream_t st);
 hipError_t launch_coulomb(const CoulombArgs& a, hipStream_t st);

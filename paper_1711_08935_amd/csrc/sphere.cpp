@@ -288,6 +288,12 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     for (int m = 0; m < L; ++m) T.phi.push_back(sp.phi[p * L + m]);
                     for (int m = 0; m < L; ++m)
                         for (int i = 0; i < 3; ++i) T.gphi.push_back(sp.grad[(p * L + m) * 3 + i]);
+                    // position moments about the site centre (velocity-gauge current)
+                    for (int m = 0; m < L; ++m)
+                        for (int i = 0; i < 3; ++i) {
+                            const double di = static_cast<double>(sp.ijk[3 * p + i]) * h[i] - sites[s].R[i];
+                            T.mphi.push_back(di * sp.phi[p * L + m]);
+                        }
                 }
                 // padding entries: the last grid point again, zero values
                 for (size_t t = nb; t < np; ++t) {
@@ -295,6 +301,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     T.img.push_back(T.img.back());
                     T.phi.insert(T.phi.end(), L, 0.0);
                     T.gphi.insert(T.gphi.end(), 3 * L, 0.0);
+                    T.mphi.insert(T.mphi.end(), 3 * L, 0.0);
                 }
                 e += static_cast<int64_t>(np);
                 nreal += static_cast<int64_t>(nb);

@@ -1,0 +1,123 @@
+"""GPU parity of the velocity-gauge path (Sec. V) against the FP64 oracle.
+
+Complex k-point workloads (collinear NiO-like, noncollinear spinors) in
+both storage precisions under a generic uniform vector potential A:
+projections c^A, the apply V^A psi, the current correction and the step
+graph replayed while A changes.  Bars as in test_gpu_parity.py: 1e-12
+normwise for FP64 states and for the FP64 arithmetic of FP32 states (c, J),
+2e-7 for V^A psi stored in FP32.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1711_08935_amd as H  # noqa: E402
+from oracle import gauge as GA  # noqa: E402
+from oracle import occupations as OCC  # noqa: E402
+from oracle import potential as POT  # noqa: E402
+from oracle import projection as OP  # noqa: E402
+from synth import make_config  # noqa: E402
+from tests.gpu_common import c_to_oracle, device_states, make_hub, states_and_occupations  # noqa: E402
+from tests.helpers import normwise, to_system  # noqa: E402
+
+A1 = np.array([0.137, -0.291, 0.083])
+A2 = np.array([-0.05, 0.12, 0.31])
+CASES = [("nio_afm", "f64"), ("nio_afm", "f32"), ("spinor_layers", "f64"), ("spinor_layers", "f32")]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[f"{a}-{b}" for a, b in CASES])
+def case(request):
+    name, prec = request.param
+    print(f"\n[gauge case] {name} {prec}", flush=True)
+    cfg = make_config(name, small=True)
+    psi, f = states_and_occupations(cfg)
+    hub = make_hub(cfg, prec, chunk=256)
+    psi_d, psi_used = device_states(hub, psi)
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    f_d = torch.from_numpy(f).cuda()
+    ueff = np.array([0.3, 0.25, 0.1, 0.12, 0.2, 0.15, 0.22][:hub.nsites])
+    ueff_d = torch.from_numpy(ueff).cuda()
+    hub.coulomb(-1)
+    c_plain = hub.project(psi_d).clone()
+    yield dict(cfg=cfg, hub=hub, psi_d=psi_d, psi_used=psi_used, f=f, f_d=f_d, sys=sys_, sps=sps, ueff=ueff,
+               ueff_d=ueff_d, c_plain=c_plain)
+    hub.set_vector_potential(None)
+
+
+def _oracle_V(sys_, c, f, ueff):
+    n, _, _ = OCC.occupations(sys_, c, f, with_pbar=False)
+    return [POT.potential_matrix(sys_, u, nn) for u, nn in zip(ueff, n)]
+
+
+def test_gauge_projection_apply_current(case):
+    hub, sys_, sps = case["hub"], case["sys"], case["sps"]
+    hub.set_vector_potential(A1)
+    c = hub.project(case["psi_d"])
+    n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
+    h = torch.zeros_like(case["psi_d"])
+    hub.apply(case["ueff_d"], n, c, h)
+    J = hub.current(case["psi_d"], c, case["f_d"], case["ueff_d"], n)
+    torch.cuda.synchronize()
+    cref = GA.project_gauge(sys_, case["psi_used"], sps, A1)
+    assert normwise(c_to_oracle(hub, c), cref) < 1e-12
+    V = _oracle_V(sys_, cref, case["f"], case["ueff"])
+    href = GA.apply_gauge(sys_, cref, V, sps, A1)
+    bar = 1e-12 if hub.precision == "f64" else 2e-7
+    assert normwise(h.cpu().numpy(), href) < bar
+    Jref = GA.current(sys_, cref, GA.moment_projections(sys_, case["psi_used"], sps, A1), V, case["f"])
+    assert np.max(np.abs(Jref)) > 1e-8
+    assert normwise(J.cpu().numpy(), Jref) < 1e-11
+
+
+def test_field_off_restores_plain_results(case):
+    hub = case["hub"]
+    hub.set_vector_potential(A1)
+    hub.project(case["psi_d"])
+    hub.set_vector_potential(None)
+    c = hub.project(case["psi_d"])
+    torch.cuda.synchronize()
+    assert torch.equal(c, case["c_plain"])
+    # a zero field takes the gauge kernels and agrees with the plain path
+    hub.set_vector_potential([0.0, 0.0, 0.0])
+    c0 = hub.project(case["psi_d"])
+    torch.cuda.synchronize()
+    hub.set_vector_potential(None)
+    assert normwise(c0.cpu().numpy(), case["c_plain"].cpu().numpy()) < 1e-13
+
+
+def test_graph_replays_follow_the_field(case):
+    hub = case["hub"]
+    psi_d, f_d = case["psi_d"], case["f_d"]
+    S = case["cfg"].nstates
+    bufs = hub.step_buffers(S)
+    try:
+        for A in (A1, A2, A1):
+            hub.set_vector_potential(A)
+            hb = torch.zeros_like(psi_d)
+            ref = hub.step(psi_d, f_d, hb, mode="batched")
+            torch.cuda.synchronize()
+            hg = torch.zeros_like(psi_d)
+            hub.step(psi_d, f_d, hg, mode="graph", bufs=bufs)
+            torch.cuda.synchronize()
+            assert torch.equal(hg, hb)
+            assert torch.equal(bufs["c"], ref["c"])
+            assert torch.equal(bufs["U"], ref["U"])
+        # the step's projections are the oracle's gauge projections at A1
+        cref = GA.project_gauge(case["sys"], case["psi_used"], case["sps"], A1)
+        assert normwise(c_to_oracle(hub, bufs["c"]), cref) < 1e-12
+    finally:
+        hub.set_vector_potential(None)
+
+
+def test_real_context_has_no_gauge_form():
+    cfg = make_config("gamma_d", small=True)
+    hub = make_hub(cfg, "f64")
+    with pytest.raises(H.HubError):
+        hub.set_vector_potential(A1)
