@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--shapes", default=None,
                     help="fixed kernel shapes PCPL,PWAVES,PLAYOUT,ACPL,AWAVES,ALAYOUT instead of autotuning "
                          "(profiling runs use the shapes the autotuner picked)")
+    ap.add_argument("--no-gauge", action="store_true",
+                    help="skip the velocity-gauge timing (complex workloads)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB three times (counter calibration)")
     return ap.parse_args()
@@ -220,6 +222,37 @@ def main():
         forces_on = args.steps / (fe0.elapsed_time(fe1) * 1e-3)
         log(f"f32 graph step + forces: {forces_on:.1f} steps/s")
 
+    gauge = None
+    if cfg.is_complex and not args.no_gauge:
+        # real-time velocity gauge (Sec. V): a new uniform A(t) before every
+        # step (device tables updated on the stream, then the graph replay),
+        # without and with the DFT+U current correction per step
+        A0 = np.array([0.05, 0.02, 0.0])
+
+        def field(i):
+            return A0 * np.sin(0.1 * i)
+
+        def run(nsteps, with_current, i0):
+            for i in range(nsteps):
+                hub32.set_vector_potential(field(i0 + i))
+                hub32.step(psi32, f_d, hpsi32, mode="graph", bufs=bufs32)
+                if with_current:
+                    hub32.current(psi32, bufs32["c"], f_d, bufs32["Ueff"], bufs32["n"])
+
+        gauge = {}
+        for with_current in (False, True):
+            run(3, with_current, 0)
+            torch.cuda.synchronize()
+            ge0, ge1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ge0.record()
+            run(args.steps, with_current, 3)
+            ge1.record()
+            torch.cuda.synchronize()
+            key = "gauge_current_steps_per_s" if with_current else "gauge_steps_per_s"
+            gauge[key] = round(args.steps / (ge0.elapsed_time(ge1) * 1e-3), 2)
+        hub32.set_vector_potential(None)
+        log(f"velocity gauge: {gauge}")
+
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -244,6 +277,8 @@ def main():
     del src, dst
 
     detail = {"coulomb_setup_ms": round(coulomb_s * 1e3, 2), "device_copy_GBs": round(copy_GBs, 1)}
+    if gauge is not None:
+        detail.update(gauge)
     if forces_on is not None:
         detail["forces_off_steps_per_s"] = round(value, 2)
         detail["forces_on_steps_per_s"] = round(forces_on, 2)
