@@ -28,11 +28,15 @@ Modules (each function cites the passage it follows):
                   noncollinear form in App. A)
 * ``forces``      Hubbard forces (Sec. IV) and finite-difference checks
 * ``step``        one whole Hubbard step from the functions above
+* ``gauge``       velocity-gauge projection and apply, the DFT+U current
+                  correction (Sec. V)
+* ``stencil``     forces through <phi|grad psi> with a 4th-order central
+                  difference of the states (Sec. IV, the paper's own form)
 
 Parity pins live in ``tests/test_oracle_*.py``.  Functions whose values no
 independent property fixes are listed there and in the design doc as
 "parity unpinned".
 """
 
-from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step  # noqa: F401
+from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step, gauge, stencil  # noqa: F401
 from .orbitals import System, Site  # noqa: F401

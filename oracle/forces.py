@@ -12,8 +12,8 @@ dc/dR = -d, d = dV sum_p exp(i k.T_p) (grad phi)(p) psi(g(p)) and
 
 (The paper's printed dn/dR formulas are garbled in their indices; this form
 is the exact derivative of the discrete E_U and is checked against central
-finite differences below.  Its alternative through <phi|grad psi> is not
-implemented.)
+finite differences below.  The alternative through <phi|grad psi>, which
+the paper uses, is in stencil.py.)
 
 Adjoint: dE_U/dpsi*(g) = dV w_k f_n (V_U psi)(g) (Eq. minimization); for
 unpolarized runs, which count the stored channel twice, both results double.
