@@ -236,6 +236,21 @@ int hub_energy(hub_ctx* ctx, const double* Ueff, const double* n, double* EU);
 int hub_forces(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
                const double* f, const double* Ueff, const double* n, double* F);
 
+/* Hubbard forces through the derivatives of the states (Sec. IV, the form
+ * the paper uses to reduce the egg-box effect): as hub_forces with
+ * d_{a,i} = -<phi_a|D_i psi>, D_i the 4th-order central difference
+ * (weights 1/12, -2/3, 0, 2/3, -1/12 over offsets -2..2, divided by h_i)
+ * applied to the Bloch extension of psi (a neighbour past the cell face
+ * along axis i is psi at the folded point times exp(i k_i a_i)).  Evaluated
+ * by summation by parts as d = dV sum_p exp(i k.T_p) (D_i phi_a)(p) psi[g(p)]
+ * over the dilated sphere (unfolded points within two steps of a sphere
+ * point along an axis, phi zero off the sphere).  The first call builds and
+ * uploads that work list (hipMalloc; not inside graph capture).  With a
+ * vector potential on, the phases are those of hub_forces.  Arguments and
+ * layout as hub_forces.  psi, c, f, Ueff, n, F: device. */
+int hub_forces_state_gradient(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
+                              const double* f, const double* Ueff, const double* n, double* F);
+
 /* Velocity gauge (Sec. V): with a uniform vector potential A (host array of
  * 3, bohr^-1; NULL switches the field off), the projections and the apply
  * of every later call and graph replay use V^A = exp(-i A.r) V_U exp(i A.r):

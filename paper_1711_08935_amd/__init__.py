@@ -44,7 +44,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
-           "hub_set_vector_potential", "hub_current"]
+           "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -79,6 +79,7 @@ def lib():
         "hub_energy": [P, P, P, P],
         "hub_forces": [P, P, I64, I, P, P, P, P, P],
         "hub_current": [P, P, I64, I, P, P, P, P, P],
+        "hub_forces_state_gradient": [P, P, I64, I, P, P, P, P, P],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -358,12 +359,18 @@ class Hubbard:
                                  _dptr(n), _dptr(J)), "hub_current")
         return J
 
-    def forces(self, psi, c, f, Ueff, n, nstates=None):
+    def forces(self, psi, c, f, Ueff, n, nstates=None, form="orbital"):
+        """Hubbard forces (n_sites, 3).  form="orbital": through the orbital
+        gradients <grad phi|psi>; form="state": through the 4th-order
+        differences of the states <phi|D psi> (hub_forces_state_gradient)."""
+        if form not in ("orbital", "state"):
+            raise ValueError(f"form must be 'orbital' or 'state', not {form!r}")
+        name = "hub_forces" if form == "orbital" else "hub_forces_state_gradient"
         ld, S = self._states(psi, nstates)
         F = torch.empty((self.nsites, 3), dtype=torch.float64, device="cuda")
         self._stream()
-        _check(lib().hub_forces(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)), _dptr(Ueff),
-                                _dptr(n), _dptr(F)), "hub_forces")
+        _check(getattr(lib(), name)(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)), _dptr(Ueff),
+                                    _dptr(n), _dptr(F)), name)
         return F
 
     def profile(self, enable=True):

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "ksmall.h"
@@ -89,6 +90,13 @@ struct hub_ctx {
     std::vector<double> phase_host;          // exp(i k.T) without a field
     double* d_grad = nullptr;
     size_t grad_cap = 0;
+    // state-gradient force form: dilated-sphere tables, built at first use
+    bool stencil_built = false;
+    int stencil_nchunks = 0;
+    int64_t stencil_part_rows = 0;
+    HubChunk* d_st_chunks = nullptr;
+    int32_t *d_st_all = nullptr, *d_st_gidx = nullptr, *d_st_site_ptr = nullptr, *d_st_site_ids = nullptr;
+    double* d_st_tab = nullptr;
     double* d_nbar_ws = nullptr;
     size_t nbar_cap = 0;
 
@@ -146,6 +154,7 @@ void release(hub_ctx* c) {
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
     f(c->d_pg); f(c->d_mphi); f(c->d_images); f(c->d_kred);
     c->d_pg = nullptr;
+    f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -295,9 +304,11 @@ int run_classes(hub_ctx* c, F&& launch) {
     return HUB_OK;
 }
 
-// Orbital table of a projection: values, gradients (forces) or position
-// moments about the site centre (velocity-gauge current).
-enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2 };
+// Orbital table of a projection: values, gradients (forces), position
+// moments about the site centre (velocity-gauge current) or the 4th-order
+// differences of the orbitals on the dilated spheres (state-gradient forces,
+// a work list of its own).
+enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2, TAB_STENCIL = 3 };
 
 ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table) {
     const bool grad = table != TAB_PHI;
@@ -314,6 +325,13 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table)
     a.tab = table == TAB_GRAD ? c->d_gphi : (table == TAB_MOMENT ? c->d_mphi : c->d_phi);
     a.tabmult = grad ? 3 : 1;
     a.prows = c->T.part_rows * a.tabmult;
+    if (table == TAB_STENCIL) {
+        a.chunks = c->d_st_chunks;
+        a.chunk_list = c->d_st_all;
+        a.gidx = c->d_st_gidx;
+        a.tab = c->d_st_tab;
+        a.prows = c->stencil_part_rows * 3;
+    }
     a.pg = c->gauge ? c->d_pg : nullptr;
     return a;
 }
@@ -342,7 +360,8 @@ ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
 
 // project + reduce into c (per_site: one projection launch per site)
 size_t part_need(const hub_ctx* c, int ncol, int mult) {
-    const int64_t rows = std::max<int64_t>(c->T.part_rows * mult, c->T.grouped.ok ? c->T.grouped.part_rows : 0);
+    int64_t rows = std::max<int64_t>(c->T.part_rows * mult, c->T.grouped.ok ? c->T.grouped.part_rows : 0);
+    if (mult == 3) rows = std::max<int64_t>(rows, c->stencil_part_rows * 3);
     return static_cast<size_t>(c->nsets()) * rows * ncol * c->ncplx();
 }
 
@@ -400,8 +419,8 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     {
     StageTimer tm(c, grad ? HUB_STAGE_GRADPROJ : HUB_STAGE_PROJECT);
     if (!per_site) {
-        HUB_TRY(launch_project(a, static_cast<int>(c->T.chunks.size()), c->nsets(), c->precision, c->is_complex,
-                               cpl, waves, 0, c->stream));
+        const int nch = table == TAB_STENCIL ? c->stencil_nchunks : static_cast<int>(c->T.chunks.size());
+        HUB_TRY(launch_project(a, nch, c->nsets(), c->precision, c->is_complex, cpl, waves, 0, c->stream));
     } else {
         for (int s = 0; s < c->T.nsites; ++s) {
             ProjArgs b = a;
@@ -412,6 +431,12 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     }
     }
     ReduceArgs r = reduce_args(c, out, ncol, mult);
+    if (table == TAB_STENCIL) {
+        r.chunks = c->d_st_chunks;
+        r.site_chunk_ptr = c->d_st_site_ptr;
+        r.site_chunk_ids = c->d_st_site_ids;
+        r.prows = c->stencil_part_rows * 3;
+    }
     StageTimer tm(c, HUB_STAGE_REDUCE);
     HUB_TRY(launch_reduce(r, c->nsets(), c->stream));
     return HUB_OK;
@@ -1049,11 +1074,44 @@ int gauge_tables(hub_ctx* c) {
     return HUB_OK;
 }
 
+// Dilated-sphere work list of the state-gradient force form, built on the
+// host and uploaded at the first call that needs it.
+int build_stencil(hub_ctx* c) {
+    StencilTables S;
+    const int st = hub_build_stencil(c->cell, c->ngrid, c->sites, c->T, c->chunk_entries, S);
+    if (st) return st;
+    std::vector<int32_t> all(S.chunks.size());
+    std::iota(all.begin(), all.end(), 0);
+    size_t bytes = 0;
+    HUB_TRY(upload(&c->d_st_chunks, S.chunks, bytes));
+    HUB_TRY(upload(&c->d_st_all, all, bytes));
+    HUB_TRY(upload(&c->d_st_gidx, S.gidx, bytes));
+    HUB_TRY(upload(&c->d_st_tab, S.tab, bytes));
+    HUB_TRY(upload(&c->d_st_site_ptr, S.site_chunk_ptr, bytes));
+    HUB_TRY(upload(&c->d_st_site_ids, S.site_chunk_ids, bytes));
+    c->table_bytes += bytes;
+    c->stencil_nchunks = static_cast<int>(S.chunks.size());
+    c->stencil_part_rows = S.part_rows;
+    c->stencil_built = true;
+    return HUB_OK;
+}
+
 }  // namespace
 
 int hub_forces(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
                const double* Ueff, const double* n, double* F) {
     return contract_moments(c, psi, ld, nstates, cc, f, Ueff, n, F, TAB_GRAD);
+}
+
+int hub_forces_state_gradient(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc,
+                              const double* f, const double* Ueff, const double* n, double* F) {
+    if (!c) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!c->stencil_built) {
+        const int st = build_stencil(c);
+        if (st) return st;
+    }
+    return contract_moments(c, psi, ld, nstates, cc, f, Ueff, n, F, TAB_STENCIL);
 }
 
 int hub_current(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,

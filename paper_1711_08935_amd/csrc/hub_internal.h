@@ -94,9 +94,34 @@ struct HostTables {
     GroupTables grouped;
 };
 
+// Work list of the state-gradient force form (Sec. IV): <phi|D_i psi>, D_i
+// the 4th-order central difference along axis i, equals by summation by
+// parts -dV sum over the dilated sphere (every unfolded point within two
+// steps of a sphere point along an axis) of exp(i k.T) (D_i phi)(p)
+// psi(g(p)), with phi zero outside the sphere.  The table holds D_i phi, so
+// the projection machinery of the orbital gradients computes
+// d = dV sum exp(i k.T) (D phi) psi = -<phi|D psi> and the force contraction
+// is shared.  Chunks are per (site, image) as in one layer of the layered
+// list; the projection needs no layers.
+struct StencilTables {
+    std::vector<HubChunk> chunks;            // site-major, then image, g ascending
+    std::vector<int32_t> gidx;               // per entry
+    std::vector<double> tab;                 // per entry, 3L values [m][i]
+    std::vector<int32_t> site_chunk_ptr;     // CSR site -> chunk ids
+    std::vector<int32_t> site_chunk_ids;
+    int64_t part_rows = 0;                   // sum of L over chunks
+    int64_t nentries = 0;                    // real (unpadded) entries
+};
+
 // Host builder (sphere.cpp).  Returns HUB_OK or a negative status.
 int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<SiteDef>& sites,
                    int chunk_entries, HostTables& out);
 
 // Closed-form average of 1/|r| over one grid cell centred at the origin.
 double hub_g0_cell_average(const double h[3]);
+
+// Dilated-sphere tables of the state-gradient force form from the spheres of
+// ``T`` (sphere.cpp).  Every image it needs is in T.images (hub_build_host
+// registers the images of the points two steps past each sphere point).
+int hub_build_stencil(const double cell[3], const int ngrid[3], const std::vector<SiteDef>& sites,
+                      const HostTables& T, int chunk_entries, StencilTables& out);

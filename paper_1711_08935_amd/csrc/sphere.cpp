@@ -218,6 +218,25 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
             }
         }
     }
+    // images of the dilated spheres of the state-gradient force form: a point
+    // up to two steps past a sphere point along one axis; only points within
+    // two steps of a cell face can change image
+    for (int s = 0; s < ns; ++s)
+        for (const Pt& q : pts[s])
+            for (int i = 0; i < 3; ++i) {
+                const int64_t f = static_cast<int64_t>(q.ijk[i]) - static_cast<int64_t>(q.img[i]) * ngrid[i];
+                if (f >= 2 && f < ngrid[i] - 2) continue;
+                for (int o = -2; o <= 2; ++o) {
+                    if (o == 0) continue;
+                    int32_t im[3] = {q.img[0], q.img[1], q.img[2]};
+                    im[i] = static_cast<int32_t>(floor_div(static_cast<int64_t>(q.ijk[i]) + o, ngrid[i]));
+                    auto key = std::make_tuple(im[0], im[1], im[2]);
+                    if (!image_id.count(key)) {
+                        const int id = static_cast<int>(image_id.size());
+                        image_id[key] = id;
+                    }
+                }
+            }
     T.images.resize(3 * image_id.size());
     for (const auto& kv : image_id) {
         T.images[3 * kv.second + 0] = std::get<0>(kv.first);
@@ -459,5 +478,136 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                 T.orb_site[T.site_orb0[s] + m] = s;
             }
     }
+    return HUB_OK;
+}
+
+int hub_build_stencil(const double cell[3], const int ngrid[3], const std::vector<SiteDef>& sites,
+                      const HostTables& T, int chunk_entries, StencilTables& S) {
+    S = StencilTables();
+    const int ns = T.nsites;
+    if (ns <= 0 || static_cast<int>(sites.size()) != ns || static_cast<int>(T.spheres.size()) != ns) return HUB_EINVAL;
+    double h[3];
+    for (int i = 0; i < 3; ++i) h[i] = cell[i] / static_cast<double>(ngrid[i]);
+    // first derivative, 4th order: weights of the values at offsets -2..2 (times 1/h)
+    constexpr int kOff[4] = {-2, -1, 1, 2};
+    constexpr double kW[4] = {1.0 / 12.0, -2.0 / 3.0, 2.0 / 3.0, -1.0 / 12.0};
+    std::map<std::tuple<int, int, int>, int> image_id;
+    for (size_t t = 0; t < T.images.size() / 3; ++t)
+        image_id[std::make_tuple(T.images[3 * t], T.images[3 * t + 1], T.images[3 * t + 2])] = static_cast<int>(t);
+    const int chunk = std::max(1, chunk_entries);
+    S.site_chunk_ptr.assign(ns + 1, 0);
+    int64_t e = 0, nreal = 0, part_rows = 0, phi0 = 0;
+    for (int s = 0; s < ns; ++s) {
+        S.site_chunk_ptr[s] = static_cast<int32_t>(S.chunks.size());
+        const SiteSphere& sp = T.spheres[s];
+        const int L = T.site_L[s];
+        const size_t np = sp.g.size();
+        if (np == 0) return HUB_EINVAL;
+        // box of unfolded coordinates: the sphere's bounds widened by 2
+        int64_t lo[3], hi[3], nb[3];
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = hi[i] = sp.ijk[i];
+            for (size_t p = 0; p < np; ++p) {
+                lo[i] = std::min<int64_t>(lo[i], sp.ijk[3 * p + i]);
+                hi[i] = std::max<int64_t>(hi[i], sp.ijk[3 * p + i]);
+            }
+            lo[i] -= 2;
+            hi[i] += 2;
+            nb[i] = hi[i] - lo[i] + 1;
+        }
+        const size_t box = static_cast<size_t>(nb[0] * nb[1] * nb[2]);
+        auto cell_of = [&](int64_t x, int64_t y, int64_t z) {
+            return static_cast<size_t>(((x - lo[0]) * nb[1] + (y - lo[1])) * nb[2] + (z - lo[2]));
+        };
+        std::vector<int32_t> at(box, -1);     // sphere point at a box cell
+        std::vector<char> dil(box, 0);        // cell of the dilated sphere
+        for (size_t p = 0; p < np; ++p) {
+            const int64_t j[3] = {sp.ijk[3 * p], sp.ijk[3 * p + 1], sp.ijk[3 * p + 2]};
+            at[cell_of(j[0], j[1], j[2])] = static_cast<int32_t>(p);
+            for (int i = 0; i < 3; ++i)
+                for (int o = 0; o < 4; ++o) {
+                    int64_t n[3] = {j[0], j[1], j[2]};
+                    n[i] += kOff[o];
+                    dil[cell_of(n[0], n[1], n[2])] = 1;
+                }
+        }
+        struct DPt {
+            int32_t g, img;
+            int64_t x, y, z;
+        };
+        std::vector<DPt> pts;
+        for (int64_t x = lo[0]; x <= hi[0]; ++x)
+            for (int64_t y = lo[1]; y <= hi[1]; ++y)
+                for (int64_t z = lo[2]; z <= hi[2]; ++z) {
+                    if (!dil[cell_of(x, y, z)]) continue;
+                    const int64_t j[3] = {x, y, z};
+                    int64_t f[3];
+                    int im[3];
+                    for (int i = 0; i < 3; ++i) {
+                        const int64_t n = floor_div(j[i], ngrid[i]);
+                        f[i] = j[i] - n * ngrid[i];
+                        im[i] = static_cast<int>(n);
+                    }
+                    auto it = image_id.find(std::make_tuple(im[0], im[1], im[2]));
+                    if (it == image_id.end()) return HUB_EINVAL;
+                    pts.push_back({static_cast<int32_t>((f[0] * ngrid[1] + f[1]) * ngrid[2] + f[2]), it->second, x, y,
+                                   z});
+                }
+        std::sort(pts.begin(), pts.end(),
+                  [](const DPt& a, const DPt& b) { return std::tie(a.img, a.g) < std::tie(b.img, b.g); });
+        // (D_i phi_m)(n) = sum_o w_o phi_m(n + o e_i) / h_i, phi zero off the sphere
+        auto table_row = [&](const DPt& q, std::vector<double>& tab) {
+            const int64_t j[3] = {q.x, q.y, q.z};
+            for (int m = 0; m < L; ++m)
+                for (int i = 0; i < 3; ++i) {
+                    double acc = 0.0;
+                    for (int o = 0; o < 4; ++o) {
+                        int64_t n[3] = {j[0], j[1], j[2]};
+                        n[i] += kOff[o];
+                        if (n[i] < lo[i] || n[i] > hi[i]) continue;
+                        const int32_t p = at[cell_of(n[0], n[1], n[2])];
+                        if (p >= 0) acc += kW[o] * sp.phi[static_cast<size_t>(p) * L + m];
+                    }
+                    tab.push_back(acc / h[i]);
+                }
+        };
+        for (size_t b = 0; b < pts.size();) {
+            const int im = pts[b].img;
+            size_t n = 0;
+            while (b + n < pts.size() && n < static_cast<size_t>(chunk) && pts[b + n].img == im) ++n;
+            const size_t npad = (n + HUB_ENTRY_ALIGN - 1) / HUB_ENTRY_ALIGN * HUB_ENTRY_ALIGN;
+            HubChunk C;
+            C.site = s;
+            C.layer = 0;
+            C.e0 = static_cast<int32_t>(e);
+            C.ne = static_cast<int32_t>(npad);
+            C.L = L;
+            C.orb0 = T.site_orb0[s];
+            C.part0 = static_cast<int32_t>(part_rows);
+            C.species = sites[s].species;
+            C.phi0 = phi0;
+            C.img = im;
+            C.nreal = static_cast<int32_t>(n);
+            for (size_t t = 0; t < n; ++t) {
+                S.gidx.push_back(pts[b + t].g);
+                table_row(pts[b + t], S.tab);
+            }
+            for (size_t t = n; t < npad; ++t) {
+                S.gidx.push_back(S.gidx.back());
+                S.tab.insert(S.tab.end(), 3 * L, 0.0);
+            }
+            S.site_chunk_ids.push_back(static_cast<int32_t>(S.chunks.size()));
+            S.chunks.push_back(C);
+            e += static_cast<int64_t>(npad);
+            nreal += static_cast<int64_t>(n);
+            phi0 += static_cast<int64_t>(npad) * L;
+            part_rows += L;
+            b += n;
+            if (e > INT32_MAX || part_rows > INT32_MAX) return HUB_EINVAL;
+        }
+    }
+    S.site_chunk_ptr[ns] = static_cast<int32_t>(S.chunks.size());
+    S.part_rows = part_rows;
+    S.nentries = nreal;
     return HUB_OK;
 }

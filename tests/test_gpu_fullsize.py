@@ -3,7 +3,8 @@ times (default chunking, kernel shapes picked by the autotuner, the step run
 as a hipGraph).  The oracle runs on the states the device holds (the FP32
 storage rounded states, upcast).  Where the oracle can compute every output
 in seconds it does (NiO-like workload: all projections, matrices, U, J and
-V_U psi; forces workload: all forces); for the 1024-state batched workload it
+V_U psi; forces workload: all forces of the orbital-gradient form, and the
+state-gradient form on sampled states); for the 1024-state batched workload it
 checks every projection and matrix and V_U psi on sampled state columns.
 """
 
@@ -20,6 +21,7 @@ from oracle import forces as OF  # noqa: E402
 from oracle import occupations as OO  # noqa: E402
 from oracle import potential as OPOT  # noqa: E402
 from oracle import projection as OP  # noqa: E402
+from oracle import stencil as SG  # noqa: E402
 from oracle import step as OS  # noqa: E402
 from paper_1711_08935_amd.tune import autotune  # noqa: E402
 from synth import make_config, make_occupations, make_states  # noqa: E402
@@ -97,14 +99,28 @@ def test_rt_batched_full_size_sampled():
 
 @pytest.mark.timeout(900)
 def test_forces_full_size():
+    """All forces of both forms.  U_eff is a seeded input of the force call
+    (the oracle takes no value from the device); the orbital-gradient form
+    over every state, the state-gradient form over 8 sampled occupied states
+    (the other occupations set to zero, so the force is their contribution)."""
     cfg, hub, psi, f, f_d, bufs, hpsi = _setup("forces_fcc", "f32")
-    F = hub.forces(psi, bufs["c"], f_d, bufs["Ueff"], bufs["n"]).cpu().numpy()
+    rng = np.random.default_rng(11)
     sys_ = to_system(cfg)
     sps = OP.all_spheres(sys_)
+    ueff = rng.uniform(0.1, 0.4, size=len(sps))
+    ueff_d = torch.from_numpy(ueff).cuda()
+    F = hub.forces(psi, bufs["c"], f_d, ueff_d, bufs["n"]).cpu().numpy()
+    cols = np.sort(rng.choice(np.flatnonzero(f[0] > 0), size=8, replace=False))
+    fm = np.zeros_like(f)
+    fm[:, cols] = f[:, cols]
+    Fs = hub.forces(psi, bufs["c"], torch.from_numpy(fm).cuda(), ueff_d, bufs["n"], form="state").cpu().numpy()
     used = psi.cpu().numpy().astype(np.float64)
     c = OP.project_sphere(sys_, used, sps)
     n, _, _ = OO.occupations(sys_, c, f, with_pbar=False)
-    ueff = bufs["Ueff"].cpu().numpy()
     V = [OPOT.potential_matrix(sys_, ueff[I], n[I]) for I in range(len(sps))]
     Fo = OF.forces_analytic(sys_, c, OF.gradient_projections(sys_, used, sps), V, f)
     assert normwise(F, Fo) < 1e-11
+    e = SG.state_gradient_projections(sys_, used[:, :, cols], sps)
+    Fso = SG.forces_state_gradient(sys_, c[:, :, cols], e, V, fm[:, cols])
+    assert np.abs(Fso).max() > 1e-8
+    assert normwise(Fs, Fso) < 1e-11
