@@ -57,6 +57,10 @@ def parse():
                          "(profiling runs use the shapes the autotuner picked)")
     ap.add_argument("--no-gauge", action="store_true",
                     help="skip the velocity-gauge timing (complex workloads)")
+    ap.add_argument("--rc-sweep", default=None,
+                    help="instead of the bench line: steps/s and grid points against the sphere radius of the "
+                         "d shells (comma-separated radii in bohr; 'cell' and 'tN' (threshold 1e-N) select a "
+                         "radius by the Sec. II methods)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB three times (counter calibration)")
     return ap.parse_args()
@@ -130,13 +134,74 @@ def cpu_baseline(cfg, psi_host, f, nsteps):
     return statistics.median(times), threads
 
 
+def rc_sweep(args):
+    """Sphere-radius sweep (Sec. II, the radius discussion and its figure of
+    grid points against the d-orbital radius): the d shells of the workload
+    take each radius in turn, the other shells keep theirs; U_eff is fixed
+    (as in the paper's sweep), so no Coulomb tensors are built.  Per radius:
+    points per d sphere, union of covered points, whether the grouped work
+    list holds (at most 16 functions per point), graph steps/s and the
+    algorithmic bytes of project + apply per second."""
+    import numpy as np
+    import torch
+
+    import paper_1711_08935_amd as H
+    from paper_1711_08935_amd.tune import autotune
+    from synth import make_config, make_occupations, make_states
+
+    cfg = make_config(args.workload)
+    dsites = [i for i, s in enumerate(cfg.sites) if s["l"] == 2]
+    psi64 = make_states(cfg, device="cuda")
+    f_d = torch.from_numpy(make_occupations(cfg)).cuda()
+    esz = 8 if cfg.is_complex else 4
+    ncol = cfg.nstates * (2 if cfg.spin == "spinor" else 1)
+    out = []
+    for tok in args.rc_sweep.split(","):
+        d0 = cfg.sites[dsites[0]]
+        if tok == "cell":
+            rc, how = H.sphere_radius("cell", cell=cfg.cell), "cell"
+        elif tok.startswith("t"):
+            rc, how = H.sphere_radius("threshold", l=2, zeta=d0["zeta"], threshold=10.0 ** (-int(tok[1:]))), tok
+        else:
+            rc, how = float(tok), "given"
+        sites = [dict(s, rc=rc) if i in dsites else s for i, s in enumerate(cfg.sites)]
+        hub = H.Hubbard(cfg.cell, cfg.ngrid, sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                        is_complex=cfg.is_complex, precision="f32", chunk=args.chunk)
+        for i in range(len(sites)):
+            hub.set_fixed_ueff(i, 0.15)
+        psi = psi64.to(hub.state_dtype)
+        bufs = hub.step_buffers(cfg.nstates)
+        h = torch.zeros_like(psi)
+        hub.step(psi, f_d, h, mode="batched", bufs=bufs)
+        if not args.no_tune:
+            autotune(hub, psi, bufs["c"], bufs["n"], bufs["Ueff"])
+        wall, ev = time_steps(hub, psi, f_d, h, "graph", args.steps, args.warmup, bufs)
+        pts = union_points(hub)
+        alg = 3 * pts * ncol * esz * hub.nsets
+        row = {"rc": round(rc, 4), "method": how, "points_per_d_sphere": int(hub.site_npts[dsites[0]]),
+               "union_points": pts, "grouped_worklist": hub.query(11) > 0, "functions_per_point_max": hub.query(12),
+               "steps_per_s": round(args.steps / ev, 2), "step_GBs": round(alg / (ev / args.steps) / 1e9, 1)}
+        log(str(row))
+        out.append(row)
+        del hub, psi, bufs, h
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "Hubbard steps/s against the d-sphere radius", "unit": "Hubbard steps/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+                      "data": "synthetic", "config": {"workload": cfg.name, "grid": list(cfg.ngrid),
+                                                      "storage": "f32 states", "ueff": "fixed 0.15 Ha"},
+                      "sweep": out}))
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding is a "
-                          "design (see DESIGN.md), so --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this library runs on one GPU; sharding over GPUs is a design only, "
+                          "so --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.rc_sweep:
+        rc_sweep(args)
+        return
     import numpy as np
     import torch
 
@@ -223,6 +288,25 @@ def main():
             torch.cuda.synchronize()
             forces_on[form] = args.steps / (fe0.elapsed_time(fe1) * 1e-3)
             log(f"f32 graph step + forces ({form} gradient): {forces_on[form]:.1f} steps/s")
+        # per-stage times of the force calls alone: gradient projection (state
+        # rows of every sphere / dilated-sphere entry plus the 3L table values),
+        # its reduction and the contraction
+        row = cfg.nstates * (8 if cfg.is_complex else 4)
+        forces_stages = {}
+        for form, q in (("orbital", 4), ("state", 13)):
+            hub32.profile(True)
+            for _ in range(20):
+                hub32.forces(psi32, bufs32["c"], f_d, bufs32["Ueff"], bufs32["n"], form=form)
+            pr = hub32.profile_read()
+            hub32.profile(False)
+            entries = hub32.query(q)
+            L = hub32.site_L[0]
+            alg = entries * hub32.nsets * (row + 3 * L * 8)
+            ms = pr["gradproject"][0] / max(1, pr["gradproject"][1])
+            forces_stages[form] = {"gradproject_ms": round(ms, 4), "reduce_ms": round(pr["reduce"][0] / 20, 4),
+                                   "forces_ms": round(pr["forces"][0] / 20, 4), "entries": int(entries),
+                                   "gradproject_GBs": round(alg / (ms * 1e-3) / 1e9, 1)}
+        log(f"force stages: {forces_stages}")
 
     gauge = None
     if cfg.is_complex and not args.no_gauge:
@@ -285,6 +369,7 @@ def main():
         detail["forces_off_steps_per_s"] = round(value, 2)
         detail["forces_on_steps_per_s"] = round(forces_on["orbital"], 2)
         detail["forces_state_gradient_on_steps_per_s"] = round(forces_on["state"], 2)
+        detail["force_stages"] = forces_stages
     if tuned is not None:
         detail["tuned_shapes"] = {"project": list(tuned["project"][0]), "apply": list(tuned["apply"][0]),
                                   "candidates_ms": tuned["table"]}

@@ -103,6 +103,23 @@ int hub_set_kpoints(hub_ctx* ctx, int nk, const double* k_red, const double* wei
 int hub_add_site(hub_ctx* ctx, const double R[3], int l, double zeta, double rc,
                  int species, int* site_id);
 
+/* Sphere radius selection (Sec. II, the radius discussion; host only, needs
+ * no context or GPU).  Of the paper's three methods, the pseudopotential's
+ * non-local cutoff is the caller's own rc; the other two:
+ *   HUB_RADIUS_CELL       rc = the shortest cell edge, min(cell[0..2])
+ *                         (l, zeta, threshold ignored);
+ *   HUB_RADIUS_THRESHOLD  rc = the radius beyond which the normalized
+ *                         radial part R(r) = N r^l exp(-zeta r),
+ *                         N^2 = (2 zeta)^(2l+3) / (2l+2)!, stays below
+ *                         threshold (bohr^-3/2): the root of R(r) = threshold
+ *                         on r >= l / zeta, to rounding (cell ignored).
+ * *rc (bohr) is written on success.  Errors: HUB_EINVAL (NULL rc, unknown
+ * method, l outside 0..3, zeta or threshold not positive and finite, a cell
+ * edge not positive, or a threshold at or above the peak of R). */
+#define HUB_RADIUS_CELL 1
+#define HUB_RADIUS_THRESHOLD 2
+int hub_sphere_radius(int method, int l, double zeta, const double cell[3], double threshold, double* rc);
+
 /* Fix the effective U of one site (the empirical DFT+U scheme, Sec. II);
  * pass NaN to return the site to ACBN0 (the default).  Any time. */
 int hub_set_fixed_ueff(hub_ctx* ctx, int site, double ueff);
@@ -167,7 +184,8 @@ int hub_set_stream(hub_ctx* ctx, void* stream);
  * 6 species, 7 k-points, 8 nblk of n/pbar, 9 bytes of device tables,
  * 10 projection workspace rows (sum of L over chunks), 11 grouped chunks
  * (0 when the grouped work list was not built), 12 largest number of
- * orbitals covering one grid point. */
+ * orbitals covering one grid point, 13 dilated-sphere entries of the
+ * state-gradient forces (0 before the first hub_forces_state_gradient). */
 int hub_query(const hub_ctx* ctx, int what, int64_t* value);
 
 /* Per-site data after hub_finalize_host: L = 2l+1, offset of its first

@@ -30,6 +30,7 @@ Modules (each function cites the passage it follows):
 * ``step``        one whole Hubbard step from the functions above
 * ``gauge``       velocity-gauge projection and apply, the DFT+U current
                   correction (Sec. V)
+* ``radius``      sphere radius selection (Sec. II, radius discussion)
 * ``stencil``     forces through <phi|grad psi> with a 4th-order central
                   difference of the states (Sec. IV, the paper's own form)
 
@@ -38,5 +39,5 @@ independent property fixes are listed there and in the design doc as
 "parity unpinned".
 """
 
-from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step, gauge, stencil  # noqa: F401
+from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step, gauge, stencil, radius  # noqa: F401
 from .orbitals import System, Site  # noqa: F401

@@ -44,7 +44,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
-           "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient"]
+           "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -80,6 +80,7 @@ def lib():
         "hub_forces": [P, P, I64, I, P, P, P, P, P],
         "hub_current": [P, P, I64, I, P, P, P, P, P],
         "hub_forces_state_gradient": [P, P, I64, I, P, P, P, P, P],
+        "hub_sphere_radius": [I, I, D, DP, D, DP],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -110,6 +111,23 @@ def _dptr(t):
 def _darr(vals):
     arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
     return arr
+
+
+HUB_RADIUS_CELL, HUB_RADIUS_THRESHOLD = 1, 2
+
+
+def sphere_radius(method, l=0, zeta=1.0, cell=None, threshold=0.0):
+    """Sphere radius (bohr) by one of the selection methods of Sec. II:
+    "cell" (the shortest cell edge) or "threshold" (where the normalized
+    Slater radial part drops below ``threshold``).  Host only."""
+    m = {"cell": HUB_RADIUS_CELL, "threshold": HUB_RADIUS_THRESHOLD}.get(method)
+    if m is None:
+        raise ValueError(f"method must be 'cell' or 'threshold', not {method!r}")
+    rc = ctypes.c_double(0.0)
+    cl = _darr(cell) if cell is not None else None
+    _check(lib().hub_sphere_radius(m, int(l), float(zeta), cl, float(threshold), ctypes.byref(rc)),
+           "hub_sphere_radius")
+    return rc.value
 
 
 class Hubbard:

@@ -93,7 +93,7 @@ struct hub_ctx {
     // state-gradient force form: dilated-sphere tables, built at first use
     bool stencil_built = false;
     int stencil_nchunks = 0;
-    int64_t stencil_part_rows = 0;
+    int64_t stencil_part_rows = 0, stencil_entries = 0;
     HubChunk* d_st_chunks = nullptr;
     int32_t *d_st_all = nullptr, *d_st_gidx = nullptr, *d_st_site_ptr = nullptr, *d_st_site_ids = nullptr;
     double* d_st_tab = nullptr;
@@ -883,6 +883,7 @@ int hub_query(const hub_ctx* c, int what, int64_t* v) {
     case 10: *v = T.part_rows; break;
     case 11: *v = T.grouped.ok ? static_cast<int64_t>(T.grouped.chunks.size()) : 0; break;
     case 12: *v = T.grouped.nfmax; break;
+    case 13: *v = c->stencil_entries; break;
     default: return HUB_EINVAL;
     }
     return HUB_OK;
@@ -1092,6 +1093,7 @@ int build_stencil(hub_ctx* c) {
     c->table_bytes += bytes;
     c->stencil_nchunks = static_cast<int>(S.chunks.size());
     c->stencil_part_rows = S.part_rows;
+    c->stencil_entries = S.nentries;
     c->stencil_built = true;
     return HUB_OK;
 }

@@ -611,3 +611,44 @@ int hub_build_stencil(const double cell[3], const int ngrid[3], const std::vecto
     S.nentries = nreal;
     return HUB_OK;
 }
+
+int hub_sphere_radius(int method, int l, double zeta, const double cell[3], double threshold, double* rc) {
+    if (!rc) return HUB_EINVAL;
+    if (method == HUB_RADIUS_CELL) {
+        if (!cell) return HUB_EINVAL;
+        double m = cell[0];
+        for (int i = 0; i < 3; ++i) {
+            if (!(cell[i] > 0.0) || !std::isfinite(cell[i])) return HUB_EINVAL;
+            m = std::min(m, cell[i]);
+        }
+        *rc = m;
+        return HUB_OK;
+    }
+    if (method != HUB_RADIUS_THRESHOLD) return HUB_EINVAL;
+    if (l < 0 || l > 3 || !(zeta > 0.0) || !std::isfinite(zeta) || !(threshold > 0.0) || !std::isfinite(threshold))
+        return HUB_EINVAL;
+    // log R(r) - log threshold; decreasing for r > l / zeta
+    double fact = 1.0;
+    for (int i = 2; i <= 2 * l + 2; ++i) fact *= i;
+    const double logN = 0.5 * ((2 * l + 3) * std::log(2.0 * zeta) - std::log(fact));
+    const double logt = std::log(threshold);
+    auto g = [&](double r) { return logN + (l > 0 ? l * std::log(r) : 0.0) - zeta * r - logt; };
+    double lo = l > 0 ? l / zeta : 0.0;
+    if (!(g(lo) > 0.0)) return HUB_EINVAL;
+    double hi = lo + 1.0 / zeta;
+    for (int it = 0; g(hi) > 0.0; ++it) {
+        if (it > 200) return HUB_EINVAL;
+        hi = lo + 2.0 * (hi - lo);
+    }
+    // bisection down to adjacent doubles: g(lo) > 0 >= g(hi)
+    for (int it = 0; it < 2000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (g(mid) > 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *rc = hi;
+    return HUB_OK;
+}

@@ -104,3 +104,27 @@ def test_layers_and_counts_full_size_geometry():
     assert hub3.nlayers == 1                      # non-overlapping spheres: one layer
     assert hub3.nentries == 759292 and hub3.J == 272
     assert hub3.ngrouped > 0 and hub3.nfmax == 7
+
+
+@pytest.mark.parametrize("l,zeta,t", [(0, 1.0, 1e-3), (1, 1.6, 1e-2), (2, 2.2, 5e-3), (2, 2.2, 1e-4), (3, 2.4, 1e-3)])
+def test_sphere_radius_matches_oracle(l, zeta, t):
+    from oracle import radius as RA
+    rc = H.sphere_radius("threshold", l=l, zeta=zeta, threshold=t)
+    assert abs(rc - RA.radius_threshold(l, zeta, t)) < 1e-12 * rc
+    assert H.sphere_radius("cell", cell=[8.35, 7.1, 9.0]) == RA.radius_cell([8.35, 7.1, 9.0])
+
+
+def test_sphere_radius_rejects_bad_arguments():
+    lib = H.lib()
+    rc = ctypes.c_double(0.0)
+    bad = [(H.HUB_RADIUS_THRESHOLD, 2, 2.2, None, 1.0),      # above the peak of R
+           (H.HUB_RADIUS_THRESHOLD, 4, 2.2, None, 1e-3),     # l out of range
+           (H.HUB_RADIUS_THRESHOLD, 1, -1.0, None, 1e-3),
+           (H.HUB_RADIUS_THRESHOLD, 1, 1.0, None, 0.0),
+           (H.HUB_RADIUS_CELL, 0, 1.0, None, 0.0),           # no cell
+           (7, 0, 1.0, None, 0.0)]
+    for m, l, z, cell, t in bad:
+        assert lib.hub_sphere_radius(m, l, z, cell, t, ctypes.byref(rc)) == H.HUB_EINVAL
+    neg = (ctypes.c_double * 3)(1.0, -2.0, 3.0)
+    assert lib.hub_sphere_radius(H.HUB_RADIUS_CELL, 0, 1.0, neg, 0.0, ctypes.byref(rc)) == H.HUB_EINVAL
+    assert lib.hub_sphere_radius(H.HUB_RADIUS_THRESHOLD, 1, 1.0, None, 1e-3, None) == H.HUB_EINVAL
