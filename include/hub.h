@@ -247,6 +247,20 @@ int hub_apply(hub_ctx* ctx, const double* Ueff, const double* n, const double* c
  * twice).  Ueff, n, EU: device. */
 int hub_energy(hub_ctx* ctx, const double* Ueff, const double* n, double* EU);
 
+/* Energy bookkeeping of App. A per site, from the occupations n (layout of
+ * hub_occupations) and the site's U and J (e.g. U-bar and J-bar of
+ * hub_acbn0_uj): out[6 * I + 0..5] = N, m_x, m_y, m_z, E_DC, E_ee with
+ *   N = sum_s sum_a n^{ss}_aa (unpolarized contexts count both spins),
+ *   m_i = sum_st (sigma_i)_st rho^{st}, rho^{st} = sum_a n^{st}_aa (the
+ *   magnetization of the shell: m_x = 2 Re rho^{ud}, m_y = 2 Im rho^{ud},
+ *   m_z = rho^{uu} - rho^{dd}; collinear: (0, 0, N_up - N_dn)),
+ *   E_DC = U/2 N(N-1) - J/2 N(N/2-1) - J/4 m.m (fully localized limit),
+ *   E_ee = the noncollinear Hartree-Fock energy of App. A written for
+ *   occupations diagonal in m, evaluated on the diagonal elements n^{st}_aa.
+ * For m-diagonal occupations E_ee - E_DC equals hub_energy's E_U at
+ * U_eff = U - J.  U, J, n, out: device. */
+int hub_energy_fll(hub_ctx* ctx, const double* U, const double* J, const double* n, double* out);
+
 /* Hubbard forces (Sec. IV) with frozen sphere membership and normalization:
  * F[I][i] = g_s * 2 Re sum_q w_k sum_s f_s sum_ab V_ab conj(d_{a,i}) c_b,
  * d = dV sum_p exp(i k.T_p) (d phi_a / d r_i)(r_p) psi[g(p)], g_s = 2 for

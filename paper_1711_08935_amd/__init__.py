@@ -44,7 +44,8 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_site_info", "hub_site_points", "hub_project", "hub_occupations", "hub_coulomb",
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
-           "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius"]
+           "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
+           "hub_energy_fll"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -81,6 +82,7 @@ def lib():
         "hub_current": [P, P, I64, I, P, P, P, P, P],
         "hub_forces_state_gradient": [P, P, I64, I, P, P, P, P, P],
         "hub_sphere_radius": [I, I, D, DP, D, DP],
+        "hub_energy_fll": [P, P, P, P, P],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -355,6 +357,14 @@ class Hubbard:
         self._stream()
         _check(lib().hub_energy(self._ctx, _dptr(Ueff), _dptr(n), _dptr(EU)), "hub_energy")
         return EU
+
+    def energy_fll(self, U, J, n):
+        """(n_sites, 6) per site: N, m_x, m_y, m_z, E_DC, E_ee (App. A)."""
+        out = torch.empty((self.nsites, 6), dtype=torch.float64, device="cuda")
+        self._stream()
+        _check(lib().hub_energy_fll(self._ctx, _dptr(self._dev(U)), _dptr(self._dev(J)), _dptr(n), _dptr(out)),
+               "hub_energy_fll")
+        return out
 
     def set_vector_potential(self, A=None):
         """Uniform vector potential A (3 floats, bohr^-1) of the velocity

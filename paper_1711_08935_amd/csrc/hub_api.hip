@@ -1008,6 +1008,21 @@ int hub_energy(hub_ctx* c, const double* Ueff, const double* n, double* EU) {
     return HUB_OK;
 }
 
+int hub_energy_fll(hub_ctx* c, const double* U, const double* J, const double* n, double* out) {
+    if (!c || !U || !J || !n || !out) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    FllArgs a{};
+    a.n = n;
+    a.U = U;
+    a.J = J;
+    a.out = out;
+    a.site_L = c->d_site_L;
+    a.nsites = c->T.nsites;
+    a.nblk = c->nblk();
+    HUB_TRY(launch_fll(a, c->stream));
+    return HUB_OK;
+}
+
 namespace {
 
 // Forces (table TAB_GRAD, real part) or velocity-gauge current (TAB_MOMENT,

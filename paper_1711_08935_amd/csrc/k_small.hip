@@ -425,6 +425,73 @@ __global__ void k_energy(const EnergyArgs a) {
     a.EU[site] = 0.5 * a.Ueff[site] * val;
 }
 
+// ---------------------------------------------------------------- FLL terms
+// App. A, per site from the diagonal elements d(s,t,a) = n^{st}_aa: the shell
+// electron count N, the magnetization m_i = sum_st (sigma_i)_st rho^{st}
+// (rho^{st} = sum_a d(s,t,a)), the double counting
+// E_DC = U/2 N(N-1) - J/2 N(N/2-1) - J/4 m.m and the Hartree-Fock energy
+// written for m-diagonal occupations.  Collinear blocks have no
+// spin-off-diagonal part; an unpolarized block stands for both spins.
+__global__ void k_fll(const FllArgs a) {
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= a.nsites) return;
+    const int L = a.site_L[site];
+    const double* nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
+    // d(s,t,a) as (re, im); zero where the storage has no such block
+    auto d = [&](int s, int t, int o, double& re, double& im) {
+        int blk = -1;
+        if (a.nblk == 4) blk = 2 * s + t;
+        else if (s == t) blk = a.nblk == 2 ? s : 0;
+        if (blk < 0) { re = im = 0.0; return; }
+        re = nb[blk * 98 + (o * 7 + o) * 2];
+        im = nb[blk * 98 + (o * 7 + o) * 2 + 1];
+    };
+    double rr[2][2], ri[2][2];          // rho^{st}
+    double sdd[2] = {0.0, 0.0};         // sum_a d(s,s,a)^2
+    double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};   // sum_a d(s,o,a) d(o,s,a)
+    for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) {
+            rr[s][t] = ri[s][t] = 0.0;
+            for (int o = 0; o < L; ++o) {
+                double re, im;
+                d(s, t, o, re, im);
+                rr[s][t] += re;
+                ri[s][t] += im;
+            }
+        }
+    for (int s = 0; s < 2; ++s)
+        for (int o = 0; o < L; ++o) {
+            double ar, ai, br, bi, cr, ci;
+            d(s, s, o, ar, ai);
+            sdd[s] += ar * ar - ai * ai;
+            d(s, 1 - s, o, br, bi);
+            d(1 - s, s, o, cr, ci);
+            xr[s] += br * cr - bi * ci;
+            xi[s] += br * ci + bi * cr;
+        }
+    const double U = a.U[site], J = a.J[site];
+    const double N = rr[0][0] + rr[1][1];
+    const double m[3] = {2.0 * rr[0][1], 2.0 * ri[0][1], rr[0][0] - rr[1][1]};
+    const double mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    const double edc = 0.5 * U * N * (N - 1.0) - 0.5 * J * N * (0.5 * N - 1.0) - 0.25 * J * mm;
+    double eee = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const int o = 1 - s;
+        // sum_{a,b} d(s,s,a) d(o,o,b), sum_{a!=b} d(s,o,a) d(o,s,b), sum_{a!=b} d(s,s,a) d(s,s,b)  (real parts)
+        const double same = rr[s][s] * rr[o][o] - ri[s][s] * ri[o][o];
+        const double flip = (rr[s][o] * rr[o][s] - ri[s][o] * ri[o][s]) - xr[s];
+        const double par = (rr[s][s] * rr[s][s] - ri[s][s] * ri[s][s]) - sdd[s];
+        eee += 0.5 * U * same - 0.5 * U * xr[s] - 0.5 * J * flip + 0.5 * (U - J) * par;
+    }
+    double* out = a.out + static_cast<int64_t>(site) * 6;
+    out[0] = N;
+    out[1] = m[0];
+    out[2] = m[1];
+    out[3] = m[2];
+    out[4] = edc;
+    out[5] = eee;
+}
+
 // ---------------------------------------------------------------- forces
 // F_i = g_s 2 Re sum_q w_k sum_col f_s sum_a conj(d_{a,i}(col)) B_a(col),
 // B = V c as in the apply kernel (Sec. IV with U_eff fixed).
@@ -587,6 +654,12 @@ hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t s
     b.Ueff += site0;
     if (b.status) b.status += site0;
     hipLaunchKernelGGL(k_acbn0, dim3(nsites), dim3(NB), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fll(const FllArgs& a, hipStream_t st) {
+    if (a.nsites <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fll, dim3((a.nsites + 63) / 64), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -63,6 +63,12 @@ struct EnergyArgs {
     const int32_t* site_L; int nsites; int nblk;
 };
 
+// Per site: N, m_x, m_y, m_z, E_DC, E_ee (App. A).
+struct FllArgs {
+    const double* n; const double* U; const double* J; double* out;
+    const int32_t* site_L; int nsites; int nblk;
+};
+
 struct ForceArgs {
     const double* c; const double* d; const double* f; const double* n; const double* ueff;
     const double* kweights; double* F;
@@ -101,5 +107,6 @@ hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st);
 hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t st);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
 hipError_t launch_forces(const ForceArgs& a, hipStream_t st);
+hipError_t launch_fll(const FllArgs& a, hipStream_t st);
 hipError_t launch_gauge_tables(const GaugeArgs& a, hipStream_t st);
 hipError_t launch_coulomb(const CoulombArgs& a, hipStream_t st);

@@ -3,7 +3,8 @@
 Reduced workloads (all five shapes, both storage precisions) that still span
 several chunks, column tiles and a ragged tail of columns.  Bars:
 * FP64 states: normwise relative error <= 1e-12 for c, n, P-bar, N-bar, the
-  Coulomb tensors, U-bar, J-bar, E_U, V_U psi and forces.
+  Coulomb tensors, U-bar, J-bar, E_U, V_U psi, forces and the App. A
+  energy terms (N, m, E_DC, E_ee).
 * FP32 states: the oracle runs on the FP32-rounded states upcast to FP64, so
   what is compared is the kernels' arithmetic; occupations and U/J must agree
   to 1e-9 absolute (they agree far better), V_U psi to the FP32 rounding of
@@ -22,6 +23,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_1711_08935_amd as H  # noqa: E402
+from oracle import fll as OFL  # noqa: E402
 from oracle import forces as OF  # noqa: E402
 from oracle import potential as OPOT  # noqa: E402
 from synth import make_config  # noqa: E402
@@ -109,6 +111,22 @@ def test_apply_and_energy(case):
     for sp in case["sps"]:
         covered[sp.g] = True
     assert np.all(h[:, ~covered] == 0)
+
+
+def test_energy_fll(case):
+    """N, m, E_DC and E_ee (App. A) from each side's own n, U-bar, J-bar."""
+    hub, ref = case["hub"], case["ref"]
+    out = hub.energy_fll(case["U"], case["J"], case["n"]).cpu().numpy()
+    sys_ = case["sys"]
+    rows = []
+    for I in range(hub.nsites):
+        N, m = OFL.moments(sys_, ref["n"][I])
+        U, J = ref["U"][I], ref["J"][I]
+        rows.append([N, *m, OFL.double_counting(N, m, U, J), OFL.hf_energy(sys_, ref["n"][I], U, J)])
+    rows = np.array(rows)
+    assert normwise(out[:, :4], rows[:, :4]) < 1e-12
+    scale = max(1e-3, np.abs(rows[:, 4:]).max())
+    assert np.max(np.abs(out[:, 4:] - rows[:, 4:])) <= 1e-12 * scale
 
 
 def test_step_modes_agree_and_graph_replays(case):
