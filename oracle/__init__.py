@@ -32,6 +32,7 @@ Modules (each function cites the passage it follows):
                   correction (Sec. V)
 * ``fll``         noncollinear HF energy and FLL double counting with the
                   magnetization of the shell (App. A)
+* ``spinorb``     spin-dependent orbitals of noncollinear runs (App. A)
 * ``radius``      sphere radius selection (Sec. II, radius discussion)
 * ``stencil``     forces through <phi|grad psi> with a 4th-order central
                   difference of the states (Sec. IV, the paper's own form)
@@ -41,5 +42,5 @@ independent property fixes are listed there and in the design doc as
 "parity unpinned".
 """
 
-from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step, gauge, stencil, radius, fll  # noqa: F401
+from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step, gauge, stencil, radius, fll, spinorb  # noqa: F401
 from .orbitals import System, Site  # noqa: F401

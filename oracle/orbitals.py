@@ -40,6 +40,7 @@ class Site:
     zeta: float
     rc: float
     species: int = 0
+    zeta_dn: float = None        # spin-down exponent of spinor orbitals (spinorb.py); None: zeta
 
     @property
     def L(self):

@@ -7,8 +7,8 @@ from oracle.orbitals import Site, System
 
 
 def to_system(cfg):
-    sites = [Site(R=np.array(s["R"]), l=s["l"], zeta=s["zeta"], rc=s["rc"], species=s["species"])
-             for s in cfg.sites]
+    sites = [Site(R=np.array(s["R"]), l=s["l"], zeta=s["zeta"], rc=s["rc"], species=s["species"],
+                  zeta_dn=s.get("zeta_dn")) for s in cfg.sites]
     return System(cell=np.array(cfg.cell), ngrid=np.array(cfg.ngrid), sites=sites,
                   kpts=np.array(cfg.kpts), kweights=np.array(cfg.kweights), spin=cfg.spin)
 

@@ -1,0 +1,102 @@
+"""Pins for oracle.spinorb: spin-dependent orbitals of noncollinear runs
+(App. A).
+
+* Without a spin-down exponent (or with zeta_dn = zeta) the projection and
+  the apply are the spin-independent spinor forms of projection.py and
+  potential.py.
+* With zeta_dn != zeta: the sphere forms equal the full-cell definitions
+  (spheres past half the cell); a state with only one spin component
+  projects like a one-component state onto that component's orbital.
+* V_U psi is the derivative of E_U with these projections: central finite
+  differences of sum_I E_U along a random direction give
+  2 Re sum dV w f <delta|V_U psi>.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import occupations as occ
+from oracle import potential as POT
+from oracle import projection as P
+from oracle import spinorb as SO
+from oracle.orbitals import Site, System
+from tests.helpers import normwise
+
+
+def _system(zdn=(2.3, None)):
+    return System(cell=[6.0, 6.5, 7.0], ngrid=[12, 13, 14],
+                  sites=[Site(R=[0.3, 6.2, 3.3], l=2, zeta=1.6, rc=3.4, species=0, zeta_dn=zdn[0]),
+                         Site(R=[3.1, 3.0, 0.5], l=1, zeta=1.3, rc=2.8, species=1, zeta_dn=zdn[1])],
+                  kpts=np.array([[0.25, -0.25, 0.5], [0.0, 0.25, 0.0]]), kweights=np.full(2, 0.5), spin="spinor")
+
+
+def _states(sys_, S, seed):
+    rng = np.random.default_rng(seed)
+    shape = (sys_.nk, sys_.G, S, 2)
+    return (rng.normal(size=shape) + 1j * rng.normal(size=shape)) * np.sqrt(1.0 / (sys_.G * sys_.dV))
+
+
+def _V(sys_, c, f, ueffs=(0.35, 0.2)):
+    n, _, _ = occ.occupations(sys_, c, f, with_pbar=False)
+    return [POT.potential_matrix(sys_, u, nn) for u, nn in zip(ueffs, n)], n
+
+
+@pytest.mark.parametrize("zdn", [(None, None), (1.6, 1.3)])
+def test_spin_independent_limit(zdn):
+    sys_ = _system(zdn)
+    psi = _states(sys_, 3, 1)
+    f = np.random.default_rng(2).uniform(0.0, 1.0, size=(sys_.nk, 3))
+    c = SO.project_spin(sys_, psi)
+    ref = P.project_fullgrid(sys_, psi)
+    assert normwise(c, ref) < 1e-13
+    V, _ = _V(sys_, c, f)
+    assert normwise(SO.apply_spin(sys_, c, V), POT.apply_fullgrid(sys_, c, V)) < 1e-13
+
+
+def test_sphere_form_equals_definition():
+    sys_ = _system()
+    psi = _states(sys_, 3, 3)
+    f = np.random.default_rng(4).uniform(0.0, 1.0, size=(sys_.nk, 3))
+    c = SO.project_spin(sys_, psi)
+    assert normwise(SO.project_spin(sys_, psi, form="sphere"), c) < 1e-13
+    assert normwise(c, P.project_fullgrid(sys_, psi)) > 1e-3        # the spin-down orbitals differ
+    V, _ = _V(sys_, c, f)
+    assert normwise(SO.apply_spin(sys_, c, V, form="sphere"), SO.apply_spin(sys_, c, V)) < 1e-13
+
+
+@pytest.mark.parametrize("sg", [0, 1])
+def test_single_component_states(sg):
+    sys_ = _system()
+    psi = _states(sys_, 3, 5)
+    psi[..., 1 - sg] = 0.0
+    c = SO.project_spin(sys_, psi)
+    assert np.all(c[..., 1 - sg] == 0.0)
+    zeta = [s.zeta if sg == 0 or s.zeta_dn is None else s.zeta_dn for s in sys_.sites]
+    one = System(cell=sys_.cell, ngrid=sys_.ngrid,
+                 sites=[Site(R=s.R, l=s.l, zeta=z, rc=s.rc, species=s.species) for s, z in zip(sys_.sites, zeta)],
+                 kpts=sys_.kpts, kweights=sys_.kweights, spin="unpolarized")
+    assert normwise(c[..., sg], P.project_sphere(one, psi[..., sg], P.all_spheres(one))) < 1e-13
+
+
+def _energy(sys_, psi, f, ueffs):
+    c = SO.project_spin(sys_, psi, form="sphere")
+    n, _, _ = occ.occupations(sys_, c, f, with_pbar=False)
+    return sum(POT.energy(sys_, u, nn) for u, nn in zip(ueffs, n))
+
+
+def test_apply_is_energy_derivative():
+    sys_ = _system()
+    psi = _states(sys_, 3, 6)
+    f = np.random.default_rng(7).uniform(0.0, 1.0, size=(sys_.nk, 3))
+    ueffs = (0.35, 0.2)
+    c = SO.project_spin(sys_, psi, form="sphere")
+    V, _ = _V(sys_, c, f, ueffs)
+    hpsi = SO.apply_spin(sys_, c, V, form="sphere")
+    rng = np.random.default_rng(8)
+    delta = rng.normal(size=psi.shape) + 1j * rng.normal(size=psi.shape)
+    eps = 1e-5
+    fd = (_energy(sys_, psi + eps * delta, f, ueffs) - _energy(sys_, psi - eps * delta, f, ueffs)) / (2 * eps)
+    wf = sys_.kweights[:, None] * f
+    an = 2.0 * sys_.dV * np.sum(np.conj(delta) * hpsi * wf[:, None, :, None]).real
+    assert abs(an) > 1e-6
+    assert abs(fd - an) < 1e-7 * abs(an)
