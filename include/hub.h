@@ -120,6 +120,21 @@ int hub_add_site(hub_ctx* ctx, const double R[3], int l, double zeta, double rc,
 #define HUB_RADIUS_THRESHOLD 2
 int hub_sphere_radius(int method, int l, double zeta, const double cell[3], double threshold, double* rc);
 
+/* Spin-dependent orbitals (App. A: the localized basis may be spinors):
+ * give site a Slater exponent zeta_dn for the orbitals of the spin-down
+ * component (same l, sphere and points; each component normalized on the
+ * grid on its own), so that spin component sigma of the states is projected
+ * on, and V_U psi built from, phi^sigma:
+ * n^{st}_ab = sum w f conj(<phi^s_a|psi^s>) <phi^t_b|psi^t>.  Spinor
+ * contexts only, before hub_finalize*.  A context with such a site uses the
+ * per-site work list (table of 2L values per entry), takes a fixed U_eff for
+ * these sites (hub_set_fixed_ueff; hub_coulomb skips them and rejects them
+ * by index), and has no forces, current or velocity-gauge form
+ * (HUB_ESTATE / HUB_EINVAL).  Errors: HUB_EINVAL (bad site, zeta_dn not
+ * positive and finite, not a spinor context), HUB_ESTATE (after
+ * finalize). */
+int hub_set_site_spin_orbital(hub_ctx* ctx, int site, double zeta_dn);
+
 /* Fix the effective U of one site (the empirical DFT+U scheme, Sec. II);
  * pass NaN to return the site to ACBN0 (the default).  Any time. */
 int hub_set_fixed_ueff(hub_ctx* ctx, int site, double ueff);

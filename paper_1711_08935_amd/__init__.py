@@ -45,7 +45,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
            "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
-           "hub_energy_fll"]
+           "hub_energy_fll", "hub_set_site_spin_orbital"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -83,6 +83,7 @@ def lib():
         "hub_forces_state_gradient": [P, P, I64, I, P, P, P, P, P],
         "hub_sphere_radius": [I, I, D, DP, D, DP],
         "hub_energy_fll": [P, P, P, P, P],
+        "hub_set_site_spin_orbital": [P, I, D],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -165,6 +166,10 @@ class Hubbard:
             sid = ctypes.c_int()
             _check(L.hub_add_site(self._ctx, _darr(s["R"]), int(s["l"]), float(s["zeta"]), float(s["rc"]),
                                   int(s.get("species", 0)), ctypes.byref(sid)), "hub_add_site")
+            if s.get("zeta_dn") is not None:
+                # spin-dependent orbitals (spinor contexts): spin-down Slater exponent
+                _check(L.hub_set_site_spin_orbital(self._ctx, sid.value, float(s["zeta_dn"])),
+                       "hub_set_site_spin_orbital")
         if chunk is not None:
             _check(L.hub_set_chunk(self._ctx, int(chunk)), "hub_set_chunk")
         _check(L.hub_finalize_host(self._ctx), "hub_finalize_host")

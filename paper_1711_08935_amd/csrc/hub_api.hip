@@ -57,6 +57,7 @@ struct hub_ctx {
     HubChunk* d_chunks = nullptr;
     int32_t *d_all = nullptr, *d_gidx = nullptr, *d_img = nullptr;
     double *d_phi = nullptr, *d_gphi = nullptr, *d_phase = nullptr;
+    double* d_phi2 = nullptr;                // [e][sigma][m] spin-dependent orbitals
     int32_t *d_site_chunk_ptr = nullptr, *d_site_chunk_ids = nullptr, *d_orb_site = nullptr;
     int32_t *d_site_L = nullptr, *d_site_orb0 = nullptr, *d_site_species = nullptr;
     int32_t *d_species_orb_ptr = nullptr, *d_species_orb_ids = nullptr;
@@ -154,6 +155,7 @@ void release(hub_ctx* c) {
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
     f(c->d_pg); f(c->d_mphi); f(c->d_images); f(c->d_kred);
     c->d_pg = nullptr;
+    f(c->d_phi2);
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
@@ -324,6 +326,11 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table)
     a.gidx = c->d_gidx;
     a.tab = table == TAB_GRAD ? c->d_gphi : (table == TAB_MOMENT ? c->d_mphi : c->d_phi);
     a.tabmult = grad ? 3 : 1;
+    if (table == TAB_PHI && c->T.spindep) {
+        // both spin components' orbitals: 2L functions per entry
+        a.tab = c->d_phi2;
+        a.tabmult = 2;
+    }
     a.prows = c->T.part_rows * a.tabmult;
     if (table == TAB_STENCIL) {
         a.chunks = c->d_st_chunks;
@@ -345,11 +352,14 @@ ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
     r.ncol = ncol;
     r.ncplx = c->ncplx();
     r.mult = mult;
+    r.pmult = mult;
+    r.spindep = 0;
     r.chunks = c->d_chunks;
     r.site_chunk_ptr = c->d_site_chunk_ptr;
     r.site_chunk_ids = c->d_site_chunk_ids;
     r.orb_site = c->d_orb_site;
     r.site_orb0 = c->d_site_orb0;
+    r.site_L = c->d_site_L;
     r.phase = c->d_phase;
     r.nimg = static_cast<int>(c->T.images.size() / 3);
     r.nspin = c->nspin();
@@ -368,9 +378,10 @@ size_t part_need(const hub_ctx* c, int ncol, int mult) {
 int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site,
                int table = TAB_PHI) {
     const bool grad = table != TAB_PHI;
+    const bool spindep = !grad && c->T.spindep;
     const int ncol = c->ncol(nstates);
     const int mult = grad ? 3 : 1;
-    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, mult), c);
+    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, spindep ? 2 : mult), c);
     if (st) return st;
     ProjArgs a = proj_args(c, psi, ld, ncol, table);
     a.part = c->d_part;
@@ -413,7 +424,8 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         return HUB_OK;
     }
     int cpl = pick_cpl(c, psi, ld, 0);
-    if (grad && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();     // gradient tiles hold 3L functions
+    // gradient tiles hold 3L functions, spin-dependent tiles 2L
+    if ((grad || spindep) && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();
     a.wide = pick_wide(c, ncol, cpl, 0);
     const int waves = c->tune_waves[0];
     {
@@ -431,6 +443,12 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     }
     }
     ReduceArgs r = reduce_args(c, out, ncol, mult);
+    if (spindep) {
+        // column 2s + sigma takes the rows of its spin component's orbitals
+        r.pmult = 2;
+        r.spindep = 1;
+        r.prows = c->T.part_rows * 2;
+    }
     if (table == TAB_STENCIL) {
         r.chunks = c->d_st_chunks;
         r.site_chunk_ptr = c->d_st_site_ptr;
@@ -578,7 +596,13 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
             return launch_apply_grouped(b, nch, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
         });
     }
-    const int cpl = pick_cpl(c, hpsi, ld, 1);
+    int cpl = pick_cpl(c, hpsi, ld, 1);
+    if (c->T.spindep) {
+        // 2L functions per entry: both spin components' orbitals
+        a.tab = c->d_phi2;
+        a.spindep = 1;
+        if (cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();
+    }
     a.wide = pick_wide(c, ncol, cpl, 1);
     const int waves = c->tune_waves[1];
     const int ns = c->T.nsites;
@@ -689,8 +713,17 @@ int hub_add_site(hub_ctx* c, const double R[3], int l, double zeta, double rc, i
     s.rc = rc;
     s.species = species;
     s.ueff_fixed = std::nan("");
+    s.zeta_dn = std::nan("");
     c->sites.push_back(s);
     if (site_id) *site_id = static_cast<int>(c->sites.size()) - 1;
+    return HUB_OK;
+}
+
+int hub_set_site_spin_orbital(hub_ctx* c, int site, double zeta_dn) {
+    if (!c || site < 0 || site >= static_cast<int>(c->sites.size())) return HUB_EINVAL;
+    if (c->built_host) return HUB_ESTATE;
+    if (c->spin_mode != HUB_SPINOR || !(zeta_dn > 0.0) || !std::isfinite(zeta_dn)) return HUB_EINVAL;
+    c->sites[site].zeta_dn = zeta_dn;
     return HUB_OK;
 }
 
@@ -796,6 +829,7 @@ int hub_finalize(hub_ctx* c, void* stream) {
     up(&c->d_img, T.img);
     up(&c->d_phi, T.phi);
     up(&c->d_gphi, T.gphi);
+    if (T.spindep) up(&c->d_phi2, T.phi2);
     up(&c->d_mphi, T.mphi);
     up(&c->d_images, T.images);
     up(&c->d_kred, c->kred);
@@ -932,6 +966,8 @@ int hub_coulomb(hub_ctx* c, int site, double* tensor) {
     const int ns = c->T.nsites;
     if (site < -1 || site >= ns) return HUB_EINVAL;
     if (site == -1 && tensor) return HUB_EINVAL;
+    // sites with spin-dependent orbitals take a fixed U_eff (no ACBN0 tensor)
+    if (site >= 0 && std::isfinite(c->sites[site].zeta_dn)) return HUB_EINVAL;
     const int s0 = site < 0 ? 0 : site, s1 = site < 0 ? ns : site + 1;
     size_t maxp = 1;
     for (int s = s0; s < s1; ++s) maxp = std::max(maxp, c->T.spheres[s].g.size());
@@ -945,6 +981,7 @@ int hub_coulomb(hub_ctx* c, int site, double* tensor) {
     for (int i = 0; i < 3; ++i) h[i] = c->cell[i] / c->ngrid[i];
     const double g0 = hub_g0_cell_average(h);
     for (int s = s0; s < s1 && e == hipSuccess; ++s) {
+        if (std::isfinite(c->sites[s].zeta_dn)) continue;
         const SiteSphere& sp = c->T.spheres[s];
         const int L = c->T.site_L[s];
         e = hipMemcpyAsync(d_ijk, sp.ijk.data(), sp.ijk.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
@@ -1032,6 +1069,7 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
                      const double* Ueff, const double* n, double* out, int table) {
     if (!c || !cc || !f || !Ueff || !n || !out) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
+    if (c->T.spindep) return HUB_ESTATE;        // no gradient tables of spin-dependent orbitals
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
     const int ncol = c->ncol(nstates);
     const size_t need = static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx();
@@ -1140,6 +1178,8 @@ int hub_set_vector_potential(hub_ctx* c, const double* A) {
     if (!c) return HUB_EINVAL;
     if (A) {
         if (!c->is_complex) return HUB_EINVAL;
+        for (const SiteDef& sd : c->sites)
+            if (std::isfinite(sd.zeta_dn)) return HUB_EINVAL;    // no gauge form of spin-dependent orbitals
         for (int i = 0; i < 3; ++i)
             if (!std::isfinite(A[i])) return HUB_EINVAL;
     }
@@ -1163,7 +1203,7 @@ int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
     // the step needs the projection workspace and the N-bar buffer; size them
     // before any capture so that the graph never sees a reallocation
     const int ncol = c->ncol(io->nstates);
-    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, 1), c);
+    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, c->T.spindep ? 2 : 1), c);
     if (st) return st;
     if (!io->nbar) {
         st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);

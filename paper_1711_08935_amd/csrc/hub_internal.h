@@ -38,6 +38,7 @@ struct SiteDef {
     double rc;
     int species;
     double ueff_fixed;   // NaN: ACBN0
+    double zeta_dn;      // spin-down exponent of spinor orbitals; NaN: zeta
 };
 
 // Host copy of one site's sphere, points sorted by (g, image).
@@ -47,6 +48,7 @@ struct SiteSphere {
     std::vector<int32_t> ijk;    // unfolded integer coordinates (3 per point)
     std::vector<double> phi;     // [p][m]
     std::vector<double> grad;    // [p][m][3]
+    std::vector<double> phi_dn;  // [p][m], spin-down orbitals (spin-dependent contexts)
 };
 
 // Largest number of functions (orbitals of all covering sites) a grouped
@@ -80,6 +82,11 @@ struct HostTables {
     std::vector<double> phi;                 // per entry, L values
     std::vector<double> gphi;                // per entry, 3L values [m][i]
     std::vector<double> mphi;                // per entry, 3L values [m][i]: (r_p - R)_i phi_m
+    // Spin-dependent orbitals (some site has a spin-down exponent): per
+    // entry 2L values [sigma][m], the orbital of each spin component (sites
+    // without one repeat their orbital); the grouped list is then not built.
+    bool spindep = false;
+    std::vector<double> phi2;
     std::vector<int32_t> images;             // unique lattice images, 3 per image
     std::vector<int32_t> site_chunk_ptr;     // CSR site -> chunk ids
     std::vector<int32_t> site_chunk_ids;

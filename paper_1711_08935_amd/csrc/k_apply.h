@@ -40,10 +40,12 @@ namespace {
 // B of one function (orbital ai of a site, seen through lattice image img)
 // for the CPL columns col0.. of state set q:
 // B = alpha scale exp(-i k.T_img) sum_b V_{ai b} c_b (spinor: with the spin
-// blocks).  Columns past ncol get B = 0.
+// blocks).  Columns past ncol get B = 0, and so do spinor columns of the
+// other spin component when the function is the orbital of component sgf
+// (spin-dependent orbitals; sgf < 0: both components).
 template <bool CPX, bool SPINOR, int CPL>
 __device__ __forceinline__ void coefficient(const ApplyArgs& a, int site, int ai, int img, int q, int col0,
-                                            double (&Bf)[CPL * (CPX ? 2 : 1)]) {
+                                            double (&Bf)[CPL * (CPX ? 2 : 1)], int sgf = -1) {
     constexpr int NC = CPX ? 2 : 1;
     const int ch = SPINOR ? 0 : (q % a.nspin);
     const int k = a.spinor ? q : q / a.nspin;
@@ -66,7 +68,7 @@ __device__ __forceinline__ void coefficient(const ApplyArgs& a, int site, int ai
             const int s = SPINOR ? (col >> 1) : col;
             sc *= a.colscale[static_cast<int64_t>(q) * a.nstates + s];
         }
-        if (!ok) sc = 0.0;
+        if (!ok || (sgf >= 0 && (col & 1) != sgf)) sc = 0.0;
         const int colc = ok ? col : 0;
         double br = 0.0, bi = 0.0;
         if constexpr (!SPINOR) {
@@ -115,8 +117,12 @@ __device__ __forceinline__ void coefficient(const ApplyArgs& a, int site, int ai
 }
 
 // Bs: LDS of the work-group, at least L * NV * HUB_WAVE doubles.
-// chunk: the chunk's index in the work-group's launch list; tile: column tile
-template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE, bool GROUPED, bool GAUGE>
+// chunk: the chunk's index in the work-group's launch list; tile: column tile.
+// L: functions per entry; SPINDEP: per-site chunks of spin-dependent orbitals,
+// function sigma * (L/2) + m is orbital m of spin component sigma, whose
+// coefficient is nonzero only in that component's columns.
+template <typename T, bool CPX, bool SPINOR, int CPL, int L, bool WIDE, bool GROUPED, bool GAUGE,
+          bool SPINDEP = false>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C, int chunk_slot, int tile,
                                            const int32_t* __restrict__ gidx, const double* __restrict__ tab,
                                            const double* __restrict__ pg, T* __restrict__ hpsi, double* Bs) {
@@ -154,11 +160,11 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
             ai = j - a.site_orb0[site];
         } else {
             site = C.site;
-            ai = f;
+            ai = SPINDEP ? f % C.L : f;
             img = C.img;
         }
         double Bf[NV];
-        coefficient<CPX, SPINOR, CPL>(a, site, ai, img, q, active ? col0 : a.ncol, Bf);
+        coefficient<CPX, SPINOR, CPL>(a, site, ai, img, q, active ? col0 : a.ncol, Bf, SPINDEP ? f / C.L : -1);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Bs[(f * NV + v) * HUB_WAVE + lane] = Bf[v];
     }
@@ -175,7 +181,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     int lo, nj;
     hub_wave_range(C.ne, nw, wave, lo, nj);
     const int32_t* __restrict__ gi = gidx + C.e0 + lo;
-    const double* __restrict__ tb = tab + (C.phi0 + static_cast<int64_t>(lo) * L);
+    const double* __restrict__ tb = tab + (C.phi0 * (SPINDEP ? 2 : 1) + static_cast<int64_t>(lo) * L);
     const int lofs = col0 * NC;
 
     // whole batches of U entries (chunk lengths are multiples of
@@ -263,18 +269,20 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
 // The sphere tables and the output are separate restrict-qualified kernel
 // arguments: the stores into hpsi inside the entry loop then cannot alias the
 // table reads, and the uniform entry data stays on scalar loads.
-template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, bool GAUGE>
+template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, bool GAUGE, bool SPINDEP = false>
 __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t* __restrict__ gidx,
                                                const double* __restrict__ tab, const double* __restrict__ pg,
                                                T* __restrict__ hpsi) {
     constexpr int NV = CPL * (CPX ? 2 : 1);
-    __shared__ double Bs[7 * NV * HUB_WAVE];
+    constexpr int M = SPINDEP ? 2 : 1;
+    __shared__ double Bs[7 * M * NV * HUB_WAVE];
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
     const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
     switch (C.L) {
 #define HUB_PCALL(n) \
-    apply_body<T, CPX, SPINOR, CPL, n, WIDE, false, GAUGE>(a, C, slot.chunk, slot.tile, gidx, tab, pg, hpsi, Bs)
+    apply_body<T, CPX, SPINOR, CPL, M * n, WIDE, false, GAUGE, SPINDEP>(a, C, slot.chunk, slot.tile, gidx, tab, pg, \
+                                                                        hpsi, Bs)
     case 1: HUB_PCALL(1); break;
     case 3: HUB_PCALL(3); break;
     case 5: HUB_PCALL(5); break;
@@ -377,6 +385,21 @@ hipError_t launch_t(const ApplyArgs& a, int nchunks, int nq, int waves, hipStrea
                                       : (static_cast<int64_t>(nq) * cg + HUB_WAVE - 1) / HUB_WAVE);
     const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
     T* h = reinterpret_cast<T*>(b.hpsi);
+    if (a.spindep) {
+        // spin-dependent spinor orbitals: 2L coefficients per lane column
+        if constexpr (SPINOR && CPL <= 2) {
+            if (a.pg) return hipErrorInvalidValue;
+            if (a.wide)
+                hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, true, false, true>), grid, dim3(HUB_WAVE * waves), 0,
+                                   st, b, b.gidx, b.tab, b.pg, h);
+            else
+                hipLaunchKernelGGL((k_apply<T, CPX, SPINOR, CPL, false, false, true>), grid, dim3(HUB_WAVE * waves), 0,
+                                   st, b, b.gidx, b.tab, b.pg, h);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (a.pg) {
         // velocity gauge: complex states only
         if constexpr (CPX) {

@@ -188,13 +188,15 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     }
 }
 
-// NV = scalars per lane (columns per lane times 1 or 2); GRAD selects the
-// gradient table (three functions per orbital); WIDE the lane layout; CLS
-// the function-count class of the launched chunks (0: per-site chunks).
+// NV = scalars per lane (columns per lane times 1 or 2); MULT the functions
+// per orbital of the table (1: orbitals; 2: the orbitals of both spin
+// components, spin-dependent spinor orbitals; 3: gradients or position
+// moments); WIDE the lane layout; CLS the function-count class of the
+// launched chunks (0: per-site chunks).
 // The tables and the output are separate restrict-qualified arguments, so
 // the compiler can keep the uniform table reads on scalar loads (a store
 // through a pointer that may alias them would force per-lane loads).
-template <typename T, int NV, bool GRAD, bool WIDE, int CLS, bool GAUGE>
+template <typename T, int NV, int MULT, bool WIDE, int CLS, bool GAUGE>
 __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t* __restrict__ gidx,
                                                  const double* __restrict__ tab, const double* __restrict__ pg,
                                                  double* __restrict__ part) {
@@ -203,12 +205,12 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
     if (slot.chunk >= a.nchunks) return;
     const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
     const int tile = slot.tile;
-    if constexpr (GRAD) {
+    if constexpr (MULT > 1) {
         switch (C.L) {
-        case 1: project_body<T, NV, 3, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
-        case 3: project_body<T, NV, 9, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
-        case 5: project_body<T, NV, 15, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
-        case 7: project_body<T, NV, 21, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 1: project_body<T, NV, MULT * 1, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 3: project_body<T, NV, MULT * 3, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 5: project_body<T, NV, MULT * 5, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        case 7: project_body<T, NV, MULT * 7, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
         default: break;
         }
     } else if constexpr (CLS == 0) {
@@ -245,25 +247,25 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
 }
 
 // Largest function count of a class (class 0: per-site chunks, L <= 7; the
-// gradient table holds 3L functions).
-constexpr int proj_nf_max(bool grad, int cls) {
-    return grad ? 21 : (cls == 0 ? 7 : (cls > HUB_NCLASS ? HUB_GF_MAX : 4 * cls));
+// per-site tables hold MULT functions per orbital).
+constexpr int proj_nf_max(int mult, int cls) {
+    return mult > 1 ? 7 * mult : (cls == 0 ? 7 : (cls > HUB_NCLASS ? HUB_GF_MAX : 4 * cls));
 }
 
-template <typename T, int NV, bool GRAD, int CLS, bool GAUGE>
+template <typename T, int NV, int MULT, int CLS, bool GAUGE>
 void launch_k(const ProjArgs& b, dim3 grid, int waves, hipStream_t st) {
     if (b.wide)
-        hipLaunchKernelGGL((k_project<T, NV, GRAD, true, CLS, GAUGE>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
+        hipLaunchKernelGGL((k_project<T, NV, MULT, true, CLS, GAUGE>), grid, dim3(HUB_WAVE * waves), 0, st, b, b.gidx,
                            b.tab, b.pg, b.part);
     else
-        hipLaunchKernelGGL((k_project<T, NV, GRAD, false, CLS, GAUGE>), grid, dim3(HUB_WAVE * waves), 0, st, b,
+        hipLaunchKernelGGL((k_project<T, NV, MULT, false, CLS, GAUGE>), grid, dim3(HUB_WAVE * waves), 0, st, b,
                            b.gidx, b.tab, b.pg, b.part);
 }
 
-template <typename T, int NV, bool GRAD, int CLS>
+template <typename T, int NV, int MULT, int CLS>
 hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, hipStream_t st) {
     // a lane's FP64 accumulators (functions x scalars) stay within 96 values
-    if constexpr (proj_nf_max(GRAD, CLS) * NV > (GRAD ? 84 : 96)) {
+    if constexpr (proj_nf_max(MULT, CLS) * NV > (MULT == 3 ? 84 : 96)) {
         return hipErrorInvalidValue;
     } else {
         const int64_t cg = (a.ncol + cpl - 1) / cpl;
@@ -274,25 +276,26 @@ hipError_t launch_t(const ProjArgs& a, int nchunks, int nq, int cpl, int waves, 
         const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
         if (a.pg) {
             // velocity gauge: complex states, per-site or merged chunk lists
-            if constexpr (NV % 2 == 0 && (CLS == 0 || CLS > HUB_NCLASS))
-                launch_k<T, NV, GRAD, CLS, true>(b, grid, waves, st);
+            // (not with spin-dependent orbitals)
+            if constexpr (NV % 2 == 0 && MULT != 2 && (CLS == 0 || CLS > HUB_NCLASS))
+                launch_k<T, NV, MULT, CLS, true>(b, grid, waves, st);
             else
                 return hipErrorInvalidValue;
         } else {
-            launch_k<T, NV, GRAD, CLS, false>(b, grid, waves, st);
+            launch_k<T, NV, MULT, CLS, false>(b, grid, waves, st);
         }
         return hipGetLastError();
     }
 }
 
-template <typename T, bool GRAD, int CLS>
+template <typename T, int MULT, int CLS>
 hipError_t launch_g(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, hipStream_t st) {
     const int nv = cpl * (cplx ? 2 : 1);
     switch (nv) {
-    case 1: return launch_t<T, 1, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
-    case 2: return launch_t<T, 2, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
-    case 4: return launch_t<T, 4, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
-    case 8: return launch_t<T, 8, GRAD, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 1: return launch_t<T, 1, MULT, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 2: return launch_t<T, 2, MULT, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 4: return launch_t<T, 4, MULT, CLS>(a, nchunks, nq, cpl, waves, st);
+    case 8: return launch_t<T, 8, MULT, CLS>(a, nchunks, nq, cpl, waves, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -303,15 +306,18 @@ template <typename T>
 hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
                                hipStream_t st) {
     if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
-    if (a.tabmult == 3) return cls == 0 ? launch_g<T, true, 0>(a, nchunks, nq, cplx, cpl, waves, st)
+    if (a.tabmult == 3) return cls == 0 ? launch_g<T, 3, 0>(a, nchunks, nq, cplx, cpl, waves, st)
                                         : hipErrorInvalidValue;
+    // spin-dependent orbitals: complex spinor states, per-site chunks
+    if (a.tabmult == 2) return (cls == 0 && cplx) ? launch_g<T, 2, 0>(a, nchunks, nq, cplx, cpl, waves, st)
+                                                  : hipErrorInvalidValue;
     switch (cls) {
-    case 0: return launch_g<T, false, 0>(a, nchunks, nq, cplx, cpl, waves, st);
-    case 1: return launch_g<T, false, 1>(a, nchunks, nq, cplx, cpl, waves, st);
-    case 2: return launch_g<T, false, 2>(a, nchunks, nq, cplx, cpl, waves, st);
-    case 3: return launch_g<T, false, 3>(a, nchunks, nq, cplx, cpl, waves, st);
-    case 4: return launch_g<T, false, 4>(a, nchunks, nq, cplx, cpl, waves, st);
-    case HUB_NCLASS + 1: return launch_g<T, false, HUB_NCLASS + 1>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 0: return launch_g<T, 1, 0>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 1: return launch_g<T, 1, 1>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 2: return launch_g<T, 1, 2>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 3: return launch_g<T, 1, 3>(a, nchunks, nq, cplx, cpl, waves, st);
+    case 4: return launch_g<T, 1, 4>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_NCLASS + 1: return launch_g<T, 1, HUB_NCLASS + 1>(a, nchunks, nq, cplx, cpl, waves, st);
     default: return hipErrorInvalidValue;
     }
 }

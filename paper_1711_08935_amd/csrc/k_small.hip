@@ -27,9 +27,12 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
     const int k = a.spinor ? q : q / a.nspin;
     const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     double s0 = 0.0, s1 = 0.0;
+    // spin-dependent orbitals: column 2s + sigma of orbital m is the partial
+    // row sigma L + m of the chunk (the orbital of its spin component)
+    const int srow = a.spindep ? (col & 1) * a.site_L[site] + local : local;
     for (int t = a.site_chunk_ptr[site]; t < a.site_chunk_ptr[site + 1]; ++t) {
         const HubChunk& C = a.chunks[a.site_chunk_ids[t]];
-        const int64_t row = static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.mult + local;
+        const int64_t row = static_cast<int64_t>(q) * a.prows + static_cast<int64_t>(C.part0) * a.pmult + srow;
         const double* p = a.part + (row * a.ncol + col) * NC;
         if (NC == 2) {
             const double pr = ph[2 * C.img], pi = ph[2 * C.img + 1];

@@ -57,6 +57,7 @@ struct ApplyArgs {
     int nchunks;              // chunks in chunk_list (set by the launcher)
     int tiles;                // column tiles per chunk (set by the launcher)
     const double* pg;         // velocity gauge: [G] exp(i A.r_g) (re, im), or null
+    int spindep;              // per-site chunks with 2L functions [sigma][m] (spinor orbitals)
     // grouped chunks: per chunk HUB_GF_MAX (orbital j, image) pairs
     const int32_t* f_orb;
     const int32_t* f_img;

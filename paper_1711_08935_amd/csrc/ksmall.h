@@ -8,9 +8,11 @@ struct ReduceArgs {
     const double* part; int64_t prows;    // workspace rows per state set
     double* out; int nrows;               // output rows per state set (J * mult)
     int ncol; int ncplx; int mult;
+    int pmult;                            // workspace rows per chunk orbital (mult, or 2: spin-dependent)
+    int spindep;                          // 1: column 2s + sigma reads the rows of orbital sigma L + m
     const HubChunk* chunks;
     const int32_t* site_chunk_ptr; const int32_t* site_chunk_ids;
-    const int32_t* orb_site; const int32_t* site_orb0;
+    const int32_t* orb_site; const int32_t* site_orb0; const int32_t* site_L;
     const double* phase; int nimg;        // exp(+i k.T) per k-point and image
     int nspin; int spinor;                // state set -> k-point
     double dV;

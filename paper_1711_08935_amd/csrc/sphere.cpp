@@ -130,6 +130,8 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
     }
     T.J = J;
     T.nspecies = nspec;
+    for (const SiteDef& sd : sites)
+        if (std::isfinite(sd.zeta_dn)) T.spindep = true;
 
     std::map<std::tuple<int, int, int>, int> image_id;
     std::vector<std::vector<Pt>> pts(ns);
@@ -208,6 +210,28 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
             for (size_t p = 0; p < np; ++p) {
                 sp.phi[p * L + m] *= nm;
                 for (int i = 0; i < 3; ++i) sp.grad[(p * L + m) * 3 + i] *= nm;
+            }
+        }
+        // spin-down orbitals: the same points and harmonics with the site's
+        // spin-down exponent, normalized on the grid on their own
+        if (T.spindep) {
+            const double zd = std::isfinite(S.zeta_dn) ? S.zeta_dn : S.zeta;
+            sp.phi_dn.resize(np * L);
+            std::vector<double> nd(L, 0.0);
+            for (size_t p = 0; p < np; ++p) {
+                const Pt& q = P[p];
+                const double r = std::sqrt((q.d[0] * q.d[0] + q.d[1] * q.d[1]) + q.d[2] * q.d[2]);
+                const double rad = std::exp(-zd * r);
+                solid_harmonics(S.l, q.d[0], q.d[1], q.d[2], Sv, dSv);
+                for (int m = 0; m < L; ++m) {
+                    const double chi = rad * Sv[m];
+                    sp.phi_dn[p * L + m] = chi;
+                    nd[m] += chi * chi;
+                }
+            }
+            for (int m = 0; m < L; ++m) {
+                const double nm = 1.0 / std::sqrt(dV * nd[m]);
+                for (size_t p = 0; p < np; ++p) sp.phi_dn[p * L + m] *= nm;
             }
         }
         for (size_t p = 0; p < np; ++p) {
@@ -305,6 +329,10 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     const Pt& q = pts[s][p];
                     T.img.push_back(image_id[std::make_tuple(q.img[0], q.img[1], q.img[2])]);
                     for (int m = 0; m < L; ++m) T.phi.push_back(sp.phi[p * L + m]);
+                    if (T.spindep) {
+                        for (int m = 0; m < L; ++m) T.phi2.push_back(sp.phi[p * L + m]);
+                        for (int m = 0; m < L; ++m) T.phi2.push_back(sp.phi_dn[p * L + m]);
+                    }
                     for (int m = 0; m < L; ++m)
                         for (int i = 0; i < 3; ++i) T.gphi.push_back(sp.grad[(p * L + m) * 3 + i]);
                     // position moments about the site centre (velocity-gauge current)
@@ -319,6 +347,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     T.gidx.push_back(T.gidx.back());
                     T.img.push_back(T.img.back());
                     T.phi.insert(T.phi.end(), L, 0.0);
+                    if (T.spindep) T.phi2.insert(T.phi2.end(), 2 * L, 0.0);
                     T.gphi.insert(T.gphi.end(), 3 * L, 0.0);
                     T.mphi.insert(T.mphi.end(), 3 * L, 0.0);
                 }
@@ -337,8 +366,9 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
     T.nentries = nreal;
     if (e > INT32_MAX) return HUB_EINVAL;
 
-    // ---- grouped work list (cover signatures)
-    {
+    // ---- grouped work list (cover signatures); not with spin-dependent
+    // orbitals (their per-site tables hold the two spin components)
+    if (!T.spindep) {
         GroupTables& GT = T.grouped;
         struct Cover {
             int32_t g, site, img;

@@ -33,6 +33,7 @@ int main(int argc, char** argv) {
         ok = ok && get(f, s.R, 3) && get(f, &s.l, 1) && get(f, &s.zeta, 1) && get(f, &s.rc, 1) &&
              get(f, &s.species, 1);
         s.ueff_fixed = NAN;
+        s.zeta_dn = NAN;
     }
     ok = ok && get(f, k, 3) && get(f, &S, 1) && S > 0;
     const long G = static_cast<long>(ngrid[0]) * ngrid[1] * ngrid[2];

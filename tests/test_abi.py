@@ -128,3 +128,29 @@ def test_sphere_radius_rejects_bad_arguments():
     neg = (ctypes.c_double * 3)(1.0, -2.0, 3.0)
     assert lib.hub_sphere_radius(H.HUB_RADIUS_CELL, 0, 1.0, neg, 0.0, ctypes.byref(rc)) == H.HUB_EINVAL
     assert lib.hub_sphere_radius(H.HUB_RADIUS_THRESHOLD, 1, 1.0, None, 1e-3, None) == H.HUB_EINVAL
+
+
+def test_spin_orbital_arguments_and_host_tables():
+    lib = H.lib()
+    cell = (ctypes.c_double * 3)(10, 10, 10)
+    ng = (ctypes.c_int * 3)(12, 12, 12)
+    R = (ctypes.c_double * 3)(5, 5, 5)
+    col = ctypes.c_void_p()
+    assert lib.hub_create(ctypes.byref(col), cell, ng, 2, 1, 0) == H.HUB_OK            # collinear complex
+    assert lib.hub_add_site(col, R, 2, 2.0, 3.0, 0, None) == H.HUB_OK
+    assert lib.hub_set_site_spin_orbital(col, 0, 2.5) == H.HUB_EINVAL                 # not a spinor context
+    assert lib.hub_destroy(col) == H.HUB_OK
+    ctx = ctypes.c_void_p()
+    assert lib.hub_create(ctypes.byref(ctx), cell, ng, 4, 1, 0) == H.HUB_OK            # spinor
+    assert lib.hub_add_site(ctx, R, 2, 2.0, 3.0, 0, None) == H.HUB_OK
+    assert lib.hub_add_site(ctx, (ctypes.c_double * 3)(0.5, 0.5, 0.5), 1, 1.5, 2.5, 1, None) == H.HUB_OK
+    assert lib.hub_set_site_spin_orbital(ctx, 2, 2.5) == H.HUB_EINVAL                 # no such site
+    assert lib.hub_set_site_spin_orbital(ctx, 0, -1.0) == H.HUB_EINVAL
+    assert lib.hub_set_site_spin_orbital(ctx, 0, float("nan")) == H.HUB_EINVAL
+    assert lib.hub_set_site_spin_orbital(ctx, 0, 2.5) == H.HUB_OK
+    assert lib.hub_set_vector_potential(ctx, (ctypes.c_double * 3)(0.1, 0, 0)) == H.HUB_EINVAL
+    assert lib.hub_finalize_host(ctx) == H.HUB_OK
+    assert lib.hub_set_site_spin_orbital(ctx, 1, 2.5) == H.HUB_ESTATE                 # after build
+    v = ctypes.c_int64()
+    assert lib.hub_query(ctx, 11, ctypes.byref(v)) == H.HUB_OK and v.value == 0       # per-site list only
+    assert lib.hub_destroy(ctx) == H.HUB_OK

@@ -1,0 +1,132 @@
+"""GPU parity of spin-dependent (spinor) orbitals (App. A) against the FP64
+oracle.
+
+The noncollinear layered workload with a spin-down Slater exponent on every
+site (d: 2.0 -> 2.6, p: 1.4 -> 1.1) and a fixed U_eff per site, both storage
+precisions: projections c^sigma = <phi^sigma|psi^sigma>, occupations, E_U,
+V_U psi, the batched and graph steps.  The oracle projects and applies per
+spin component on the whole cell (its full-grid definitions).  Bars as in
+test_gpu_parity.py.  With zeta_dn = zeta the spin-dependent kernels give
+results bitwise equal to the spin-independent per-site path.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1711_08935_amd as H  # noqa: E402
+from oracle import occupations as OCC  # noqa: E402
+from oracle import potential as POT  # noqa: E402
+from oracle import spinorb as SO  # noqa: E402
+from synth import make_config  # noqa: E402
+from tests.gpu_common import c_to_oracle, device_states, n_site, states_and_occupations  # noqa: E402
+from tests.helpers import normwise, to_system  # noqa: E402
+
+UEFF = 0.15
+
+
+def _config(zeta_dn):
+    cfg = make_config("spinor_layers", small=True)
+    cfg.sites = [dict(s, zeta_dn=zeta_dn(s)) for s in cfg.sites]
+    return cfg
+
+
+def _hub(cfg, prec, worklist_grouped=True):
+    hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                    is_complex=cfg.is_complex, precision=prec, chunk=256)
+    hub.set_worklist(worklist_grouped)
+    for i in range(hub.nsites):
+        hub.set_fixed_ueff(i, UEFF)
+    return hub
+
+
+@pytest.fixture(scope="module", params=["f64", "f32"])
+def case(request):
+    prec = request.param
+    print(f"\n[spinorb case] spinor_layers {prec}", flush=True)
+    cfg = _config(lambda s: 2.6 if s["l"] == 2 else 1.1)
+    psi, f = states_and_occupations(cfg)
+    hub = _hub(cfg, prec)
+    psi_d, used = device_states(hub, psi)
+    sys_ = to_system(cfg)
+    cref = SO.project_spin(sys_, used)
+    n, _, _ = OCC.occupations(sys_, cref, f, with_pbar=False)
+    V = [POT.potential_matrix(sys_, UEFF, nn) for nn in n]
+    ref = dict(c=cref, n=n, V=V, EU=np.array([POT.energy(sys_, UEFF, nn) for nn in n]),
+               hpsi=SO.apply_spin(sys_, cref, V))
+    return dict(prec=prec, cfg=cfg, hub=hub, psi_d=psi_d, f=f, f_d=torch.from_numpy(f).cuda(), sys=sys_, ref=ref)
+
+
+def test_projection_occupations_energy_apply(case):
+    hub, ref = case["hub"], case["ref"]
+    assert hub.query(11) == 0                      # per-site work list
+    c = hub.project(case["psi_d"])
+    n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
+    ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
+    EU = hub.energy(ueff, n)
+    h = torch.zeros_like(case["psi_d"])
+    hub.apply(ueff, n, c, h)
+    torch.cuda.synchronize()
+    assert normwise(c_to_oracle(hub, c), ref["c"]) < 1e-12
+    for I in range(hub.nsites):
+        assert normwise(n_site(hub, n, I, hub.site_L[I]), ref["n"][I]) < 1e-12, I
+    assert normwise(EU.cpu().numpy(), ref["EU"]) < 1e-12
+    bar = 1e-12 if case["prec"] == "f64" else 2e-7
+    assert normwise(h.cpu().numpy(), ref["hpsi"]) < bar
+
+
+def test_steps(case):
+    hub, ref = case["hub"], case["ref"]
+    S = case["cfg"].nstates
+    outs = {}
+    for mode in ("batched", "graph", "persite"):
+        bufs = hub.step_buffers(S)
+        h = torch.zeros_like(case["psi_d"])
+        hub.step(case["psi_d"], case["f_d"], h, mode=mode, bufs=bufs)
+        torch.cuda.synchronize()
+        outs[mode] = (h, bufs)
+    h, bufs = outs["batched"]
+    assert torch.equal(outs["graph"][0], h)
+    assert torch.equal(outs["persite"][0], h)
+    assert normwise(c_to_oracle(hub, bufs["c"]), ref["c"]) < 1e-12
+    assert torch.all(bufs["Ueff"] == UEFF)
+    bar = 1e-12 if case["prec"] == "f64" else 2e-7
+    assert normwise(h.cpu().numpy(), ref["hpsi"]) < bar
+
+
+def test_no_forces_current_or_gauge(case):
+    hub = case["hub"]
+    c = hub.project(case["psi_d"])
+    n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
+    ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HubError):
+        hub.forces(case["psi_d"], c, case["f_d"], ueff, n)
+    with pytest.raises(H.HubError):
+        hub.set_vector_potential([0.1, 0.0, 0.0])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_equal_exponents_match_spin_independent_path(prec):
+    cfg_same = _config(lambda s: s["zeta"])
+    cfg_plain = make_config("spinor_layers", small=True)
+    psi, f = states_and_occupations(cfg_plain)
+    a = _hub(cfg_same, prec)
+    b = _hub(cfg_plain, prec, worklist_grouped=False)
+    psi_d, _ = device_states(a, psi)
+    f_d = torch.from_numpy(f).cuda()
+    ca, cb = a.project(psi_d), b.project(psi_d)
+    na, _, _ = a.occupations(ca, f_d, with_pbar=False)
+    nb, _, _ = b.occupations(cb, f_d, with_pbar=False)
+    ueff = torch.full((a.nsites,), UEFF, dtype=torch.float64, device="cuda")
+    ha, hb = torch.zeros_like(psi_d), torch.zeros_like(psi_d)
+    a.apply(ueff, na, ca, ha)
+    b.apply(ueff, nb, cb, hb)
+    torch.cuda.synchronize()
+    assert torch.equal(ca, cb)
+    assert torch.equal(na, nb)
+    assert torch.equal(ha, hb)
