@@ -139,9 +139,9 @@ def rc_sweep(args):
     grid points against the d-orbital radius): the d shells of the workload
     take each radius in turn, the other shells keep theirs; U_eff is fixed
     (as in the paper's sweep), so no Coulomb tensors are built.  Per radius:
-    points per d sphere, union of covered points, whether the grouped work
-    list holds (at most 16 functions per point), graph steps/s and the
-    algorithmic bytes of project + apply per second."""
+    points per d sphere, union of covered points, passes of the grouped
+    apply (points with more than 16 functions are split over passes), graph
+    steps/s and the algorithmic bytes of project + apply per second."""
     import numpy as np
     import torch
 
@@ -179,7 +179,7 @@ def rc_sweep(args):
         pts = union_points(hub)
         alg = 3 * pts * ncol * esz * hub.nsets
         row = {"rc": round(rc, 4), "method": how, "points_per_d_sphere": int(hub.site_npts[dsites[0]]),
-               "union_points": pts, "grouped_worklist": hub.query(11) > 0, "functions_per_point_max": hub.query(12),
+               "union_points": pts, "grouped_passes": hub.query(14), "functions_per_point_max": hub.query(12),
                "steps_per_s": round(args.steps / ev, 2), "step_GBs": round(alg / (ev / args.steps) / 1e9, 1)}
         log(str(row))
         out.append(row)

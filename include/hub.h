@@ -156,9 +156,11 @@ int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves, int la
  * grid point covered by any sphere with all its (site, lattice image) covers,
  * so each state row is read once by the projection and written once by the
  * apply; 0 uses one chunk per site and image, with overlapping sites applied
- * in successive atomic-free layers.  The grouped list exists only when no grid
- * point is covered by more than 16 orbitals in total; otherwise the per-site
- * list is used.  Both give the same results up to summation order.  Any
+ * in successive atomic-free layers.  A grid point covered by more than 16
+ * orbitals in total has its covers split over several passes of the
+ * grouped list (at most 16 orbitals each; the apply launches the passes in
+ * turn, hub_query 14).  Without spin-dependent orbitals the grouped list
+ * always exists.  Both give the same results up to summation order.  Any
  * time. */
 int hub_set_worklist(hub_ctx* ctx, int grouped_list);
 
@@ -173,7 +175,8 @@ int hub_set_worklist(hub_ctx* ctx, int grouped_list);
  *   HUB_CLASSES_CONCURRENT  one launch per class on side streams forked from
  *                           and joined back to the context's stream
  *                           (parallel branches of a captured graph).
- * Results are identical.  Any time; a captured step graph is rebuilt on the
+ * Results are identical.  With more than one pass the launches are merged
+ * whatever the policy.  Any time; a captured step graph is rebuilt on the
  * next graph-mode hub_step. */
 #define HUB_CLASSES_MERGED 0
 #define HUB_CLASSES_SEQUENTIAL 1
@@ -200,7 +203,9 @@ int hub_set_stream(hub_ctx* ctx, void* stream);
  * 10 projection workspace rows (sum of L over chunks), 11 grouped chunks
  * (0 when the grouped work list was not built), 12 largest number of
  * orbitals covering one grid point, 13 dilated-sphere entries of the
- * state-gradient forces (0 before the first hub_forces_state_gradient). */
+ * state-gradient forces (0 before the first hub_forces_state_gradient),
+ * 14 passes of the grouped apply (points covered by more than 16 orbitals
+ * have their covers split over passes; 0 without a grouped work list). */
 int hub_query(const hub_ctx* ctx, int what, int64_t* value);
 
 /* Per-site data after hub_finalize_host: L = 2l+1, offset of its first

@@ -65,7 +65,8 @@ struct hub_ctx {
     // grouped (cover-signature) work list
     bool use_grouped = true;
     int class_policy = HUB_CLASSES_MERGED;
-    int32_t* d_gall_m = nullptr;             // chunk list of the merged launch
+    int32_t* d_gall_m = nullptr;             // chunk list of the merged launch, by pass
+    std::vector<int> gpass_ptr;              // d_gall_m[gpass_ptr[p], gpass_ptr[p+1]): chunks of pass p
     int gcls_ptr[HUB_NCLASS + 1] = {};       // d_gall[gcls_ptr[k-1], gcls_ptr[k]): chunks of class k
     HubChunk* d_gchunks = nullptr;
     int32_t *d_gall = nullptr, *d_ggidx = nullptr, *d_gf_orb = nullptr, *d_gf_img = nullptr;
@@ -274,8 +275,24 @@ int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
 // forked from the context's stream and joined back to it: the classes write
 // disjoint outputs, so their kernels run concurrently (parallel branches of
 // a captured graph).
+//
+// With more than one pass (points with more than HUB_GF_MAX functions), the
+// launches are merged: the apply (per_pass) launches the passes one after
+// the other, since a point appears once per pass; the projection launches
+// every pass at once.
 template <typename F>
-int run_classes(hub_ctx* c, F&& launch) {
+int run_classes(hub_ctx* c, F&& launch, bool per_pass = false) {
+    const int np = c->T.grouped.npass;
+    if (np > 1) {
+        if (!per_pass) {
+            HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m, c->gpass_ptr[np], c->stream));
+            return HUB_OK;
+        }
+        for (int p = 0; p < np; ++p)
+            HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m + c->gpass_ptr[p], c->gpass_ptr[p + 1] - c->gpass_ptr[p],
+                           c->stream));
+        return HUB_OK;
+    }
     // the velocity-gauge kernels are built for the merged launch only
     if (c->class_policy == HUB_CLASSES_MERGED || c->gauge) {
         HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m, c->gcls_ptr[HUB_NCLASS], c->stream));
@@ -594,7 +611,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
             b.chunk_list = list;
             const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), std::min(4 * k, HUB_GF_MAX));
             return launch_apply_grouped(b, nch, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
-        });
+        }, true);
     }
     int cpl = pick_cpl(c, hpsi, ld, 1);
     if (c->T.spindep) {
@@ -856,14 +873,18 @@ int hub_finalize(hub_ctx* c, void* stream) {
         }
         up(&c->d_gchunks, T.grouped.chunks);
         up(&c->d_gall, gall);
-        // merged launch: chunks with more functions (fewer entries per batch,
-        // longer entry loops) and more entries first
+        // merged launch, pass by pass: chunks with more functions (fewer
+        // entries per batch, longer entry loops) and more entries first
         std::vector<int32_t> gm(gall);
         std::stable_sort(gm.begin(), gm.end(), [&T](int32_t x, int32_t y) {
             const HubChunk &X = T.grouped.chunks[x], &Y = T.grouped.chunks[y];
+            if (X.layer != Y.layer) return X.layer < Y.layer;
             const int kx = hub_nf_class(X.L) > 2, ky = hub_nf_class(Y.L) > 2;
             return kx != ky ? kx > ky : X.ne > Y.ne;
         });
+        c->gpass_ptr.assign(T.grouped.npass + 1, 0);
+        for (int32_t i : gm) ++c->gpass_ptr[T.grouped.chunks[i].layer + 1];
+        for (int p = 0; p < T.grouped.npass; ++p) c->gpass_ptr[p + 1] += c->gpass_ptr[p];
         up(&c->d_gall_m, gm);
         up(&c->d_ggidx, T.grouped.gidx);
         up(&c->d_gtab, T.grouped.tab);
@@ -918,6 +939,7 @@ int hub_query(const hub_ctx* c, int what, int64_t* v) {
     case 11: *v = T.grouped.ok ? static_cast<int64_t>(T.grouped.chunks.size()) : 0; break;
     case 12: *v = T.grouped.nfmax; break;
     case 13: *v = c->stencil_entries; break;
+    case 14: *v = T.grouped.ok ? T.grouped.npass : 0; break;
     default: return HUB_EINVAL;
     }
     return HUB_OK;

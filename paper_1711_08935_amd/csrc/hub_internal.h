@@ -57,13 +57,16 @@ struct SiteSphere {
 #define HUB_GF_MAX 16
 
 // Work list grouped by cover signature: every grid point covered by any
-// sphere appears in exactly one grouped chunk, together with all its
+// sphere appears in one grouped chunk per pass, together with its
 // (site, image) covers in a fixed slot order, so the projection reads each
-// state row once and the apply writes it once (no layers).  The chunk's
-// functions are the concatenated orbitals of its slots.
+// state row once per pass and the apply writes it once per pass.  The
+// chunk's functions are the concatenated orbitals of its slots; a point with
+// more than HUB_GF_MAX functions has its slots split over several passes.
 struct GroupTables {
     bool ok = false;
-    int nfmax = 0;
+    int nfmax = 0;                           // most functions covering one grid point
+    int npass = 1;                           // apply passes (chunk.layer): points with more
+                                             // than HUB_GF_MAX functions are split over passes
     std::vector<HubChunk> chunks;            // L = number of functions, e0/ne over points
     std::vector<int32_t> gidx;               // per point
     std::vector<double> tab;                 // per point, L values (slot-major)

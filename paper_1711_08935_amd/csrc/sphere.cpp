@@ -385,37 +385,61 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
         std::sort(cov.begin(), cov.end(), [](const Cover& a, const Cover& b) {
             return std::tie(a.g, a.site, a.img) < std::tie(b.g, b.site, b.img);
         });
-        // signature -> points (each point: index of its first cover in cov)
-        std::map<std::vector<std::pair<int, int>>, std::vector<size_t>> groups;
-        std::vector<std::vector<std::pair<int, int>>> order;
+        // (pass, signature) -> points (each point: index in cov of the first
+        // cover of that pass).  A point with more than HUB_GF_MAX functions
+        // has its covers split into consecutive slot ranges of at most
+        // HUB_GF_MAX functions, one per pass; the apply launches the passes
+        // one after the other, so a point is updated by one chunk at a time.
+        // Points are grouped by the covers of each pass (not by their whole
+        // cover list), which keeps the chunks long when large spheres give
+        // nearly every point a cover list of its own.
+        using Sig = std::vector<std::pair<int, int>>;
+        std::map<std::pair<int, Sig>, std::vector<size_t>> groups;
+        std::vector<std::pair<int, Sig>> order;
         bool ok = true;
-        int nfmax = 0;
+        int nfmax = 0, npass = 1;
         for (size_t i = 0; i < cov.size();) {
             size_t k = i;
-            std::vector<std::pair<int, int>> sig;
-            int nf = 0;
+            int nf = 0, acc = 0, pass = 0;
+            size_t first = i;
+            Sig sig;
+            auto close = [&]() {
+                auto key = std::make_pair(pass, sig);
+                auto it = groups.find(key);
+                if (it == groups.end()) {
+                    order.push_back(key);
+                    groups[key].push_back(first);
+                } else {
+                    it->second.push_back(first);
+                }
+            };
             while (k < cov.size() && cov[k].g == cov[i].g) {
+                const int Ls = T.site_L[cov[k].site];
+                if (acc + Ls > HUB_GF_MAX) {
+                    close();
+                    ++pass;
+                    sig.clear();
+                    acc = 0;
+                    first = k;
+                }
                 sig.push_back({cov[k].site, cov[k].img});
-                nf += T.site_L[cov[k].site];
+                acc += Ls;
+                nf += Ls;
                 ++k;
             }
+            close();
             nfmax = std::max(nfmax, nf);
-            if (nf > HUB_GF_MAX) ok = false;
-            auto it = groups.find(sig);
-            if (it == groups.end()) {
-                order.push_back(sig);
-                groups[sig].push_back(i);
-            } else {
-                it->second.push_back(i);
-            }
+            npass = std::max(npass, pass + 1);
             i = k;
         }
         GT.nfmax = nfmax;
         GT.ok = ok;
         if (ok) {
             int64_t rows = 0, tab0 = 0;
-            for (const auto& sig : order) {
-                const std::vector<size_t>& firsts = groups[sig];
+            for (const auto& key : order) {
+                const std::vector<size_t>& firsts = groups[key];
+                const int pass = key.first;
+                const Sig& sig = key.second;
                 int nf = 0;
                 for (const auto& sl : sig) nf += T.site_L[sl.first];
                 // more than 8 functions: the kernels take half as many entries
@@ -427,7 +451,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     const size_t np = (nb + HUB_ENTRY_ALIGN - 1) / HUB_ENTRY_ALIGN * HUB_ENTRY_ALIGN;
                     HubChunk C;
                     C.site = sig[0].first;
-                    C.layer = 0;
+                    C.layer = pass;
                     C.e0 = static_cast<int32_t>(GT.gidx.size());
                     C.ne = static_cast<int32_t>(np);
                     C.nreal = static_cast<int32_t>(nb);
@@ -466,6 +490,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     GT.chunks.push_back(C);
                 }
             }
+            GT.npass = npass;
             GT.part_rows = rows;
             if (rows > INT32_MAX) GT.ok = false;
             // CSR orbital j -> (workspace row, image)

@@ -1,0 +1,93 @@
+"""GPU parity of the multi-pass grouped work list: spheres large enough that
+grid points are covered by more than 16 orbitals (through several sites and
+their periodic images), so the grouped apply runs in passes.
+
+NiO-like collinear k-point states with the Ni d radius at 6 bohr (3 passes)
+and the real Gamma-point d shell with r_c = 9 bohr in a 10 bohr cell (its own
+images overlap), both storage precisions, U_eff fixed: projections and
+V_U psi against the oracle (full-cell definitions), the per-site work list
+and the graph step.  Bars as in test_gpu_parity.py.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1711_08935_amd as H  # noqa: E402
+from oracle import occupations as OCC  # noqa: E402
+from oracle import potential as POT  # noqa: E402
+from oracle import projection as OP  # noqa: E402
+from synth import make_config  # noqa: E402
+from tests.gpu_common import c_to_oracle, device_states, states_and_occupations  # noqa: E402
+from tests.helpers import normwise, to_system  # noqa: E402
+
+UEFF = 0.15
+CASES = [("nio_afm", 6.0, "f64"), ("nio_afm", 6.0, "f32"), ("gamma_d", 9.0, "f64"), ("gamma_d", 9.0, "f32")]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[f"{a}-rc{b}-{c}" for a, b, c in CASES])
+def case(request):
+    name, rc, prec = request.param
+    print(f"\n[passes case] {name} rc={rc} {prec}", flush=True)
+    cfg = make_config(name, small=True)
+    cfg.sites = [dict(s, rc=rc) if s["l"] == 2 else s for s in cfg.sites]
+    psi, f = states_and_occupations(cfg)
+    hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                    is_complex=cfg.is_complex, precision=prec, chunk=256)
+    for i in range(hub.nsites):
+        hub.set_fixed_ueff(i, UEFF)
+    psi_d, used = device_states(hub, psi)
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    cref = OP.project_fullgrid(sys_, used, sps)
+    n, _, _ = OCC.occupations(sys_, cref, f, with_pbar=False)
+    V = [POT.potential_matrix(sys_, UEFF, nn) for nn in n]
+    href = POT.apply_fullgrid(sys_, cref, V, sps)
+    return dict(prec=prec, cfg=cfg, hub=hub, psi_d=psi_d, f_d=torch.from_numpy(f).cuda(), cref=cref,
+                href=href if hub.is_complex else href.real)
+
+
+def _run(hub, psi_d, f_d):
+    c = hub.project(psi_d)
+    n, _, _ = hub.occupations(c, f_d, with_pbar=False)
+    ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
+    h = torch.zeros_like(psi_d)
+    hub.apply(ueff, n, c, h)
+    torch.cuda.synchronize()
+    return c, h
+
+
+def test_passes_against_oracle_and_per_site_list(case):
+    hub = case["hub"]
+    assert hub.query(12) > 16 and hub.query(14) >= 2
+    c, h = _run(hub, case["psi_d"], case["f_d"])
+    assert normwise(c_to_oracle(hub, c), case["cref"]) < 1e-12
+    bar = 1e-12 if case["prec"] == "f64" else 2e-7
+    assert normwise(h.cpu().numpy(), case["href"]) < bar
+    hub.set_worklist(False)
+    try:
+        c2, h2 = _run(hub, case["psi_d"], case["f_d"])
+    finally:
+        hub.set_worklist(True)
+    assert normwise(c2.cpu().numpy(), c.cpu().numpy()) < 1e-13
+    assert normwise(h2.cpu().numpy(), h.cpu().numpy()) < (1e-13 if case["prec"] == "f64" else 2e-7)
+
+
+def test_graph_step_matches_batched(case):
+    hub = case["hub"]
+    S = case["cfg"].nstates
+    outs = []
+    for mode in ("batched", "graph", "graph"):
+        bufs = hub.step_buffers(S)
+        h = torch.zeros_like(case["psi_d"])
+        hub.step(case["psi_d"], case["f_d"], h, mode=mode, bufs=bufs)
+        torch.cuda.synchronize()
+        outs.append((h, bufs["c"]))
+    for h, c in outs[1:]:
+        assert torch.equal(h, outs[0][0])
+        assert torch.equal(c, outs[0][1])
