@@ -18,6 +18,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from oracle import forces as OF  # noqa: E402
+from oracle import gauge as GA  # noqa: E402
 from oracle import occupations as OO  # noqa: E402
 from oracle import potential as OPOT  # noqa: E402
 from oracle import projection as OP  # noqa: E402
@@ -72,6 +73,76 @@ def test_nio_full_size_every_output(prec):
     _compare_matrices(hub, bufs, ref)
     bar = 1e-12 if prec == "f64" else 2e-7
     assert normwise(hpsi.cpu().numpy(), ref["hpsi"]) < bar
+
+
+@pytest.mark.timeout(900)
+def test_nio_full_size_velocity_gauge():
+    """The bench's real-time configuration with a field on: the graph step
+    under A, then the current.  Every projection c^A, the matrices, U and J,
+    V^A psi on sampled states and the current against the oracle."""
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("nio_afm", "f32")
+    A = np.array([0.05, 0.02, -0.03])
+    hub.set_vector_potential(A)
+    try:
+        hpsi.zero_()
+        hub.step(psi, f_d, hpsi, mode="graph", bufs=bufs)
+        J = hub.current(psi, bufs["c"], f_d, bufs["Ueff"], bufs["n"]).cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        hub.set_vector_potential(None)
+    used = psi.cpu().numpy().astype(np.complex128)
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    cA = GA.project_gauge(sys_, used, sps, A)
+    assert normwise(c_to_oracle(hub, bufs["c"]), cA) < 1e-12
+    n, pbar, nb = OO.occupations(sys_, cA, f)
+    tens = OS.site_tensors(sys_, sps)
+    ref = dict(n=n, pbar=pbar, nbar=nb, U=np.zeros(len(sps)), J=np.zeros(len(sps)))
+    from oracle import acbn0
+    for I in range(len(sps)):
+        U, Jh, _, _ = acbn0.uj_collinear(OO.channels(sys_, n[I]), OO.channels(sys_, pbar[I]), tens[I])
+        ref["U"][I], ref["J"][I] = U, Jh
+    _compare_matrices(hub, bufs, ref)
+    V = [OPOT.potential_matrix(sys_, ref["U"][I] - ref["J"][I], n[I]) for I in range(len(sps))]
+    cols = np.sort(np.random.default_rng(1).choice(cfg.nstates, size=8, replace=False))
+    h_ref = GA.apply_gauge(sys_, cA[:, :, cols], V, sps, A)
+    h = hpsi[:, :, torch.from_numpy(cols).cuda()].cpu().numpy()
+    assert normwise(h, h_ref) < 2e-7
+    rho = GA.moment_projections(sys_, used, sps, A)
+    Jref = GA.current(sys_, cA, rho, V, f)
+    assert normwise(J, Jref) < 1e-11
+
+
+@pytest.mark.timeout(900)
+def test_nio_full_size_large_spheres_in_passes():
+    """Ni d spheres of 6 bohr on the full grid (3 passes of the grouped
+    apply), U_eff fixed, graph step: every projection and V_U psi on sampled
+    states against the oracle."""
+    cfg = make_config("nio_afm")
+    cfg.sites = [dict(s, rc=6.0) if s["l"] == 2 else s for s in cfg.sites]
+    print(f"\n[fullsize] nio_afm rc=6.0 f32", flush=True)
+    hub = make_hub(cfg, "f32")
+    assert hub.query(14) == 3
+    for i in range(hub.nsites):
+        hub.set_fixed_ueff(i, 0.15)
+    psi = make_states(cfg, device="cuda").to(hub.state_dtype)
+    f = make_occupations(cfg)
+    f_d = torch.from_numpy(f).cuda()
+    bufs = hub.step_buffers(cfg.nstates)
+    hpsi = torch.zeros_like(psi)
+    hub.step(psi, f_d, hpsi, mode="graph", bufs=bufs)
+    torch.cuda.synchronize()
+    used = psi.cpu().numpy().astype(np.complex128)
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    c = OP.project_sphere(sys_, used, sps)
+    assert normwise(c_to_oracle(hub, bufs["c"]), c) < 1e-12
+    n, _, _ = OO.occupations(sys_, c, f, with_pbar=False)
+    V = [OPOT.potential_matrix(sys_, 0.15, nn) for nn in n]
+    cols = np.sort(np.random.default_rng(2).choice(cfg.nstates, size=8, replace=False))
+    h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
+    h = hpsi[:, :, torch.from_numpy(cols).cuda()].cpu().numpy()
+    assert normwise(h, h_ref) < 2e-7
 
 
 @pytest.mark.timeout(900)
