@@ -1158,6 +1158,13 @@ int build_stencil(hub_ctx* c) {
     if (st) return st;
     std::vector<int32_t> all(S.chunks.size());
     std::iota(all.begin(), all.end(), 0);
+    // a failed earlier attempt may have left some of the tables allocated
+    for (void** p : {reinterpret_cast<void**>(&c->d_st_chunks), reinterpret_cast<void**>(&c->d_st_all),
+                     reinterpret_cast<void**>(&c->d_st_gidx), reinterpret_cast<void**>(&c->d_st_tab),
+                     reinterpret_cast<void**>(&c->d_st_site_ptr), reinterpret_cast<void**>(&c->d_st_site_ids)}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
     size_t bytes = 0;
     HUB_TRY(upload(&c->d_st_chunks, S.chunks, bytes));
     HUB_TRY(upload(&c->d_st_all, all, bytes));
