@@ -336,8 +336,44 @@ def main():
             torch.cuda.synchronize()
             key = "gauge_current_steps_per_s" if with_current else "gauge_steps_per_s"
             gauge[key] = round(args.steps / (ge0.elapsed_time(ge1) * 1e-3), 2)
+        # per-stage times under a field (batched steps, library HIP events)
+        hub32.set_vector_potential(A0)
+        hub32.profile(True)
+        for _ in range(max(5, min(args.steps, 30))):
+            hub32.step(psi32, f_d, hpsi32, mode="batched", bufs=bufs32)
+        gprof = hub32.profile_read()
+        hub32.profile(False)
         hub32.set_vector_potential(None)
         log(f"velocity gauge: {gauge}")
+
+    spindep = None
+    if cfg.spin == "spinor":
+        # spin-dependent spinor orbitals (App. A): spin-down exponents
+        # (d 2.0 -> 2.6, p 1.4 -> 1.1), fixed U_eff, per-site work list; beside
+        # it the spin-independent context on the same per-site list
+        sd_sites = [dict(s, zeta_dn=(s["zeta"] + 0.6 if s["l"] == 2 else s["zeta"] - 0.3)) for s in cfg.sites]
+        hsd = H.Hubbard(cfg.cell, cfg.ngrid, sd_sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                        is_complex=cfg.is_complex, precision="f32", chunk=args.chunk)
+        for i in range(hsd.nsites):
+            hsd.set_fixed_ueff(i, 0.15)
+        bsd = hsd.step_buffers(S)
+        hsd_out = torch.zeros_like(psi32)
+        hsd.step(psi32, f_d, hsd_out, mode="batched", bufs=bsd)
+        if not args.no_tune:
+            autotune(hsd, psi32, bsd["c"], bsd["n"], bsd["Ueff"])
+        _, sd_ev = time_steps(hsd, psi32, f_d, hsd_out, "graph", args.steps, args.warmup, bsd)
+        hsd.profile(True)
+        for _ in range(max(5, min(args.steps, 30))):
+            hsd.step(psi32, f_d, hsd_out, mode="batched", bufs=bsd)
+        sd_prof = hsd.profile_read()
+        hsd.profile(False)
+        hub32.set_worklist(False)
+        _, ps_ev = time_steps(hub32, psi32, f_d, hpsi32, "graph", args.steps, args.warmup, bufs32)
+        hub32.set_worklist(args.worklist == "grouped")
+        spindep = {"steps_per_s": round(args.steps / sd_ev, 2),
+                   "spin_independent_persite_steps_per_s": round(args.steps / ps_ev, 2)}
+        log(f"spin-dependent orbitals: {spindep}")
+        del hsd, bsd, hsd_out
 
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 4
@@ -387,6 +423,21 @@ def main():
     proj_bytes = U_pts * ncol * esz * hub32.nsets               # psi read at every sphere point once
     apply_bytes = 2 * proj_bytes                                # hpsi read + write
     detail["algorithmic_bytes_per_step"] = int(proj_bytes + apply_bytes)
+    for tag, pr in (("gauge", gprof if gauge is not None else None),
+                    ("spin_dependent", sd_prof if spindep is not None else None)):
+        if pr is None:
+            continue
+        rates = {}
+        for k, b in (("project", proj_bytes), ("apply", apply_bytes)):
+            ms = pr[k][0] / max(1, pr[k][1])
+            rates[f"{k}_ms"] = round(ms, 4)
+            rates[f"{k}_GBs"] = round(b / (ms * 1e-3) / 1e9, 1)
+        if tag == "gauge":
+            detail["gauge_stages"] = rates
+        else:
+            spindep.update(rates)
+    if spindep is not None:
+        detail["spin_dependent_orbitals"] = spindep
     detail["step_GBs"] = round((proj_bytes + apply_bytes) * value / 1e9, 1)
     grouped = args.worklist == "grouped"
     kernels = {
