@@ -227,6 +227,15 @@ int hub_site_points(const hub_ctx* ctx, int site, int32_t* g, int32_t* image3,
  * c: device, [nq][J][ncol].  nstates >= 1, ld >= ncol. */
 int hub_project(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, double* c);
 
+/* hub_project for the state sets set0 .. set0 + nsets - 1 only (a caller
+ * that holds one k-point, or one k-point and spin, at a time): psi holds
+ * those sets (set stride G * ld elements) and c receives [nsets][J][ncol];
+ * each set keeps its own k-point phase.  The occupations still need the
+ * projections of every set (hub_occupations).  Errors: HUB_EINVAL (set range
+ * outside 0 .. number of sets, as hub_project), HUB_ESTATE. */
+int hub_project_sets(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, int set0, int nsets,
+                     double* c);
+
 /* Occupations (Eq. occ_matrices), renormalized occupations N-bar
  * (Eq. notation_Nbar) and P-bar (Eq. notation_Pbar); spinors: App. A and B.
  * c: device [nq][J][ncol] from hub_project; f: device occupations.  Outputs
@@ -261,6 +270,12 @@ int hub_acbn0_uj(hub_ctx* ctx, const double* n, const double* pbar,
  * ld; only sphere grid points are written. */
 int hub_apply(hub_ctx* ctx, const double* Ueff, const double* n, const double* c,
               int nstates, const double* colscale, double alpha, void* hpsi, int64_t ld);
+
+/* hub_apply for the state sets set0 .. set0 + nsets - 1 only: c, hpsi and
+ * colscale ([nsets][nstates] or NULL) hold those sets; Ueff and n are the
+ * context's (from every set).  Errors as hub_project_sets. */
+int hub_apply_sets(hub_ctx* ctx, const double* Ueff, const double* n, const double* c, int nstates,
+                   const double* colscale, double alpha, void* hpsi, int64_t ld, int set0, int nsets);
 
 /* Dudarev energy per site (Eq. E_Dudarev; App. A for spinors):
  * EU[I] = Ueff/2 sum_sigma Tr[n - n n] (unpolarized counts the channel

@@ -45,7 +45,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
            "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
-           "hub_energy_fll", "hub_set_site_spin_orbital"]
+           "hub_energy_fll", "hub_set_site_spin_orbital", "hub_project_sets", "hub_apply_sets"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -84,6 +84,8 @@ def lib():
         "hub_sphere_radius": [I, I, D, DP, D, DP],
         "hub_energy_fll": [P, P, P, P, P],
         "hub_set_site_spin_orbital": [P, I, D],
+        "hub_project_sets": [P, P, I64, I, I, I, P],
+        "hub_apply_sets": [P, P, P, P, I, P, D, P, I64, I, I],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -277,8 +279,9 @@ class Hubbard:
     def ncol(self, nstates):
         return 2 * nstates if self.spin == "spinor" else nstates
 
-    def _states(self, psi, nstates=None):
-        """Validate a state tensor; returns (ld, nstates)."""
+    def _states(self, psi, nstates=None, nq=None):
+        """Validate a state tensor of nq state sets (default: all); returns
+        (ld, nstates)."""
         if psi.dtype != self.state_dtype:
             raise TypeError(f"states must be {self.state_dtype}, got {psi.dtype}")
         if not psi.is_cuda:
@@ -293,8 +296,9 @@ class Hubbard:
                 raise ValueError("states must be [nsets][G][ld-major columns] with unit column stride")
             ld = psi.stride(1)
             S = psi.shape[2] // (2 if self.spin == "spinor" else 1)
-        if psi.shape[0] != self.nsets or psi.shape[1] != self.G:
-            raise ValueError(f"states must have {self.nsets} sets of {self.G} grid points")
+        want = self.nsets if nq is None else nq
+        if psi.shape[0] != want or psi.shape[1] != self.G:
+            raise ValueError(f"states must have {want} sets of {self.G} grid points")
         if psi.stride(0) != self.G * ld:
             raise ValueError("state sets must be consecutive ([q][g][ld])")
         return ld, (nstates if nstates is not None else S)
@@ -312,11 +316,19 @@ class Hubbard:
         return torch.empty((self.nsites, self.nblk, LMAX, LMAX), dtype=torch.complex128, device="cuda")
 
     # ---------------------------------------------------------- entry points
-    def project(self, psi, nstates=None, out=None):
-        ld, S = self._states(psi, nstates)
-        c = out if out is not None else self.empty_c(S)
+    def project(self, psi, nstates=None, out=None, sets=None):
+        """Projections of every state set, or of sets = (first, count) only
+        (psi and the result then hold those sets)."""
+        ld, S = self._states(psi, nstates, None if sets is None else int(sets[1]))
+        if sets is None:
+            c = out if out is not None else self.empty_c(S)
+            self._stream()
+            _check(lib().hub_project(self._ctx, _dptr(psi), ld, S, _dptr(c)), "hub_project")
+            return c
+        q0, nq = int(sets[0]), int(sets[1])
+        c = out if out is not None else self.empty_c(S)[:nq].contiguous()
         self._stream()
-        _check(lib().hub_project(self._ctx, _dptr(psi), ld, S, _dptr(c)), "hub_project")
+        _check(lib().hub_project_sets(self._ctx, _dptr(psi), ld, S, q0, nq, _dptr(c)), "hub_project_sets")
         return c
 
     def occupations(self, c, f, with_pbar=True, nbar=True):
@@ -350,11 +362,17 @@ class Hubbard:
                "hub_acbn0_uj")
         return U, J, Ueff, st
 
-    def apply(self, Ueff, n, c, hpsi, alpha=1.0, colscale=None, nstates=None):
-        ld, S = self._states(hpsi, nstates)
+    def apply(self, Ueff, n, c, hpsi, alpha=1.0, colscale=None, nstates=None, sets=None):
+        """hpsi += alpha V_U psi for every state set, or for sets = (first,
+        count) only (c, hpsi and colscale then hold those sets)."""
+        ld, S = self._states(hpsi, nstates, None if sets is None else int(sets[1]))
         self._stream()
-        _check(lib().hub_apply(self._ctx, _dptr(Ueff), _dptr(n), _dptr(c), S, _dptr(colscale), float(alpha),
-                               _dptr(hpsi), ld), "hub_apply")
+        if sets is None:
+            _check(lib().hub_apply(self._ctx, _dptr(Ueff), _dptr(n), _dptr(c), S, _dptr(colscale), float(alpha),
+                                   _dptr(hpsi), ld), "hub_apply")
+        else:
+            _check(lib().hub_apply_sets(self._ctx, _dptr(Ueff), _dptr(n), _dptr(c), S, _dptr(colscale),
+                                        float(alpha), _dptr(hpsi), ld, int(sets[0]), int(sets[1])), "hub_apply_sets")
         return hpsi
 
     def energy(self, Ueff, n):

@@ -371,6 +371,7 @@ ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
     r.mult = mult;
     r.pmult = mult;
     r.spindep = 0;
+    r.q0 = 0;
     r.chunks = c->d_chunks;
     r.site_chunk_ptr = c->d_site_chunk_ptr;
     r.site_chunk_ids = c->d_site_chunk_ids;
@@ -392,8 +393,11 @@ size_t part_need(const hub_ctx* c, int ncol, int mult) {
     return static_cast<size_t>(c->nsets()) * rows * ncol * c->ncplx();
 }
 
+// q0, nq: the state sets projected (psi and out hold those sets only);
+// nq < 0: every set of the context.
 int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site,
-               int table = TAB_PHI) {
+               int table = TAB_PHI, int q0 = 0, int nq = -1) {
+    if (nq < 0) nq = c->nsets();
     const bool grad = table != TAB_PHI;
     const bool spindep = !grad && c->T.spindep;
     const int ncol = c->ncol(nstates);
@@ -402,6 +406,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     if (st) return st;
     ProjArgs a = proj_args(c, psi, ld, ncol, table);
     a.part = c->d_part;
+    a.nq = nq;
     if (!per_site && !grad && grouped(c)) {
         const GroupTables& GT = c->T.grouped;
         a.chunks = c->d_gchunks;
@@ -416,7 +421,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
                 b.chunk_list = list;
                 const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), std::min(4 * k, HUB_GF_MAX));
                 b.wide = pick_wide(c, ncol, cpl, 0);
-                return launch_project(b, nch, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[0], k, s);
+                return launch_project(b, nch, nq, c->precision, c->is_complex, cpl, c->tune_waves[0], k, s);
             });
             if (st) return st;
         }
@@ -435,9 +440,10 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         r.nimg = static_cast<int>(c->T.images.size() / 3);
         r.nspin = c->nspin();
         r.spinor = c->spin_mode == HUB_SPINOR;
+        r.q0 = q0;
         r.dV = (c->cell[0] / c->ngrid[0]) * (c->cell[1] / c->ngrid[1]) * (c->cell[2] / c->ngrid[2]);
         StageTimer tm(c, HUB_STAGE_REDUCE);
-        HUB_TRY(launch_reduce_grouped(r, c->nsets(), c->stream));
+        HUB_TRY(launch_reduce_grouped(r, nq, c->stream));
         return HUB_OK;
     }
     int cpl = pick_cpl(c, psi, ld, 0);
@@ -449,17 +455,18 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     StageTimer tm(c, grad ? HUB_STAGE_GRADPROJ : HUB_STAGE_PROJECT);
     if (!per_site) {
         const int nch = table == TAB_STENCIL ? c->stencil_nchunks : static_cast<int>(c->T.chunks.size());
-        HUB_TRY(launch_project(a, nch, c->nsets(), c->precision, c->is_complex, cpl, waves, 0, c->stream));
+        HUB_TRY(launch_project(a, nch, nq, c->precision, c->is_complex, cpl, waves, 0, c->stream));
     } else {
         for (int s = 0; s < c->T.nsites; ++s) {
             ProjArgs b = a;
             b.chunk_list = c->d_site_chunk_ids + c->T.site_chunk_ptr[s];
-            HUB_TRY(launch_project(b, c->T.site_chunk_ptr[s + 1] - c->T.site_chunk_ptr[s], c->nsets(), c->precision,
+            HUB_TRY(launch_project(b, c->T.site_chunk_ptr[s + 1] - c->T.site_chunk_ptr[s], nq, c->precision,
                                    c->is_complex, cpl, waves, 0, c->stream));
         }
     }
     }
     ReduceArgs r = reduce_args(c, out, ncol, mult);
+    r.q0 = q0;
     if (spindep) {
         // column 2s + sigma takes the rows of its spin component's orbitals
         r.pmult = 2;
@@ -473,7 +480,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         r.prows = c->stencil_part_rows * 3;
     }
     StageTimer tm(c, HUB_STAGE_REDUCE);
-    HUB_TRY(launch_reduce(r, c->nsets(), c->stream));
+    HUB_TRY(launch_reduce(r, nq, c->stream));
     return HUB_OK;
 }
 
@@ -566,8 +573,11 @@ int do_acbn0(hub_ctx* c, const double* n, const double* pbar, double* U, double*
     return HUB_OK;
 }
 
+// q0, nq: the state sets updated (cc, colscale and hpsi hold those sets
+// only); nq < 0: every set of the context.
 int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, int nstates, const double* colscale,
-             double alpha, void* hpsi, int64_t ld, bool per_site) {
+             double alpha, void* hpsi, int64_t ld, bool per_site, int q0 = 0, int nq = -1) {
+    if (nq < 0) nq = c->nsets();
     const int ncol = c->ncol(nstates);
     int st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(ld) * c->ncplx(), c);
     if (st) return st;
@@ -579,7 +589,8 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.qstride = c->G() * ld * c->ncplx();
     a.ncol = ncol;
     a.nstates = nstates;
-    a.nq = c->nsets();
+    a.nq = nq;
+    a.q0 = q0;
     a.nspin = c->nspin();
     a.spinor = c->spin_mode == HUB_SPINOR;
     a.nblk = c->nblk();
@@ -610,7 +621,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
             ApplyArgs b = a;
             b.chunk_list = list;
             const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), std::min(4 * k, HUB_GF_MAX));
-            return launch_apply_grouped(b, nch, c->nsets(), c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
+            return launch_apply_grouped(b, nch, nq, c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
         }, true);
     }
     int cpl = pick_cpl(c, hpsi, ld, 1);
@@ -629,7 +640,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
             ApplyArgs b = a;
             const int c0 = c->T.layer_chunk_ptr[lay];
             b.chunk_list = c->d_all + c0;
-            HUB_TRY(launch_apply(b, c->T.layer_chunk_ptr[lay + 1] - c0, c->nsets(), c->precision, c->is_complex, cpl,
+            HUB_TRY(launch_apply(b, c->T.layer_chunk_ptr[lay + 1] - c0, nq, c->precision, c->is_complex, cpl,
                                  waves, c->stream));
         } else {
             for (int s = 0; s < ns; ++s) {
@@ -638,7 +649,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
                 if (c1 <= c0) continue;
                 ApplyArgs b = a;
                 b.chunk_list = c->d_all + c0;
-                HUB_TRY(launch_apply(b, c1 - c0, c->nsets(), c->precision, c->is_complex, cpl, waves, c->stream));
+                HUB_TRY(launch_apply(b, c1 - c0, nq, c->precision, c->is_complex, cpl, waves, c->stream));
             }
         }
     }
@@ -975,6 +986,14 @@ int hub_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* co
     return do_project(c, psi, ld, nstates, cout, false);
 }
 
+int hub_project_sets(hub_ctx* c, const void* psi, int64_t ld, int nstates, int set0, int nsets, double* cout) {
+    if (!c || !cout) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
+    if (set0 < 0 || nsets < 1 || set0 + nsets > c->nsets()) return HUB_EINVAL;
+    return do_project(c, psi, ld, nstates, cout, false, TAB_PHI, set0, nsets);
+}
+
 int hub_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, double* n, double* pbar,
                     double* nbar) {
     if (!c || !cc || !f || !n || nstates < 1) return HUB_EINVAL;
@@ -1051,6 +1070,15 @@ int hub_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc,
     if (!built(c)) return HUB_ESTATE;
     if (!valid_states(c, hpsi, ld, nstates) || !std::isfinite(alpha)) return HUB_EINVAL;
     return do_apply(c, Ueff, n, cc, nstates, colscale, alpha, hpsi, ld, false);
+}
+
+int hub_apply_sets(hub_ctx* c, const double* Ueff, const double* n, const double* cc, int nstates,
+                   const double* colscale, double alpha, void* hpsi, int64_t ld, int set0, int nsets) {
+    if (!c || !Ueff || !n || !cc) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, hpsi, ld, nstates) || !std::isfinite(alpha)) return HUB_EINVAL;
+    if (set0 < 0 || nsets < 1 || set0 + nsets > c->nsets()) return HUB_EINVAL;
+    return do_apply(c, Ueff, n, cc, nstates, colscale, alpha, hpsi, ld, false, set0, nsets);
 }
 
 int hub_energy(hub_ctx* c, const double* Ueff, const double* n, double* EU) {

@@ -47,8 +47,9 @@ template <bool CPX, bool SPINOR, int CPL>
 __device__ __forceinline__ void coefficient(const ApplyArgs& a, int site, int ai, int img, int q, int col0,
                                             double (&Bf)[CPL * (CPX ? 2 : 1)], int sgf = -1) {
     constexpr int NC = CPX ? 2 : 1;
-    const int ch = SPINOR ? 0 : (q % a.nspin);
-    const int k = a.spinor ? q : q / a.nspin;
+    // q counts the launch's state sets; q0 + q is the context's set (k-point, spin)
+    const int ch = SPINOR ? 0 : ((a.q0 + q) % a.nspin);
+    const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
     const int o0 = a.site_orb0[site];
     const int L = a.site_L[site];
     const double U = a.ueff[site];

@@ -24,7 +24,7 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
     const int site = a.orb_site[r / a.mult];
     const int local = r - a.site_orb0[site] * a.mult;
     const int NC = a.ncplx;
-    const int k = a.spinor ? q : q / a.nspin;
+    const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
     const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     double s0 = 0.0, s1 = 0.0;
     // spin-dependent orbitals: column 2s + sigma of orbital m is the partial
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedA
     const int q = blockIdx.z;
     const bool active = col < a.ncol;
     const int NC = a.ncplx;
-    const int k = a.spinor ? q : q / a.nspin;
+    const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
     const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     const double* base =
         a.part + static_cast<int64_t>(q) * a.prows * a.ncol * NC + static_cast<int64_t>(active ? col : 0) * NC;

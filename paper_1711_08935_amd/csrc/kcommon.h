@@ -58,6 +58,7 @@ struct ApplyArgs {
     int tiles;                // column tiles per chunk (set by the launcher)
     const double* pg;         // velocity gauge: [G] exp(i A.r_g) (re, im), or null
     int spindep;              // per-site chunks with 2L functions [sigma][m] (spinor orbitals)
+    int q0;                   // context index of the first state set of the launch (k-point, spin)
     // grouped chunks: per chunk HUB_GF_MAX (orbital j, image) pairs
     const int32_t* f_orb;
     const int32_t* f_img;

@@ -15,6 +15,7 @@ struct ReduceArgs {
     const int32_t* orb_site; const int32_t* site_orb0; const int32_t* site_L;
     const double* phase; int nimg;        // exp(+i k.T) per k-point and image
     int nspin; int spinor;                // state set -> k-point
+    int q0;                               // context index of the first state set of the launch
     double dV;
 };
 
@@ -23,6 +24,7 @@ struct ReduceGroupedArgs {
     double* out; int J; int ncol; int ncplx;
     const int32_t* red_ptr; const int32_t* red_row; const int32_t* red_img;
     const double* phase; int nimg; int nspin; int spinor;
+    int q0;                   // context index of the first state set of the launch
     double dV;
     int rows_per_orbital;     // average workspace rows per orbital (host)
 };

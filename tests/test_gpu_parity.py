@@ -129,6 +129,25 @@ def test_energy_fll(case):
     assert np.max(np.abs(out[:, 4:] - rows[:, 4:])) <= 1e-12 * scale
 
 
+def test_state_set_ranges(case):
+    """hub_project_sets / hub_apply_sets on one set at a time and on a range
+    reproduce the slices of the all-set calls (each set keeps its k-point)."""
+    hub = case["hub"]
+    psi_d, c_all, hpsi_all = case["psi_d"], case["c"], case["hpsi"]
+    nq = psi_d.shape[0]
+    ranges = [(q, 1) for q in range(nq)] + ([(1, nq - 1)] if nq > 1 else [])
+    for q0, m in ranges:
+        cs = hub.project(psi_d[q0:q0 + m], sets=(q0, m))
+        h = torch.zeros_like(psi_d[q0:q0 + m])
+        hub.apply(case["Ueff"], case["n"], cs, h, sets=(q0, m))
+        torch.cuda.synchronize()
+        assert normwise(cs.cpu().numpy(), c_all[q0:q0 + m].cpu().numpy()) < 1e-14, (q0, m)
+        bar = 1e-14 if case["prec"] == "f64" else 1e-7
+        assert normwise(h.cpu().numpy(), hpsi_all[q0:q0 + m].cpu().numpy()) < bar, (q0, m)
+    with pytest.raises(H.HubError):
+        hub.project(psi_d[:1], sets=(nq, 1))
+
+
 def test_step_modes_agree_and_graph_replays(case):
     hub = case["hub"]
     psi_d, f_d = case["psi_d"], case["f_d"]
