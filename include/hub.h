@@ -63,6 +63,8 @@ extern "C" {
 #define HUB_ENOMEM (-2)      /* host or device allocation failed            */
 #define HUB_EDEVICE (-3)     /* HIP runtime error (incl. an earlier fault)  */
 #define HUB_ESTATE (-4)      /* call not valid in the context's state       */
+#define HUB_ENONFINITE (-5)  /* per-site device status: occupations, U or J
+                                not finite (NaN or Inf in the states)      */
 #define HUB_WDEGENERATE 1    /* per-site status: a U/J denominator < 1e-12  */
 
 /* spin modes */
@@ -256,8 +258,10 @@ int hub_coulomb(hub_ctx* ctx, int site, double* tensor);
  * U_eff = U-bar - J-bar per site, from n and pbar (device).  Sites with a
  * fixed U_eff (hub_set_fixed_ueff) report U = Ueff = fixed, J = 0.  Needs the
  * Coulomb tensors (hub_coulomb(ctx, -1, NULL)) or returns HUB_ESTATE.
- * status (device int32, may be NULL): 0, or HUB_WDEGENERATE where a
- * denominator is below 1e-12 (that U or J is then 0). */
+ * status (device int32, may be NULL): 0, HUB_WDEGENERATE where a
+ * denominator is below 1e-12 (that U or J is then 0), or HUB_ENONFINITE
+ * where the site's occupations (or its U, J) are not finite (U, J, Ueff are
+ * then NaN; a fixed U_eff is kept). */
 int hub_acbn0_uj(hub_ctx* ctx, const double* n, const double* pbar,
                  double* U, double* J, double* Ueff, int* status);
 

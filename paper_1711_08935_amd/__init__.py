@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhub.so")
 
 HUB_OK, HUB_EINVAL, HUB_ENOMEM, HUB_EDEVICE, HUB_ESTATE = 0, -1, -2, -3, -4
 HUB_WDEGENERATE = 1
+HUB_ENONFINITE = -5
 SPIN_MODES = {"unpolarized": 1, "collinear": 2, "spinor": 4}
 PRECISIONS = {"f64": 0, "f32": 1}
 STEP_MODES = {"batched": 0, "graph": 1, "persite": 2}

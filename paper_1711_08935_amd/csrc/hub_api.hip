@@ -684,6 +684,7 @@ const char* hub_strerror(int code) {
     case HUB_EDEVICE: return "HIP device error";
     case HUB_ESTATE: return "call not valid in the current context state";
     case HUB_WDEGENERATE: return "degenerate U/J denominator";
+    case HUB_ENONFINITE: return "occupations, U or J not finite";
     default: return "unknown status";
     }
 }

@@ -287,7 +287,17 @@ __global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
             a.U[site] = fixed;
             a.J[site] = 0.0;
             a.Ueff[site] = fixed;
-            if (a.status) a.status[site] = 0;
+            if (a.status) {
+                // flag occupations that are not finite (NaN or Inf in the states)
+                bool finite = true;
+                const double* nb0 = a.n + static_cast<int64_t>(site) * a.nblk * 98;
+                for (int b = 0; b < a.nblk; ++b)
+                    for (int e = 0; e < L * L; ++e) {
+                        const int64_t o = b * 98 + ((e / L) * 7 + e % L) * 2;
+                        finite = finite && isfinite(nb0[o]) && isfinite(nb0[o + 1]);
+                    }
+                a.status[site] = finite ? 0 : HUB_ENONFINITE;
+            }
         }
         return;
     }
@@ -388,6 +398,11 @@ __global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
     double U = 0.0, J = 0.0;
     if (fabs(dU) < 1e-12) st = HUB_WDEGENERATE; else U = redU[0] / dU;
     if (fabs(dJ) < 1e-12) st = HUB_WDEGENERATE; else J = redJ[0] / dJ;
+    if (!isfinite(redU[0]) || !isfinite(redJ[0]) || !isfinite(dU) || !isfinite(dJ)) {
+        // occupations that are not finite: report it and keep U, J NaN
+        st = HUB_ENONFINITE;
+        U = J = __builtin_nan("");
+    }
     a.U[site] = U;
     a.J[site] = J;
     a.Ueff[site] = U - J;

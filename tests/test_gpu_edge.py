@@ -107,3 +107,41 @@ def test_argument_errors_raise_before_launch():
     assert e.value.code == H.HUB_ESTATE
     rc = H.lib().hub_project(hub._ctx, psi.data_ptr(), 2, 4, psi.data_ptr())   # ld < nstates
     assert rc == H.HUB_EINVAL
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+def test_nonfinite_states_are_flagged(fixed):
+    """A NaN in one state at a grid point that only site 0 covers: site 0's
+    status is HUB_ENONFINITE (ACBN0: U and J NaN; fixed U_eff kept), and the
+    sites of the other species, whose projections and N-bar never see it,
+    stay finite with status 0."""
+    from synth import make_config, make_occupations, make_states
+    cfg = make_config("nio_afm", small=True)
+    hub = make_hub(cfg, "f64")
+    if fixed:
+        for i in range(hub.nsites):
+            hub.set_fixed_ueff(i, 0.2)
+    else:
+        hub.coulomb(-1)
+    cover = np.zeros((hub.nsites, hub.G), bool)
+    for s in range(hub.nsites):
+        cover[s, hub.site_points(s)[0]] = True
+    only0 = np.flatnonzero(cover[0] & ~cover[1:].any(axis=0))
+    assert only0.size > 0
+    psi = make_states(cfg, device="cuda")
+    psi[0, int(only0[0]), 3] = float("nan")
+    f_d = torch.from_numpy(make_occupations(cfg)).cuda()
+    c = hub.project(psi)
+    n, pbar, _ = hub.occupations(c, f_d)
+    U, J, Ueff, st = hub.acbn0(n, pbar)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert st[0] == H.HUB_ENONFINITE
+    other = [s for s in range(hub.nsites) if cfg.sites[s]["species"] != cfg.sites[0]["species"]]
+    assert other and all(st[s] == 0 for s in other)
+    assert np.all(np.isfinite(U.cpu().numpy()[other]))
+    if fixed:
+        assert np.all(Ueff.cpu().numpy() == 0.2)
+    else:
+        assert np.isnan(U.cpu().numpy()[0])
+    assert H.lib().hub_strerror(H.HUB_ENONFINITE) == b"occupations, U or J not finite"
