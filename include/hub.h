@@ -128,9 +128,9 @@ int hub_sphere_radius(int method, int l, double zeta, const double cell[3], doub
  * grid on its own), so that spin component sigma of the states is projected
  * on, and V_U psi built from, phi^sigma:
  * n^{st}_ab = sum w f conj(<phi^s_a|psi^s>) <phi^t_b|psi^t>.  Spinor
- * contexts only, before hub_finalize*.  A context with such a site uses the
- * per-site work list (table of 2L values per entry), takes a fixed U_eff for
- * these sites (hub_set_fixed_ueff; hub_coulomb skips them and rejects them
+ * contexts only, before hub_finalize*.  Both work lists then carry the two
+ * spin components' orbitals (2L functions per cover).  A context with such a
+ * site takes a fixed U_eff for these sites (hub_set_fixed_ueff; hub_coulomb skips them and rejects them
  * by index), and has no forces, current or velocity-gauge form
  * (HUB_ESTATE / HUB_EINVAL).  Errors: HUB_EINVAL (bad site, zeta_dn not
  * positive and finite, not a spinor context), HUB_ESTATE (after
@@ -160,10 +160,9 @@ int hub_set_tuning(hub_ctx* ctx, int which, int cols_per_lane, int waves, int la
  * apply; 0 uses one chunk per site and image, with overlapping sites applied
  * in successive atomic-free layers.  A grid point covered by more than 16
  * orbitals in total has its covers split over several passes of the
- * grouped list (at most 16 orbitals each; the apply launches the passes in
- * turn, hub_query 14).  Without spin-dependent orbitals the grouped list
- * always exists.  Both give the same results up to summation order.  Any
- * time. */
+ * grouped list (at most 16 functions each; the apply launches the passes in
+ * turn, hub_query 14).  Both give the same results up to summation order.
+ * Any time. */
 int hub_set_worklist(hub_ctx* ctx, int grouped_list);
 
 /* Launch policy of the grouped work list, whose chunks fall in four classes

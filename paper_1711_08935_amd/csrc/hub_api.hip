@@ -71,6 +71,7 @@ struct hub_ctx {
     HubChunk* d_gchunks = nullptr;
     int32_t *d_gall = nullptr, *d_ggidx = nullptr, *d_gf_orb = nullptr, *d_gf_img = nullptr;
     int32_t *d_gred_ptr = nullptr, *d_gred_row = nullptr, *d_gred_img = nullptr;
+    int32_t* d_gspin_shift = nullptr;        // spin-dependent orbitals: L per orbital
     double* d_gtab = nullptr;
     std::vector<char> have_tensor;
     size_t table_bytes = 0;
@@ -159,7 +160,7 @@ void release(hub_ctx* c) {
     f(c->d_phi2);
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
-    f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab);
+    f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -412,6 +413,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         a.chunks = c->d_gchunks;
         a.gidx = c->d_ggidx;
         a.tab = c->d_gtab;
+        a.tabmult = 1;               // grouped chunks count their functions in C.L
         a.prows = GT.part_rows;
         {
             StageTimer tm(c, HUB_STAGE_PROJECT);
@@ -436,6 +438,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         r.red_row = c->d_gred_row;
         r.red_img = c->d_gred_img;
         r.rows_per_orbital = GT.red_ptr.empty() ? 0 : GT.red_ptr.back() / std::max(1, c->T.J);
+        r.spin_shift = c->T.spindep ? c->d_gspin_shift : nullptr;
         r.phase = c->d_phase;
         r.nimg = static_cast<int>(c->T.images.size() / 3);
         r.nspin = c->nspin();
@@ -608,6 +611,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.orb_site = c->d_orb_site;
     a.site_orb0 = c->d_site_orb0;
     a.site_L = c->d_site_L;
+    a.spindep = c->T.spindep ? 1 : 0;
     if (!per_site && grouped(c)) {
         a.wide = 1;
         a.chunks = c->d_gchunks;
@@ -905,6 +909,12 @@ int hub_finalize(hub_ctx* c, void* stream) {
         up(&c->d_gred_ptr, T.grouped.red_ptr);
         up(&c->d_gred_row, T.grouped.red_row);
         up(&c->d_gred_img, T.grouped.red_img);
+        if (T.spindep) {
+            std::vector<int32_t> shift(T.J);
+            for (int s = 0; s < T.nsites; ++s)
+                for (int m = 0; m < T.site_L[s]; ++m) shift[T.site_orb0[s] + m] = T.site_L[s];
+            up(&c->d_gspin_shift, shift);
+        }
     }
     if (e == hipSuccess) {
         e = hipMalloc(reinterpret_cast<void**>(&c->d_tensor), c->sites.size() * 2401 * sizeof(double));

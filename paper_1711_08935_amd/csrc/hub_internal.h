@@ -87,7 +87,8 @@ struct HostTables {
     std::vector<double> mphi;                // per entry, 3L values [m][i]: (r_p - R)_i phi_m
     // Spin-dependent orbitals (some site has a spin-down exponent): per
     // entry 2L values [sigma][m], the orbital of each spin component (sites
-    // without one repeat their orbital); the grouped list is then not built.
+    // without one repeat their orbital); the grouped list then carries 2L
+    // functions per cover as well.
     bool spindep = false;
     std::vector<double> phi2;
     std::vector<int32_t> images;             // unique lattice images, 3 per image

@@ -153,9 +153,15 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
     // column compute zeros for column 0 of their set and are then idle)
     for (int f = wave; f < L; f += nw) {
         int site, ai, img;
+        int sgf = -1;
         if constexpr (GROUPED) {
             const int chunk = a.chunk_list[chunk_slot];
-            const int j = a.f_orb[chunk * HUB_GF_MAX + f];
+            int j = a.f_orb[chunk * HUB_GF_MAX + f];
+            if (a.spindep) {
+                // function of the spin component sgf's orbital j (stored as j + sgf J)
+                sgf = j >= a.J ? 1 : 0;
+                j -= sgf * a.J;
+            }
             img = a.f_img[chunk * HUB_GF_MAX + f];
             site = a.orb_site[j];
             ai = j - a.site_orb0[site];
@@ -165,7 +171,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, const HubChunk& C
             img = C.img;
         }
         double Bf[NV];
-        coefficient<CPX, SPINOR, CPL>(a, site, ai, img, q, active ? col0 : a.ncol, Bf, SPINDEP ? f / C.L : -1);
+        if constexpr (SPINDEP) sgf = f / C.L;
+        coefficient<CPX, SPINOR, CPL>(a, site, ai, img, q, active ? col0 : a.ncol, Bf, sgf);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Bs[(f * NV + v) * HUB_WAVE + lane] = Bf[v];
     }

@@ -64,8 +64,11 @@ __global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedA
     const int NC = a.ncplx;
     const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
     const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
-    const double* base =
-        a.part + static_cast<int64_t>(q) * a.prows * a.ncol * NC + static_cast<int64_t>(active ? col : 0) * NC;
+    // spin-dependent orbitals: spinor column 2s + sigma reads the rows of the
+    // orbital of its spin component
+    const int64_t shift = (a.spin_shift && (col & 1)) ? a.spin_shift[j] : 0;
+    const double* base = a.part + (static_cast<int64_t>(q) * a.prows + shift) * a.ncol * NC +
+                         static_cast<int64_t>(active ? col : 0) * NC;
     double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
     const int t0 = a.red_ptr[j], t1 = a.red_ptr[j + 1];
     int t = t0 + wave;

@@ -27,6 +27,8 @@ struct ReduceGroupedArgs {
     int q0;                   // context index of the first state set of the launch
     double dV;
     int rows_per_orbital;     // average workspace rows per orbital (host)
+    const int32_t* spin_shift;  // spin-dependent orbitals: per orbital, the rows from a
+                                // spin-up function to its spin-down one (L); else null
 };
 
 struct NbarArgs {

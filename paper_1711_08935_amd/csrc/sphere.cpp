@@ -366,9 +366,12 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
     T.nentries = nreal;
     if (e > INT32_MAX) return HUB_EINVAL;
 
-    // ---- grouped work list (cover signatures); not with spin-dependent
-    // orbitals (their per-site tables hold the two spin components)
-    if (!T.spindep) {
+    // ---- grouped work list (cover signatures).  With spin-dependent
+    // orbitals every cover contributes 2L functions, the orbitals of the
+    // spin-up then of the spin-down component (function sigma L + m; its
+    // orbital index is stored as j + sigma J)
+    {
+        const int smul = T.spindep ? 2 : 1;
         GroupTables& GT = T.grouped;
         struct Cover {
             int32_t g, site, img;
@@ -414,7 +417,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                 }
             };
             while (k < cov.size() && cov[k].g == cov[i].g) {
-                const int Ls = T.site_L[cov[k].site];
+                const int Ls = smul * T.site_L[cov[k].site];
                 if (acc + Ls > HUB_GF_MAX) {
                     close();
                     ++pass;
@@ -441,7 +444,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                 const int pass = key.first;
                 const Sig& sig = key.second;
                 int nf = 0;
-                for (const auto& sl : sig) nf += T.site_L[sl.first];
+                for (const auto& sl : sig) nf += smul * T.site_L[sl.first];
                 // more than 8 functions: the kernels take half as many entries
                 // per batch, so half-length chunks keep the per-wave chains
                 // (and the launches' latency) comparable
@@ -469,6 +472,10 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                             const int L = T.site_L[cv.site];
                             const double* src = &T.spheres[cv.site].phi[static_cast<size_t>(cv.p) * L];
                             for (int m = 0; m < L; ++m) GT.tab.push_back(src[m]);
+                            if (T.spindep) {
+                                const double* dn = &T.spheres[cv.site].phi_dn[static_cast<size_t>(cv.p) * L];
+                                for (int m = 0; m < L; ++m) GT.tab.push_back(dn[m]);
+                            }
                         }
                     }
                     for (size_t t = nb; t < np; ++t) {
@@ -481,10 +488,11 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     }
                     int f = 0;
                     for (const auto& sl : sig)
-                        for (int m = 0; m < T.site_L[sl.first]; ++m, ++f) {
-                            GT.f_orb[GT.chunks.size() * HUB_GF_MAX + f] = T.site_orb0[sl.first] + m;
-                            GT.f_img[GT.chunks.size() * HUB_GF_MAX + f] = sl.second;
-                        }
+                        for (int sg = 0; sg < smul; ++sg)
+                            for (int m = 0; m < T.site_L[sl.first]; ++m, ++f) {
+                                GT.f_orb[GT.chunks.size() * HUB_GF_MAX + f] = T.site_orb0[sl.first] + m + sg * J;
+                                GT.f_img[GT.chunks.size() * HUB_GF_MAX + f] = sl.second;
+                            }
                     tab0 += static_cast<int64_t>(np) * nf;
                     rows += nf;
                     GT.chunks.push_back(C);
@@ -493,11 +501,14 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
             GT.npass = npass;
             GT.part_rows = rows;
             if (rows > INT32_MAX) GT.ok = false;
-            // CSR orbital j -> (workspace row, image)
+            // CSR orbital j -> (workspace row, image); with spin-dependent
+            // orbitals the rows of the spin-up functions (the spin-down
+            // function of the same orbital and cover is L rows further)
             std::vector<std::vector<std::pair<int32_t, int32_t>>> red(J);
             for (size_t c = 0; c < GT.chunks.size(); ++c)
                 for (int f = 0; f < GT.chunks[c].L; ++f) {
                     const int j = GT.f_orb[c * HUB_GF_MAX + f];
+                    if (j >= J) continue;
                     red[j].push_back({GT.chunks[c].part0 + f, GT.f_img[c * HUB_GF_MAX + f]});
                 }
             GT.red_ptr.assign(J + 1, 0);

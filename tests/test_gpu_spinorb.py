@@ -3,11 +3,13 @@ oracle.
 
 The noncollinear layered workload with a spin-down Slater exponent on every
 site (d: 2.0 -> 2.6, p: 1.4 -> 1.1) and a fixed U_eff per site, both storage
-precisions: projections c^sigma = <phi^sigma|psi^sigma>, occupations, E_U,
-V_U psi, the batched and graph steps.  The oracle projects and applies per
-spin component on the whole cell (its full-grid definitions).  Bars as in
-test_gpu_parity.py.  With zeta_dn = zeta the spin-dependent kernels give
-results bitwise equal to the spin-independent per-site path.
+precisions, both work lists: projections c^sigma = <phi^sigma|psi^sigma>,
+occupations, E_U, V_U psi, the batched, graph and per-site steps.  The oracle
+projects and applies per spin component on the whole cell (its full-grid
+definitions).  Bars as in test_gpu_parity.py.  With zeta_dn = zeta the
+spin-dependent per-site kernels give results bitwise equal to the
+spin-independent per-site path, and the grouped ones agree with the
+spin-independent grouped path to rounding.
 """
 
 import numpy as np
@@ -62,9 +64,18 @@ def case(request):
     return dict(prec=prec, cfg=cfg, hub=hub, psi_d=psi_d, f=f, f_d=torch.from_numpy(f).cuda(), sys=sys_, ref=ref)
 
 
-def test_projection_occupations_energy_apply(case):
+@pytest.mark.parametrize("grouped", [True, False], ids=["grouped", "persite"])
+def test_projection_occupations_energy_apply(case, grouped):
     hub, ref = case["hub"], case["ref"]
-    assert hub.query(11) == 0                      # per-site work list
+    assert hub.query(11) > 0
+    hub.set_worklist(grouped)
+    try:
+        _check_calls(case, hub, ref)
+    finally:
+        hub.set_worklist(True)
+
+
+def _check_calls(case, hub, ref):
     c = hub.project(case["psi_d"])
     n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
     ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
@@ -92,7 +103,8 @@ def test_steps(case):
         outs[mode] = (h, bufs)
     h, bufs = outs["batched"]
     assert torch.equal(outs["graph"][0], h)
-    assert torch.equal(outs["persite"][0], h)
+    # per-site launches use the per-site list: the same sums in another order
+    assert normwise(outs["persite"][0].cpu().numpy(), h.cpu().numpy()) < (1e-13 if case["prec"] == "f64" else 2e-7)
     assert normwise(c_to_oracle(hub, bufs["c"]), ref["c"]) < 1e-12
     assert torch.all(bufs["Ueff"] == UEFF)
     bar = 1e-12 if case["prec"] == "f64" else 2e-7
@@ -115,7 +127,22 @@ def test_equal_exponents_match_spin_independent_path(prec):
     cfg_same = _config(lambda s: s["zeta"])
     cfg_plain = make_config("spinor_layers", small=True)
     psi, f = states_and_occupations(cfg_plain)
+    # grouped lists: the same sums, split over different passes
     a = _hub(cfg_same, prec)
+    b = _hub(cfg_plain, prec)
+    psi_d, _ = device_states(a, psi)
+    f_d = torch.from_numpy(f).cuda()
+    ca, cb = a.project(psi_d), b.project(psi_d)
+    na, _, _ = a.occupations(ca, f_d, with_pbar=False)
+    ueff = torch.full((a.nsites,), UEFF, dtype=torch.float64, device="cuda")
+    ha, hb = torch.zeros_like(psi_d), torch.zeros_like(psi_d)
+    a.apply(ueff, na, ca, ha)
+    b.apply(ueff, na, ca, hb)
+    torch.cuda.synchronize()
+    assert normwise(ca.cpu().numpy(), cb.cpu().numpy()) < 1e-14
+    assert normwise(ha.cpu().numpy(), hb.cpu().numpy()) < (1e-14 if prec == "f64" else 1e-7)
+    # per-site lists: bitwise
+    a = _hub(cfg_same, prec, worklist_grouped=False)
     b = _hub(cfg_plain, prec, worklist_grouped=False)
     psi_d, _ = device_states(a, psi)
     f_d = torch.from_numpy(f).cuda()
