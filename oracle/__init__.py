@@ -37,9 +37,9 @@ Modules (each function cites the passage it follows):
 * ``stencil``     forces through <phi|grad psi> with a 4th-order central
                   difference of the states (Sec. IV, the paper's own form)
 
-Parity pins live in ``tests/test_oracle_*.py``.  Functions whose values no
-independent property fixes are listed there and in the design doc as
-"parity unpinned".
+Parity pins live in ``tests/test_oracle_*.py``.  A function whose values no
+independent property fixes would say "parity unpinned" in its module
+header; none does.
 """
 
 from . import harmonics, orbitals, projection, occupations, coulomb, acbn0, potential, forces, step, gauge, stencil, radius, fll, spinorb  # noqa: F401

@@ -2,7 +2,7 @@
 
 Collinear (Sec. III, Eqs. ACBN0_U and ACBN0_J) and noncollinear (App. B).
 
-Index reading of the numerators (the design doc lists it): the printed numerators
+Index reading of the numerators: the printed numerators
 repeat m' and leave m''' free; they are read as
 P-bar^alpha_{m m'} P-bar^beta_{m'' m'''} (m m'|m'' m''') for U and
 P-bar^alpha_{m m'} P-bar^alpha_{m'' m'''} (m m'''|m'' m') for J, the same

@@ -7,7 +7,7 @@ Paper passages followed:
 * App. B, notation for (m m' sigma | m'' m''' sigma'): the double integral of
   phi_m* phi_m'(r1) phi_m''* phi_m'''(r2) / |r1 - r2|.
 
-Discretisation (readings listed in the design doc):
+Discretisation (readings where the paper is silent):
 * Free-space (isolated) kernel even in periodic cells: the integrals are
   single-centre, over the unfolded sphere points of one site.
 * T[a,b,c,d] = dV^2 sum_{p,p'} rho_ab(p) K(p - p') rho_cd(p'),

@@ -9,7 +9,7 @@ Paper passages followed:
 * Sec. II, sphere-radius discussion: the sphere is truncated at a radius r_c.
 * Eq. occ_matrices: the projections are <phi_{I,m}|psi_{nk}>.
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
 * The radial part is a Slater-type r^l exp(-zeta r) (the paper's come from
   pseudopotentials); phi_m(r) = N_m exp(-zeta |r|) S_lm(r) with S_lm the real
   solid harmonic.

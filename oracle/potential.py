@@ -5,7 +5,7 @@
   sum_{mm' ss'} n^{ss'}_{mm'} n^{s's}_{m'm}] (App. A, final equation).
 * V_U|psi> = sum_I sum_{mm'} V_mm' |phi_m><phi_m'|psi> (Eq. pot_V_U).
 
-Transpose reading (the design doc lists it): the potential is the functional
+Transpose reading: the potential is the functional
 derivative of E_U with respect to psi* (Eq. minimization).  With
 n_mm' = <psi|phi_m><phi_m'|psi> this derivative gives
 V_ab = U_eff (delta_ab / 2 - n_ba), i.e. the transpose of the printed

@@ -1,6 +1,6 @@
 """Seeded Kohn-Sham-like states and occupations.
 
-Recipe (also stated in the design doc):
+Recipe:
 * Random numbers come from ``numpy.random.default_rng(cfg.seed)`` on the host,
   drawn in a fixed order: for every state set q (k-point major, then spin),
   for every state: 8 Gaussian centres U(cell), widths U[0.5, 1.5] bohr and
