@@ -14,7 +14,10 @@ Everything after the projection (occupations, U_eff, V, E_U) is unchanged;
 the apply builds component sigma of V_U psi from phi^sigma:
 (V_U psi)^s(r_g) = sum_a Phi^s_{a,k}(r_g) B^s_a, B^s = sum_t V^{st} c^t
 (potential.coefficients).  U_eff is given (the empirical scheme): App. B
-writes ACBN0 for spin-independent orbitals.
+writes ACBN0 for spin-independent orbitals.  The forces (Sec. IV) and the
+current (Sec. V) keep their forms with the gradient and position-moment
+projections of each component's orbital (forces.forces_analytic,
+gauge.current on the spinor layout).
 """
 
 import numpy as np
@@ -63,3 +66,30 @@ def apply_spin(system, c, V_list, form="fullgrid"):
                     np.add.at(out[ik, :, :, sg], sp.g, (sp.phi * ph[None, :]).T @ blk)
                     off += site.L
     return out
+
+
+def _per_component(system, psi, fn):
+    """Stack fn(component system, component states, its spheres) over the two
+    spin components on a last axis."""
+    out = []
+    for sg, comp in enumerate(component_systems(system)):
+        out.append(fn(comp, np.asarray(psi)[..., sg], all_spheres(comp)))
+    return np.stack(out, axis=-1)
+
+
+def gradient_projections_spin(system, psi):
+    """d[k][j][i][s][sigma] = <grad phi^sigma_j|psi^sigma_s> (forces.py form)."""
+    from .forces import gradient_projections
+    return _per_component(system, psi, gradient_projections)
+
+
+def moment_projections_spin(system, psi, A=(0.0, 0.0, 0.0)):
+    """rho[k][j][i][s][sigma]: position moments of phi^sigma (gauge.py form)."""
+    from .gauge import moment_projections
+    return _per_component(system, psi, lambda comp, x, sps: moment_projections(comp, x, sps, A))
+
+
+def project_gauge_spin(system, psi, A):
+    """c^A[k][j][s][sigma] with the orbital of each spin component."""
+    from .gauge import project_gauge
+    return _per_component(system, psi, lambda comp, x, sps: project_gauge(comp, x, sps, A))

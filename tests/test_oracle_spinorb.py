@@ -100,3 +100,68 @@ def test_apply_is_energy_derivative():
     an = 2.0 * sys_.dV * np.sum(np.conj(delta) * hpsi * wf[:, None, :, None]).real
     assert abs(an) > 1e-6
     assert abs(fd - an) < 1e-7 * abs(an)
+
+
+def test_forces_are_position_derivative():
+    """F from the components' orbital gradients = central FD of E_U in R
+    (frozen sphere points and normalization, both components moved)."""
+    from oracle import forces as FO
+    from oracle.orbitals import build_sphere
+    sys_ = _system()
+    psi = _states(sys_, 3, 11)
+    f = np.random.default_rng(12).uniform(0.0, 1.0, size=(sys_.nk, 3))
+    ueffs = (0.35, 0.2)
+    comps = SO.component_systems(sys_)
+    ref = [[build_sphere(cs, s) for s in cs.sites] for cs in comps]
+
+    def energy(I, i, dR):
+        cs_list = []
+        for cs, sps in zip(comps, ref):
+            sp = list(sps)
+            R = cs.sites[I].R.copy()
+            R[i] += dR
+            sp[I] = build_sphere(cs, cs.sites[I], R_eval=R, norms=sps[I].norms)
+            cs_list.append(sp)
+        c = np.stack([P.project_sphere(cs, psi[..., sg], sps) for sg, (cs, sps) in enumerate(zip(comps, cs_list))],
+                     axis=-1)
+        n, _, _ = occ.occupations(sys_, c, f, with_pbar=False)
+        return sum(POT.energy(sys_, u, nn) for u, nn in zip(ueffs, n))
+
+    c = SO.project_spin(sys_, psi, form="sphere")
+    V, _ = _V(sys_, c, f, ueffs)
+    F = FO.forces_analytic(sys_, c, SO.gradient_projections_spin(sys_, psi), V, f)
+    delta = 1e-4
+    for I in range(2):
+        for i in range(3):
+            fd = -(energy(I, i, delta) - energy(I, i, -delta)) / (2 * delta)
+            assert abs(F[I, i] - fd) < 1e-6 * max(1.0, np.abs(F).max()), (I, i)
+    assert np.abs(F).max() > 1e-4
+
+
+def test_current_is_field_derivative():
+    """J from the components' position moments = central FD in A of the
+    site's sum w f <psi|V^A|psi> with V fixed."""
+    from oracle import gauge as GA
+    sys_ = _system()
+    psi = _states(sys_, 3, 13)
+    f = np.random.default_rng(14).uniform(0.0, 1.0, size=(sys_.nk, 3))
+    A = np.array([0.137, -0.291, 0.083])
+    cA = SO.project_gauge_spin(sys_, psi, A)
+    V, _ = _V(sys_, cA, f)
+    J = GA.current(sys_, cA, SO.moment_projections_spin(sys_, psi, A), V, f)
+    off = P.orbital_offsets(sys_)
+
+    def site_e(c, I):
+        mask = np.zeros(c.shape[1], bool)
+        mask[off[I]:off[I + 1]] = True
+        return GA.expectation(sys_, np.where(mask[None, :, None, None], c, 0.0), V, f)
+
+    delta = 1e-5
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = delta
+        cp, cm = SO.project_gauge_spin(sys_, psi, A + e), SO.project_gauge_spin(sys_, psi, A - e)
+        for I in range(2):
+            fd = (site_e(cp, I) - site_e(cm, I)) / (2 * delta)
+            assert abs(J[I, i] - fd) < 1e-7 * np.abs(J).max(), (I, i)
+    assert np.abs(J).max() > 1e-4
