@@ -129,12 +129,13 @@ int hub_sphere_radius(int method, int l, double zeta, const double cell[3], doub
  * on, and V_U psi built from, phi^sigma:
  * n^{st}_ab = sum w f conj(<phi^s_a|psi^s>) <phi^t_b|psi^t>.  Spinor
  * contexts only, before hub_finalize*.  Both work lists then carry the two
- * spin components' orbitals (2L functions per cover).  A context with such a
- * site takes a fixed U_eff for these sites (hub_set_fixed_ueff; hub_coulomb skips them and rejects them
- * by index), and has no forces, current or velocity-gauge form
- * (HUB_ESTATE / HUB_EINVAL).  Errors: HUB_EINVAL (bad site, zeta_dn not
- * positive and finite, not a spinor context), HUB_ESTATE (after
- * finalize). */
+ * spin components' orbitals (2L functions per cover).  Such sites take a
+ * fixed U_eff (hub_set_fixed_ueff; hub_coulomb skips them and rejects them
+ * by index).  hub_forces and hub_current use each component's orbital
+ * gradients and position moments; the state-gradient forces and the
+ * velocity gauge are not available in such a context (HUB_ESTATE /
+ * HUB_EINVAL).  Errors: HUB_EINVAL (bad site, zeta_dn not positive and
+ * finite, not a spinor context), HUB_ESTATE (after finalize). */
 int hub_set_site_spin_orbital(hub_ctx* ctx, int site, double zeta_dn);
 
 /* Fix the effective U of one site (the empirical DFT+U scheme, Sec. II);

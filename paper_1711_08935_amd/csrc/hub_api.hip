@@ -58,6 +58,7 @@ struct hub_ctx {
     int32_t *d_all = nullptr, *d_gidx = nullptr, *d_img = nullptr;
     double *d_phi = nullptr, *d_gphi = nullptr, *d_phase = nullptr;
     double* d_phi2 = nullptr;                // [e][sigma][m] spin-dependent orbitals
+    double *d_gphi_dn = nullptr, *d_mphi_dn = nullptr;   // their gradient and moment tables
     int32_t *d_site_chunk_ptr = nullptr, *d_site_chunk_ids = nullptr, *d_orb_site = nullptr;
     int32_t *d_site_L = nullptr, *d_site_orb0 = nullptr, *d_site_species = nullptr;
     int32_t *d_species_orb_ptr = nullptr, *d_species_orb_ids = nullptr;
@@ -157,7 +158,7 @@ void release(hub_ctx* c) {
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
     f(c->d_pg); f(c->d_mphi); f(c->d_images); f(c->d_kred);
     c->d_pg = nullptr;
-    f(c->d_phi2);
+    f(c->d_phi2); f(c->d_gphi_dn); f(c->d_mphi_dn);
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift);
@@ -328,7 +329,7 @@ int run_classes(hub_ctx* c, F&& launch, bool per_pass = false) {
 // moments about the site centre (velocity-gauge current) or the 4th-order
 // differences of the orbitals on the dilated spheres (state-gradient forces,
 // a work list of its own).
-enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2, TAB_STENCIL = 3 };
+enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2, TAB_STENCIL = 3, TAB_GRAD_DN = 4, TAB_MOMENT_DN = 5 };
 
 ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table) {
     const bool grad = table != TAB_PHI;
@@ -343,6 +344,8 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table)
     a.chunk_list = c->d_all;
     a.gidx = c->d_gidx;
     a.tab = table == TAB_GRAD ? c->d_gphi : (table == TAB_MOMENT ? c->d_mphi : c->d_phi);
+    if (table == TAB_GRAD_DN) a.tab = c->d_gphi_dn;         // spin-down orbitals' tables
+    if (table == TAB_MOMENT_DN) a.tab = c->d_mphi_dn;
     a.tabmult = grad ? 3 : 1;
     if (table == TAB_PHI && c->T.spindep) {
         // both spin components' orbitals: 2L functions per entry
@@ -373,6 +376,7 @@ ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
     r.pmult = mult;
     r.spindep = 0;
     r.q0 = 0;
+    r.colpar = -1;
     r.chunks = c->d_chunks;
     r.site_chunk_ptr = c->d_site_chunk_ptr;
     r.site_chunk_ids = c->d_site_chunk_ids;
@@ -396,8 +400,10 @@ size_t part_need(const hub_ctx* c, int ncol, int mult) {
 
 // q0, nq: the state sets projected (psi and out hold those sets only);
 // nq < 0: every set of the context.
+// colpar >= 0: the reduction writes only the columns of that parity (the
+// spin component whose orbitals the table holds).
 int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site,
-               int table = TAB_PHI, int q0 = 0, int nq = -1) {
+               int table = TAB_PHI, int q0 = 0, int nq = -1, int colpar = -1) {
     if (nq < 0) nq = c->nsets();
     const bool grad = table != TAB_PHI;
     const bool spindep = !grad && c->T.spindep;
@@ -470,6 +476,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     }
     ReduceArgs r = reduce_args(c, out, ncol, mult);
     r.q0 = q0;
+    r.colpar = colpar;
     if (spindep) {
         // column 2s + sigma takes the rows of its spin component's orbitals
         r.pmult = 2;
@@ -862,7 +869,11 @@ int hub_finalize(hub_ctx* c, void* stream) {
     up(&c->d_img, T.img);
     up(&c->d_phi, T.phi);
     up(&c->d_gphi, T.gphi);
-    if (T.spindep) up(&c->d_phi2, T.phi2);
+    if (T.spindep) {
+        up(&c->d_phi2, T.phi2);
+        up(&c->d_gphi_dn, T.gphi_dn);
+        up(&c->d_mphi_dn, T.mphi_dn);
+    }
     up(&c->d_mphi, T.mphi);
     up(&c->d_images, T.images);
     up(&c->d_kred, c->kred);
@@ -1130,13 +1141,22 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
                      const double* Ueff, const double* n, double* out, int table) {
     if (!c || !cc || !f || !Ueff || !n || !out) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
-    if (c->T.spindep) return HUB_ESTATE;        // no gradient tables of spin-dependent orbitals
+    if (c->T.spindep && table == TAB_STENCIL) return HUB_ESTATE;   // no dilated tables per spin
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
     const int ncol = c->ncol(nstates);
     const size_t need = static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx();
     int st = ensure(&c->d_grad, &c->grad_cap, need, c);
     if (st) return st;
-    st = do_project(c, psi, ld, nstates, c->d_grad, false, table);
+    if (c->T.spindep) {
+        // spin-dependent orbitals: the spin-up tables give the even columns,
+        // the spin-down tables the odd ones
+        st = do_project(c, psi, ld, nstates, c->d_grad, false, table, 0, -1, 0);
+        if (!st)
+            st = do_project(c, psi, ld, nstates, c->d_grad, false, table == TAB_GRAD ? TAB_GRAD_DN : TAB_MOMENT_DN,
+                            0, -1, 1);
+    } else {
+        st = do_project(c, psi, ld, nstates, c->d_grad, false, table);
+    }
     if (st) return st;
     ForceArgs a{};
     a.c = cc;

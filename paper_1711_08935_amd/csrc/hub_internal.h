@@ -49,6 +49,7 @@ struct SiteSphere {
     std::vector<double> phi;     // [p][m]
     std::vector<double> grad;    // [p][m][3]
     std::vector<double> phi_dn;  // [p][m], spin-down orbitals (spin-dependent contexts)
+    std::vector<double> grad_dn; // [p][m][3], their gradients
 };
 
 // Largest number of functions (orbitals of all covering sites) a grouped
@@ -91,6 +92,7 @@ struct HostTables {
     // functions per cover as well.
     bool spindep = false;
     std::vector<double> phi2;
+    std::vector<double> gphi_dn, mphi_dn;    // per entry, 3L values [m][i] of the spin-down orbitals
     std::vector<int32_t> images;             // unique lattice images, 3 per image
     std::vector<int32_t> site_chunk_ptr;     // CSR site -> chunk ids
     std::vector<int32_t> site_chunk_ids;

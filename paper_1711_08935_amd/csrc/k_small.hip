@@ -27,6 +27,9 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
     const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
     const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     double s0 = 0.0, s1 = 0.0;
+    // gradient or moment tables of spin-dependent orbitals: one launch per
+    // spin component, each writing the columns of its component
+    if (a.colpar >= 0 && (col & 1) != a.colpar) return;
     // spin-dependent orbitals: column 2s + sigma of orbital m is the partial
     // row sigma L + m of the chunk (the orbital of its spin component)
     const int srow = a.spindep ? (col & 1) * a.site_L[site] + local : local;

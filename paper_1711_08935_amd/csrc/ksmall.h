@@ -10,6 +10,7 @@ struct ReduceArgs {
     int ncol; int ncplx; int mult;
     int pmult;                            // workspace rows per chunk orbital (mult, or 2: spin-dependent)
     int spindep;                          // 1: column 2s + sigma reads the rows of orbital sigma L + m
+    int colpar;                           // >= 0: write only the columns of this parity (spin component)
     const HubChunk* chunks;
     const int32_t* site_chunk_ptr; const int32_t* site_chunk_ids;
     const int32_t* orb_site; const int32_t* site_orb0; const int32_t* site_L;

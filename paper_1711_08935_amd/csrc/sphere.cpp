@@ -217,6 +217,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
         if (T.spindep) {
             const double zd = std::isfinite(S.zeta_dn) ? S.zeta_dn : S.zeta;
             sp.phi_dn.resize(np * L);
+            sp.grad_dn.resize(np * L * 3);
             std::vector<double> nd(L, 0.0);
             for (size_t p = 0; p < np; ++p) {
                 const Pt& q = P[p];
@@ -227,11 +228,18 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     const double chi = rad * Sv[m];
                     sp.phi_dn[p * L + m] = chi;
                     nd[m] += chi * chi;
+                    for (int i = 0; i < 3; ++i) {
+                        const double radial = (r > 0.0) ? zd * (q.d[i] / r) * Sv[m] : 0.0;
+                        sp.grad_dn[(p * L + m) * 3 + i] = rad * (dSv[3 * m + i] - radial);
+                    }
                 }
             }
             for (int m = 0; m < L; ++m) {
                 const double nm = 1.0 / std::sqrt(dV * nd[m]);
-                for (size_t p = 0; p < np; ++p) sp.phi_dn[p * L + m] *= nm;
+                for (size_t p = 0; p < np; ++p) {
+                    sp.phi_dn[p * L + m] *= nm;
+                    for (int i = 0; i < 3; ++i) sp.grad_dn[(p * L + m) * 3 + i] *= nm;
+                }
             }
         }
         for (size_t p = 0; p < np; ++p) {
@@ -332,6 +340,12 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     if (T.spindep) {
                         for (int m = 0; m < L; ++m) T.phi2.push_back(sp.phi[p * L + m]);
                         for (int m = 0; m < L; ++m) T.phi2.push_back(sp.phi_dn[p * L + m]);
+                        for (int m = 0; m < L; ++m)
+                            for (int i = 0; i < 3; ++i) {
+                                T.gphi_dn.push_back(sp.grad_dn[(p * L + m) * 3 + i]);
+                                const double di = static_cast<double>(sp.ijk[3 * p + i]) * h[i] - sites[s].R[i];
+                                T.mphi_dn.push_back(di * sp.phi_dn[p * L + m]);
+                            }
                     }
                     for (int m = 0; m < L; ++m)
                         for (int i = 0; i < 3; ++i) T.gphi.push_back(sp.grad[(p * L + m) * 3 + i]);
@@ -347,7 +361,11 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     T.gidx.push_back(T.gidx.back());
                     T.img.push_back(T.img.back());
                     T.phi.insert(T.phi.end(), L, 0.0);
-                    if (T.spindep) T.phi2.insert(T.phi2.end(), 2 * L, 0.0);
+                    if (T.spindep) {
+                        T.phi2.insert(T.phi2.end(), 2 * L, 0.0);
+                        T.gphi_dn.insert(T.gphi_dn.end(), 3 * L, 0.0);
+                        T.mphi_dn.insert(T.mphi_dn.end(), 3 * L, 0.0);
+                    }
                     T.gphi.insert(T.gphi.end(), 3 * L, 0.0);
                     T.mphi.insert(T.mphi.end(), 3 * L, 0.0);
                 }

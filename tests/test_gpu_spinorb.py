@@ -4,7 +4,8 @@ oracle.
 The noncollinear layered workload with a spin-down Slater exponent on every
 site (d: 2.0 -> 2.6, p: 1.4 -> 1.1) and a fixed U_eff per site, both storage
 precisions, both work lists: projections c^sigma = <phi^sigma|psi^sigma>,
-occupations, E_U, V_U psi, the batched, graph and per-site steps.  The oracle
+occupations, E_U, V_U psi, the batched, graph and per-site steps, the forces
+and the current.  The oracle
 projects and applies per spin component on the whole cell (its full-grid
 definitions).  Bars as in test_gpu_parity.py.  With zeta_dn = zeta the
 spin-dependent per-site kernels give results bitwise equal to the
@@ -61,7 +62,8 @@ def case(request):
     V = [POT.potential_matrix(sys_, UEFF, nn) for nn in n]
     ref = dict(c=cref, n=n, V=V, EU=np.array([POT.energy(sys_, UEFF, nn) for nn in n]),
                hpsi=SO.apply_spin(sys_, cref, V))
-    return dict(prec=prec, cfg=cfg, hub=hub, psi_d=psi_d, f=f, f_d=torch.from_numpy(f).cuda(), sys=sys_, ref=ref)
+    return dict(prec=prec, cfg=cfg, hub=hub, psi_d=psi_d, used=used, f=f, f_d=torch.from_numpy(f).cuda(), sys=sys_,
+                ref=ref)
 
 
 @pytest.mark.parametrize("grouped", [True, False], ids=["grouped", "persite"])
@@ -111,13 +113,33 @@ def test_steps(case):
     assert normwise(h.cpu().numpy(), ref["hpsi"]) < bar
 
 
-def test_no_forces_current_or_gauge(case):
+def test_forces_and_current(case):
+    """Forces through each component's orbital gradients and the current
+    through its position moments, against the oracle."""
+    from oracle import forces as OF
+    from oracle import gauge as GA
+    hub, ref, sys_ = case["hub"], case["ref"], case["sys"]
+    c = hub.project(case["psi_d"])
+    n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
+    ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
+    F = hub.forces(case["psi_d"], c, case["f_d"], ueff, n).cpu().numpy()
+    J = hub.current(case["psi_d"], c, case["f_d"], ueff, n).cpu().numpy()
+    torch.cuda.synchronize()
+    used = case["used"]
+    Fo = OF.forces_analytic(sys_, ref["c"], SO.gradient_projections_spin(sys_, used), ref["V"], case["f"])
+    Jo = GA.current(sys_, ref["c"], SO.moment_projections_spin(sys_, used), ref["V"], case["f"])
+    assert np.abs(Fo).max() > 1e-6 and np.abs(Jo).max() > 1e-8
+    assert normwise(F, Fo) < 1e-11
+    assert normwise(J, Jo) < 1e-11
+
+
+def test_no_state_gradient_forces_or_gauge(case):
     hub = case["hub"]
     c = hub.project(case["psi_d"])
     n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
     ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
     with pytest.raises(H.HubError):
-        hub.forces(case["psi_d"], c, case["f_d"], ueff, n)
+        hub.forces(case["psi_d"], c, case["f_d"], ueff, n, form="state")
     with pytest.raises(H.HubError):
         hub.set_vector_potential([0.1, 0.0, 0.0])
 
