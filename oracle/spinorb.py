@@ -93,3 +93,21 @@ def project_gauge_spin(system, psi, A):
     """c^A[k][j][s][sigma] with the orbital of each spin component."""
     from .gauge import project_gauge
     return _per_component(system, psi, lambda comp, x, sps: project_gauge(comp, x, sps, A))
+
+
+def apply_gauge_spin(system, c, V_list, A):
+    """V^A psi with the spin-dependent orbitals (gauge.py's apply, each
+    component scattered through its own orbital), from c = c^A."""
+    from .gauge import gauge_phase
+    B = coefficients(system, c, V_list)
+    out = np.zeros((system.nk, system.G) + c.shape[2:], dtype=np.complex128)
+    for sg, comp in enumerate(component_systems(system)):
+        sps = all_spheres(comp)
+        for ik in range(system.nk):
+            off = 0
+            for site, sp in zip(comp.sites, sps):
+                ph = np.conj(gauge_phase(comp, system.kpts[ik], site, sp, A))
+                blk = B[ik, off:off + site.L, :, sg]
+                np.add.at(out[ik, :, :, sg], sp.g, (sp.phi * ph[None, :]).T @ blk)
+                off += site.L
+    return out

@@ -455,6 +455,8 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         HUB_TRY(launch_reduce_grouped(r, nq, c->stream));
         return HUB_OK;
     }
+    // per-site chunks of spin-dependent orbitals have no velocity-gauge form
+    if (spindep && c->gauge) return HUB_ESTATE;
     int cpl = pick_cpl(c, psi, ld, 0);
     // gradient tiles hold 3L functions, spin-dependent tiles 2L
     if ((grad || spindep) && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();
@@ -637,6 +639,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     }
     int cpl = pick_cpl(c, hpsi, ld, 1);
     if (c->T.spindep) {
+        if (c->gauge) return HUB_ESTATE;       // no velocity-gauge form of these per-site chunks
         // 2L functions per entry: both spin components' orbitals
         a.tab = c->d_phi2;
         a.spindep = 1;
@@ -1266,8 +1269,6 @@ int hub_set_vector_potential(hub_ctx* c, const double* A) {
     if (!c) return HUB_EINVAL;
     if (A) {
         if (!c->is_complex) return HUB_EINVAL;
-        for (const SiteDef& sd : c->sites)
-            if (std::isfinite(sd.zeta_dn)) return HUB_EINVAL;    // no gauge form of spin-dependent orbitals
         for (int i = 0; i < 3; ++i)
             if (!std::isfinite(A[i])) return HUB_EINVAL;
     }

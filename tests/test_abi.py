@@ -148,7 +148,6 @@ def test_spin_orbital_arguments_and_host_tables():
     assert lib.hub_set_site_spin_orbital(ctx, 0, -1.0) == H.HUB_EINVAL
     assert lib.hub_set_site_spin_orbital(ctx, 0, float("nan")) == H.HUB_EINVAL
     assert lib.hub_set_site_spin_orbital(ctx, 0, 2.5) == H.HUB_OK
-    assert lib.hub_set_vector_potential(ctx, (ctypes.c_double * 3)(0.1, 0, 0)) == H.HUB_EINVAL
     assert lib.hub_finalize_host(ctx) == H.HUB_OK
     assert lib.hub_set_site_spin_orbital(ctx, 1, 2.5) == H.HUB_ESTATE                 # after build
     v = ctypes.c_int64()

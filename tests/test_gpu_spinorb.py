@@ -5,7 +5,7 @@ The noncollinear layered workload with a spin-down Slater exponent on every
 site (d: 2.0 -> 2.6, p: 1.4 -> 1.1) and a fixed U_eff per site, both storage
 precisions, both work lists: projections c^sigma = <phi^sigma|psi^sigma>,
 occupations, E_U, V_U psi, the batched, graph and per-site steps, the forces
-and the current.  The oracle
+and the current, and all of these under a vector potential.  The oracle
 projects and applies per spin component on the whole cell (its full-grid
 definitions).  Bars as in test_gpu_parity.py.  With zeta_dn = zeta the
 spin-dependent per-site kernels give results bitwise equal to the
@@ -133,15 +133,50 @@ def test_forces_and_current(case):
     assert normwise(J, Jo) < 1e-11
 
 
-def test_no_state_gradient_forces_or_gauge(case):
+def test_velocity_gauge(case):
+    """Under a field: c^A, V^A psi and the current against the oracle, and
+    the graph step follows the field; the per-site list has no gauge form."""
+    from oracle import gauge as GA
+    hub, sys_ = case["hub"], case["sys"]
+    A = np.array([0.137, -0.291, 0.083])
+    hub.set_vector_potential(A)
+    try:
+        c = hub.project(case["psi_d"])
+        n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
+        ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
+        h = torch.zeros_like(case["psi_d"])
+        hub.apply(ueff, n, c, h)
+        J = hub.current(case["psi_d"], c, case["f_d"], ueff, n).cpu().numpy()
+        bufs = hub.step_buffers(case["cfg"].nstates)
+        hg = torch.zeros_like(case["psi_d"])
+        hub.step(case["psi_d"], case["f_d"], hg, mode="graph", bufs=bufs)
+        torch.cuda.synchronize()
+        hub.set_worklist(False)
+        with pytest.raises(H.HubError):
+            hub.project(case["psi_d"])
+    finally:
+        hub.set_worklist(True)
+        hub.set_vector_potential(None)
+    used, f = case["used"], case["f"]
+    cA = SO.project_gauge_spin(sys_, used, A)
+    assert normwise(c_to_oracle(hub, c), cA) < 1e-12
+    nA, _, _ = OCC.occupations(sys_, cA, f, with_pbar=False)
+    V = [POT.potential_matrix(sys_, UEFF, nn) for nn in nA]
+    href = SO.apply_gauge_spin(sys_, cA, V, A)
+    bar = 1e-12 if case["prec"] == "f64" else 2e-7
+    assert normwise(h.cpu().numpy(), href) < bar
+    assert normwise(hg.cpu().numpy(), href) < bar
+    Jo = GA.current(sys_, cA, SO.moment_projections_spin(sys_, used, A), V, f)
+    assert normwise(J, Jo) < 1e-11
+
+
+def test_no_state_gradient_forces(case):
     hub = case["hub"]
     c = hub.project(case["psi_d"])
     n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
     ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
     with pytest.raises(H.HubError):
         hub.forces(case["psi_d"], c, case["f_d"], ueff, n, form="state")
-    with pytest.raises(H.HubError):
-        hub.set_vector_potential([0.1, 0.0, 0.0])
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -165,3 +165,30 @@ def test_current_is_field_derivative():
             fd = (site_e(cp, I) - site_e(cm, I)) / (2 * delta)
             assert abs(J[I, i] - fd) < 1e-7 * np.abs(J).max(), (I, i)
     assert np.abs(J).max() > 1e-4
+
+
+def _grid_r(sys_):
+    h = np.asarray(sys_.cell) / np.asarray(sys_.ngrid)
+    ix, iy, iz = np.meshgrid(*[np.arange(n) for n in sys_.ngrid], indexing="ij")
+    return np.stack([ix.ravel() * h[0], iy.ravel() * h[1], iz.ravel() * h[2]], axis=1)
+
+
+def test_gauge_forms():
+    """A = 0 gives the plain spin-dependent forms; for any A the gauge
+    projection and apply are the plain ones at k + A of exp(i A.r) psi."""
+    sys_ = _system()
+    psi = _states(sys_, 3, 15)
+    f = np.random.default_rng(16).uniform(0.0, 1.0, size=(sys_.nk, 3))
+    c0 = SO.project_spin(sys_, psi, form="sphere")
+    V, _ = _V(sys_, c0, f)
+    assert normwise(SO.project_gauge_spin(sys_, psi, np.zeros(3)), c0) < 1e-14
+    assert normwise(SO.apply_gauge_spin(sys_, c0, V, np.zeros(3)), SO.apply_spin(sys_, c0, V, form="sphere")) < 1e-14
+    A = np.array([0.137, -0.291, 0.083])
+    dk = A * np.asarray(sys_.cell) / (2 * np.pi)
+    sh = System(cell=sys_.cell, ngrid=sys_.ngrid, sites=sys_.sites, kpts=np.asarray(sys_.kpts) + dk[None, :],
+                kweights=sys_.kweights, spin="spinor")
+    mod = np.exp(1j * (_grid_r(sys_) @ A))[None, :, None, None]
+    cA = SO.project_gauge_spin(sys_, psi, A)
+    assert normwise(cA, SO.project_spin(sh, psi * mod, form="sphere")) < 1e-13
+    VA, _ = _V(sys_, cA, f)
+    assert normwise(SO.apply_gauge_spin(sys_, cA, VA, A) * mod, SO.apply_spin(sh, cA, VA, form="sphere")) < 1e-13
