@@ -131,11 +131,10 @@ int hub_sphere_radius(int method, int l, double zeta, const double cell[3], doub
  * contexts only, before hub_finalize*.  Both work lists then carry the two
  * spin components' orbitals (2L functions per cover).  Such sites take a
  * fixed U_eff (hub_set_fixed_ueff; hub_coulomb skips them and rejects them
- * by index).  hub_forces and hub_current use each component's orbital
- * gradients and position moments.  Under a vector potential the grouped
- * work list serves the projections and the apply (the per-site list then
- * returns HUB_ESTATE); the state-gradient forces are not available in such
- * a context (HUB_ESTATE).  Errors: HUB_EINVAL (bad site, zeta_dn not positive and
+ * by index).  hub_forces, hub_forces_state_gradient and hub_current use
+ * each component's orbital gradients, differences and position moments.
+ * Under a vector potential the grouped work list serves the projections and
+ * the apply (the per-site list then returns HUB_ESTATE).  Errors: HUB_EINVAL (bad site, zeta_dn not positive and
  * finite, not a spinor context), HUB_ESTATE (after finalize). */
 int hub_set_site_spin_orbital(hub_ctx* ctx, int site, double zeta_dn);
 

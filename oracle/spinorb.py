@@ -111,3 +111,9 @@ def apply_gauge_spin(system, c, V_list, A):
                 np.add.at(out[ik, :, :, sg], sp.g, (sp.phi * ph[None, :]).T @ blk)
                 off += site.L
     return out
+
+
+def state_gradient_projections_spin(system, psi):
+    """e[k][j][i][s][sigma] = <phi^sigma_j|D_i psi^sigma_s> (stencil.py form)."""
+    from .stencil import state_gradient_projections
+    return _per_component(system, psi, state_gradient_projections)

@@ -101,6 +101,7 @@ struct hub_ctx {
     HubChunk* d_st_chunks = nullptr;
     int32_t *d_st_all = nullptr, *d_st_gidx = nullptr, *d_st_site_ptr = nullptr, *d_st_site_ids = nullptr;
     double* d_st_tab = nullptr;
+    double* d_st_tab_dn = nullptr;           // spin-down orbitals (spin-dependent contexts)
     double* d_nbar_ws = nullptr;
     size_t nbar_cap = 0;
 
@@ -159,7 +160,7 @@ void release(hub_ctx* c) {
     f(c->d_pg); f(c->d_mphi); f(c->d_images); f(c->d_kred);
     c->d_pg = nullptr;
     f(c->d_phi2); f(c->d_gphi_dn); f(c->d_mphi_dn);
-    f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab);
+    f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab); f(c->d_st_tab_dn);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -329,7 +330,9 @@ int run_classes(hub_ctx* c, F&& launch, bool per_pass = false) {
 // moments about the site centre (velocity-gauge current) or the 4th-order
 // differences of the orbitals on the dilated spheres (state-gradient forces,
 // a work list of its own).
-enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2, TAB_STENCIL = 3, TAB_GRAD_DN = 4, TAB_MOMENT_DN = 5 };
+enum { TAB_PHI = 0, TAB_GRAD = 1, TAB_MOMENT = 2, TAB_STENCIL = 3, TAB_GRAD_DN = 4, TAB_MOMENT_DN = 5,
+       TAB_STENCIL_DN = 6 };
+bool stencil_table(int table) { return table == TAB_STENCIL || table == TAB_STENCIL_DN; }
 
 ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table) {
     const bool grad = table != TAB_PHI;
@@ -353,11 +356,11 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table)
         a.tabmult = 2;
     }
     a.prows = c->T.part_rows * a.tabmult;
-    if (table == TAB_STENCIL) {
+    if (stencil_table(table)) {
         a.chunks = c->d_st_chunks;
         a.chunk_list = c->d_st_all;
         a.gidx = c->d_st_gidx;
-        a.tab = c->d_st_tab;
+        a.tab = table == TAB_STENCIL ? c->d_st_tab : c->d_st_tab_dn;
         a.prows = c->stencil_part_rows * 3;
     }
     a.pg = c->gauge ? c->d_pg : nullptr;
@@ -465,7 +468,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     {
     StageTimer tm(c, grad ? HUB_STAGE_GRADPROJ : HUB_STAGE_PROJECT);
     if (!per_site) {
-        const int nch = table == TAB_STENCIL ? c->stencil_nchunks : static_cast<int>(c->T.chunks.size());
+        const int nch = stencil_table(table) ? c->stencil_nchunks : static_cast<int>(c->T.chunks.size());
         HUB_TRY(launch_project(a, nch, nq, c->precision, c->is_complex, cpl, waves, 0, c->stream));
     } else {
         for (int s = 0; s < c->T.nsites; ++s) {
@@ -485,7 +488,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         r.spindep = 1;
         r.prows = c->T.part_rows * 2;
     }
-    if (table == TAB_STENCIL) {
+    if (stencil_table(table)) {
         r.chunks = c->d_st_chunks;
         r.site_chunk_ptr = c->d_st_site_ptr;
         r.site_chunk_ids = c->d_st_site_ids;
@@ -1144,7 +1147,6 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
                      const double* Ueff, const double* n, double* out, int table) {
     if (!c || !cc || !f || !Ueff || !n || !out) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
-    if (c->T.spindep && table == TAB_STENCIL) return HUB_ESTATE;   // no dilated tables per spin
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
     const int ncol = c->ncol(nstates);
     const size_t need = static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx();
@@ -1153,10 +1155,9 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
     if (c->T.spindep) {
         // spin-dependent orbitals: the spin-up tables give the even columns,
         // the spin-down tables the odd ones
+        const int dn = table == TAB_GRAD ? TAB_GRAD_DN : (table == TAB_MOMENT ? TAB_MOMENT_DN : TAB_STENCIL_DN);
         st = do_project(c, psi, ld, nstates, c->d_grad, false, table, 0, -1, 0);
-        if (!st)
-            st = do_project(c, psi, ld, nstates, c->d_grad, false, table == TAB_GRAD ? TAB_GRAD_DN : TAB_MOMENT_DN,
-                            0, -1, 1);
+        if (!st) st = do_project(c, psi, ld, nstates, c->d_grad, false, dn, 0, -1, 1);
     } else {
         st = do_project(c, psi, ld, nstates, c->d_grad, false, table);
     }
@@ -1223,7 +1224,8 @@ int build_stencil(hub_ctx* c) {
     // a failed earlier attempt may have left some of the tables allocated
     for (void** p : {reinterpret_cast<void**>(&c->d_st_chunks), reinterpret_cast<void**>(&c->d_st_all),
                      reinterpret_cast<void**>(&c->d_st_gidx), reinterpret_cast<void**>(&c->d_st_tab),
-                     reinterpret_cast<void**>(&c->d_st_site_ptr), reinterpret_cast<void**>(&c->d_st_site_ids)}) {
+                     reinterpret_cast<void**>(&c->d_st_site_ptr), reinterpret_cast<void**>(&c->d_st_site_ids),
+                     reinterpret_cast<void**>(&c->d_st_tab_dn)}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -1234,6 +1236,7 @@ int build_stencil(hub_ctx* c) {
     HUB_TRY(upload(&c->d_st_tab, S.tab, bytes));
     HUB_TRY(upload(&c->d_st_site_ptr, S.site_chunk_ptr, bytes));
     HUB_TRY(upload(&c->d_st_site_ids, S.site_chunk_ids, bytes));
+    if (c->T.spindep) HUB_TRY(upload(&c->d_st_tab_dn, S.tab_dn, bytes));
     c->table_bytes += bytes;
     c->stencil_nchunks = static_cast<int>(S.chunks.size());
     c->stencil_part_rows = S.part_rows;

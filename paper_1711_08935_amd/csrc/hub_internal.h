@@ -120,6 +120,7 @@ struct StencilTables {
     std::vector<HubChunk> chunks;            // site-major, then image, g ascending
     std::vector<int32_t> gidx;               // per entry
     std::vector<double> tab;                 // per entry, 3L values [m][i]
+    std::vector<double> tab_dn;              // the same for the spin-down orbitals (spin-dependent contexts)
     std::vector<int32_t> site_chunk_ptr;     // CSR site -> chunk ids
     std::vector<int32_t> site_chunk_ids;
     int64_t part_rows = 0;                   // sum of L over chunks

@@ -640,7 +640,7 @@ int hub_build_stencil(const double cell[3], const int ngrid[3], const std::vecto
         std::sort(pts.begin(), pts.end(),
                   [](const DPt& a, const DPt& b) { return std::tie(a.img, a.g) < std::tie(b.img, b.g); });
         // (D_i phi_m)(n) = sum_o w_o phi_m(n + o e_i) / h_i, phi zero off the sphere
-        auto table_row = [&](const DPt& q, std::vector<double>& tab) {
+        auto table_row = [&](const DPt& q, const std::vector<double>& phi, std::vector<double>& tab) {
             const int64_t j[3] = {q.x, q.y, q.z};
             for (int m = 0; m < L; ++m)
                 for (int i = 0; i < 3; ++i) {
@@ -650,7 +650,7 @@ int hub_build_stencil(const double cell[3], const int ngrid[3], const std::vecto
                         n[i] += kOff[o];
                         if (n[i] < lo[i] || n[i] > hi[i]) continue;
                         const int32_t p = at[cell_of(n[0], n[1], n[2])];
-                        if (p >= 0) acc += kW[o] * sp.phi[static_cast<size_t>(p) * L + m];
+                        if (p >= 0) acc += kW[o] * phi[static_cast<size_t>(p) * L + m];
                     }
                     tab.push_back(acc / h[i]);
                 }
@@ -674,11 +674,13 @@ int hub_build_stencil(const double cell[3], const int ngrid[3], const std::vecto
             C.nreal = static_cast<int32_t>(n);
             for (size_t t = 0; t < n; ++t) {
                 S.gidx.push_back(pts[b + t].g);
-                table_row(pts[b + t], S.tab);
+                table_row(pts[b + t], sp.phi, S.tab);
+                if (T.spindep) table_row(pts[b + t], sp.phi_dn, S.tab_dn);
             }
             for (size_t t = n; t < npad; ++t) {
                 S.gidx.push_back(S.gidx.back());
                 S.tab.insert(S.tab.end(), 3 * L, 0.0);
+                if (T.spindep) S.tab_dn.insert(S.tab_dn.end(), 3 * L, 0.0);
             }
             S.site_chunk_ids.push_back(static_cast<int32_t>(S.chunks.size()));
             S.chunks.push_back(C);

@@ -4,8 +4,8 @@ oracle.
 The noncollinear layered workload with a spin-down Slater exponent on every
 site (d: 2.0 -> 2.6, p: 1.4 -> 1.1) and a fixed U_eff per site, both storage
 precisions, both work lists: projections c^sigma = <phi^sigma|psi^sigma>,
-occupations, E_U, V_U psi, the batched, graph and per-site steps, the forces
-and the current, and all of these under a vector potential.  The oracle
+occupations, E_U, V_U psi, the batched, graph and per-site steps, both
+force forms and the current, and the gauge forms under a vector potential.  The oracle
 projects and applies per spin component on the whole cell (its full-grid
 definitions).  Bars as in test_gpu_parity.py.  With zeta_dn = zeta the
 spin-dependent per-site kernels give results bitwise equal to the
@@ -170,13 +170,18 @@ def test_velocity_gauge(case):
     assert normwise(J, Jo) < 1e-11
 
 
-def test_no_state_gradient_forces(case):
-    hub = case["hub"]
+def test_state_gradient_forces(case):
+    """Forces through <phi^sigma|D psi^sigma> against the oracle."""
+    from oracle import stencil as SG
+    hub, ref, sys_ = case["hub"], case["ref"], case["sys"]
     c = hub.project(case["psi_d"])
     n, _, _ = hub.occupations(c, case["f_d"], with_pbar=False)
     ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
-    with pytest.raises(H.HubError):
-        hub.forces(case["psi_d"], c, case["f_d"], ueff, n, form="state")
+    F = hub.forces(case["psi_d"], c, case["f_d"], ueff, n, form="state").cpu().numpy()
+    e = SO.state_gradient_projections_spin(sys_, case["used"])
+    Fo = SG.forces_state_gradient(sys_, ref["c"], e, ref["V"], case["f"])
+    assert np.abs(Fo).max() > 1e-6
+    assert normwise(F, Fo) < 1e-11
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

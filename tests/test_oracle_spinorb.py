@@ -192,3 +192,24 @@ def test_gauge_forms():
     assert normwise(cA, SO.project_spin(sh, psi * mod, form="sphere")) < 1e-13
     VA, _ = _V(sys_, cA, f)
     assert normwise(SO.apply_gauge_spin(sys_, cA, VA, A) * mod, SO.apply_spin(sh, cA, VA, form="sphere")) < 1e-13
+
+
+def test_state_gradient_projections():
+    """Equal exponents give stencil.py's spinor result; a state with only a
+    spin-down component projects like a one-component state onto the
+    spin-down orbital."""
+    from oracle import stencil as SG
+    same = _system(zdn=(1.6, 1.3))
+    psi = _states(same, 3, 17)
+    e = SO.state_gradient_projections_spin(same, psi)
+    assert normwise(e, SG.state_gradient_projections(same, psi, P.all_spheres(same))) < 1e-13
+    sys_ = _system()
+    psi[..., 0] = 0.0
+    e = SO.state_gradient_projections_spin(sys_, psi)
+    assert np.all(e[..., 0] == 0.0)
+    one = System(cell=sys_.cell, ngrid=sys_.ngrid,
+                 sites=[Site(R=s.R, l=s.l, zeta=s.zeta_dn if s.zeta_dn is not None else s.zeta, rc=s.rc,
+                             species=s.species) for s in sys_.sites],
+                 kpts=sys_.kpts, kweights=sys_.kweights, spin="unpolarized")
+    ref = SG.state_gradient_projections(one, psi[..., 1], P.all_spheres(one))
+    assert normwise(e[..., 1], ref) < 1e-13
