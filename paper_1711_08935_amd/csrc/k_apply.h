@@ -11,8 +11,9 @@
 // so its phase is folded into B_f once per chunk.
 // The host groups entries in layers that never repeat a grid point and
 // launches one layer at a time (or, with the grouped work list, puts every
-// grid point in one chunk with all its covering functions), so no two lanes
-// in flight update the same element: no atomics, deterministic results.
+// grid point in one chunk per pass with the covering functions of that pass
+// and launches the passes one at a time), so no two lanes in flight update
+// the same element: no atomics, deterministic results.
 // Sums are FP64; the updated element is rounded once to the storage type.
 // Velocity gauge (GAUGE, Sec. V): the entry's update is rotated by the
 // conjugate grid-point phase exp(-i A.r_g); the image part of the field's
