@@ -9,7 +9,7 @@ simulation cell, and the radius at which the radial part of the orbital
 drops below a threshold.
 
 Readings (the paper gives no formulas):
-* "smallest dimension of the cell" is the shortest cell edge, min_i a_i
+* the smallest dimension of the cell is the shortest cell edge, min_i a_i
   (orthorhombic cells), so a sphere may reach its own periodic images;
 * the radial part is the continuum-normalized Slater function
   R(r) = N r^l exp(-zeta r), N = sqrt((2 zeta)^(2l+3) / (2l+2)!), so that
