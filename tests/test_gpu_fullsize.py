@@ -3,8 +3,10 @@ times (default chunking, kernel shapes picked by the autotuner, the step run
 as a hipGraph).  The oracle runs on the states the device holds (the FP32
 storage rounded states, upcast).  Where the oracle can compute every output
 in seconds it does (NiO-like workload: all projections, matrices, U, J and
-V_U psi; forces workload: all forces of the orbital-gradient form, and the
-state-gradient form on sampled states); for the 1024-state batched workload it
+V_U psi; noncollinear workload: every projection and matrix, V_U psi on
+sampled states; forces workload: all forces of the orbital-gradient form, and
+the state-gradient form on sampled states); for the 1024-state batched
+workload it
 checks every projection and matrix and V_U psi on sampled state columns.
 """
 
@@ -142,6 +144,33 @@ def test_nio_full_size_large_spheres_in_passes():
     cols = np.sort(np.random.default_rng(2).choice(cfg.nstates, size=8, replace=False))
     h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
     h = hpsi[:, :, torch.from_numpy(cols).cuda()].cpu().numpy()
+    assert normwise(h, h_ref) < 2e-7
+
+
+@pytest.mark.timeout(900)
+def test_spinor_layers_full_size():
+    """Noncollinear spinors at full size (4 k-points, 256 two-component
+    states): every projection, the 2L x 2L occupation blocks, U and J, and
+    V_U psi on sampled states."""
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("spinor_layers", "f32")
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    used = psi.cpu().numpy().astype(np.complex128)
+    used = used.reshape(used.shape[0], used.shape[1], -1, 2)
+    c = OP.project_sphere(sys_, used, sps)
+    assert normwise(c_to_oracle(hub, bufs["c"]), c) < 1e-12
+    n, pbar, nb = OO.occupations(sys_, c, f)
+    tens = OS.site_tensors(sys_, sps)
+    ref = dict(n=n, pbar=pbar, nbar=nb, U=np.zeros(len(sps)), J=np.zeros(len(sps)))
+    from oracle import acbn0
+    for I in range(len(sps)):
+        U, J, _, _ = acbn0.uj_spinor(n[I], pbar[I], tens[I])
+        ref["U"][I], ref["J"][I] = U, J
+    _compare_matrices(hub, bufs, ref)
+    V = [OPOT.potential_matrix(sys_, ref["U"][I] - ref["J"][I], n[I]) for I in range(len(sps))]
+    cols = np.sort(np.random.default_rng(3).choice(cfg.nstates, size=8, replace=False))
+    h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
+    h = hpsi.cpu().numpy().reshape(hpsi.shape[0], hpsi.shape[1], -1, 2)[:, :, cols]
     assert normwise(h, h_ref) < 2e-7
 
 
