@@ -6,8 +6,8 @@ in seconds it does (NiO-like workload: all projections, matrices, U, J and
 V_U psi; noncollinear workload: every projection and matrix, V_U psi on
 sampled states; forces workload: all forces of the orbital-gradient form, and
 the state-gradient form on sampled states); for the 1024-state batched
-workload it
-checks every projection and matrix and V_U psi on sampled state columns.
+workload it checks every projection and matrix and V_U psi on sampled state
+columns.
 """
 
 import numpy as np
