@@ -2,9 +2,10 @@
 grid points are covered by more than 16 orbitals (through several sites and
 their periodic images), so the grouped apply runs in passes.
 
-NiO-like collinear k-point states with the Ni d radius at 6 bohr (3 passes)
-and the real Gamma-point d shell with r_c = 9 bohr in a 10 bohr cell (its own
-images overlap), both storage precisions, U_eff fixed: projections and
+NiO-like collinear k-point states with the Ni d radius at 6 bohr (3 passes),
+the real Gamma-point d shell with r_c = 9 bohr in a 10 bohr cell (its own
+images overlap) and the noncollinear layers with every radius at 6 bohr
+(2 passes), both storage precisions, U_eff fixed: projections and
 V_U psi against the oracle (full-cell definitions), the per-site work list
 and the graph step.  Bars as in test_gpu_parity.py.
 """
@@ -27,7 +28,8 @@ from tests.gpu_common import c_to_oracle, device_states, states_and_occupations 
 from tests.helpers import normwise, to_system  # noqa: E402
 
 UEFF = 0.15
-CASES = [("nio_afm", 6.0, "f64"), ("nio_afm", 6.0, "f32"), ("gamma_d", 9.0, "f64"), ("gamma_d", 9.0, "f32")]
+CASES = [("nio_afm", 6.0, "f64"), ("nio_afm", 6.0, "f32"), ("gamma_d", 9.0, "f64"), ("gamma_d", 9.0, "f32"),
+         ("spinor_layers", 6.0, "f64"), ("spinor_layers", 6.0, "f32")]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[f"{a}-rc{b}-{c}" for a, b, c in CASES])
@@ -35,7 +37,8 @@ def case(request):
     name, rc, prec = request.param
     print(f"\n[passes case] {name} rc={rc} {prec}", flush=True)
     cfg = make_config(name, small=True)
-    cfg.sites = [dict(s, rc=rc) if s["l"] == 2 else s for s in cfg.sites]
+    every = name == "spinor_layers"
+    cfg.sites = [dict(s, rc=rc) if (every or s["l"] == 2) else s for s in cfg.sites]
     psi, f = states_and_occupations(cfg)
     hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
                     is_complex=cfg.is_complex, precision=prec, chunk=256)
