@@ -6,8 +6,10 @@
 // comparison with the oracle's -<phi|D psi>.
 //
 // Input (binary, native endianness): cell[3] f64, ngrid[3] i32, nsites i32,
-// per site {R[3] f64, l i32, zeta f64, rc f64, species i32}, k_red[3] f64,
-// nstates i32, psi[G][nstates] complex f64.  Output: d as complex f64.
+// per site {R[3] f64, l i32, zeta f64, rc f64, species i32, zeta_dn f64
+// (NaN: none)}, k_red[3] f64, nstates i32, psi[G][nstates] complex f64.
+// Output: d as complex f64, then (if some site has a spin-down exponent) the
+// same sum over the spin-down orbitals' table.
 // Exit status 0 (ok), 1 (bad input or builder error), 2 (an index out of range).
 #include <cmath>
 #include <complex>
@@ -31,9 +33,8 @@ int main(int argc, char** argv) {
     std::vector<SiteDef> sites(ok ? ns : 0);
     for (auto& s : sites) {
         ok = ok && get(f, s.R, 3) && get(f, &s.l, 1) && get(f, &s.zeta, 1) && get(f, &s.rc, 1) &&
-             get(f, &s.species, 1);
+             get(f, &s.species, 1) && get(f, &s.zeta_dn, 1);
         s.ueff_fixed = NAN;
-        s.zeta_dn = NAN;
     }
     ok = ok && get(f, k, 3) && get(f, &S, 1) && S > 0;
     const long G = static_cast<long>(ngrid[0]) * ngrid[1] * ngrid[2];
@@ -60,11 +61,17 @@ int main(int argc, char** argv) {
             tab_used += static_cast<long>(C.ne) * C.L;
         }
     for (int g : X.gidx) bad += g < 0 || g >= G;
+    bad += T.spindep ? X.tab_dn.size() != X.tab.size() : !X.tab_dn.empty();
     std::printf("chunks %zu entries %ld sphere_entries %ld images %ld bad %ld\n", X.chunks.size(),
                 static_cast<long>(X.nentries), static_cast<long>(T.nentries), nimg, bad);
     if (bad) return 2;
 
     const double dV = cell[0] / ngrid[0] * cell[1] / ngrid[1] * cell[2] / ngrid[2];
+    FILE* o = std::fopen(argv[2], "wb");
+    if (!o) return 1;
+    bool wrote = true;
+    for (const std::vector<double>* tab : {&X.tab, &X.tab_dn}) {
+    if (tab->empty()) continue;
     std::vector<std::complex<double>> d(static_cast<size_t>(T.J) * 3 * S);
     for (const HubChunk& C : X.chunks) {
         const int32_t* im = &T.images[3 * C.img];
@@ -73,14 +80,13 @@ int main(int argc, char** argv) {
         for (int e = 0; e < C.ne; ++e) {
             const long g = X.gidx[C.e0 + e];
             for (int fn = 0; fn < 3 * C.L; ++fn) {
-                const double w = X.tab[(C.phi0 + static_cast<long>(e) * C.L) * 3 + fn];
+                const double w = (*tab)[(C.phi0 + static_cast<long>(e) * C.L) * 3 + fn];
                 for (int c = 0; c < S; ++c) d[(static_cast<size_t>(C.orb0) * 3 + fn) * S + c] += dV * ph * w * psi[g * S + c];
             }
         }
     }
-    FILE* o = std::fopen(argv[2], "wb");
-    if (!o) return 1;
-    const bool wrote = std::fwrite(d.data(), sizeof(d[0]), d.size(), o) == d.size();
+    wrote = wrote && std::fwrite(d.data(), sizeof(d[0]), d.size(), o) == d.size();
+    }
     std::fclose(o);
     return wrote ? 0 : 1;
 }

@@ -6,7 +6,8 @@ buffer and sums the dilated-sphere table against the states as the
 projection kernels do.  The result must equal the oracle's -<phi|D psi>
 (4th-order differences of the states, then the plain sphere projection):
 spheres that reach past half the cell, sites next to the cell faces, an s
-shell next to p/d/f shells, generic k-points."""
+shell next to p/d/f shells, generic k-points, and the spin-down orbitals'
+table of a context with spin-dependent orbitals."""
 
 import os
 import shutil
@@ -30,6 +31,8 @@ CASES = [
     ([5.0, 5.0, 5.0], [10, 10, 10], [Site(R=[0.0, 0.0, 0.0], l=3, zeta=1.2, rc=4.1),
                                      Site(R=[2.5, 4.99, 0.01], l=0, zeta=1.0, rc=1.3, species=1)], [0.1, 0.37, -0.2]),
     ([8.0, 8.0, 8.0], [40, 40, 40], [Site(R=[0.05, 7.97, 4.0], l=2, zeta=1.6, rc=2.0)], [0.0, 0.0, 0.0]),
+    ([6.0, 6.5, 7.0], [12, 13, 14], [Site(R=[0.3, 6.2, 3.3], l=2, zeta=1.6, rc=3.4, zeta_dn=2.3),
+                                     Site(R=[3.1, 3.0, 0.5], l=1, zeta=1.3, rc=2.8, species=1)], [0.25, -0.25, 0.5]),
 ]
 
 
@@ -57,12 +60,22 @@ def test_stencil_tables_match_oracle(checker, tmp_path, case):
         f.write(struct.pack("3d", *cell) + struct.pack("3i", *ngrid) + struct.pack("i", len(sites)))
         for s in sites:
             f.write(struct.pack("3d", *s.R) + struct.pack("i", s.l) + struct.pack("2d", s.zeta, s.rc) +
-                    struct.pack("i", s.species))
+                    struct.pack("i", s.species) +
+                    struct.pack("d", s.zeta_dn if s.zeta_dn is not None else float("nan")))
         f.write(struct.pack("3d", *k) + struct.pack("i", S))
         f.write(np.ascontiguousarray(psi[0]).tobytes())
     r = subprocess.run([checker, str(inp), str(out)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     J = sum(s.L for s in sites)
-    d = np.fromfile(out, dtype=np.complex128).reshape(J, 3, S)
+    dd = np.fromfile(out, dtype=np.complex128)
+    spin = any(s.zeta_dn is not None for s in sites)
+    dd = dd.reshape((2 if spin else 1), J, 3, S)
     e = SG.state_gradient_projections(sys_, psi, P.all_spheres(sys_))[0]
-    assert normwise(d, -e) < 1e-13
+    assert normwise(dd[0], -e) < 1e-13
+    if spin:
+        # the spin-down table: the same sum over the spin-down orbitals
+        dn = System(cell=cell, ngrid=ngrid, kpts=np.array([k]), kweights=np.ones(1), spin="unpolarized",
+                    sites=[Site(R=s.R, l=s.l, zeta=(s.zeta_dn if s.zeta_dn is not None else s.zeta), rc=s.rc,
+                                species=s.species) for s in sites])
+        e_dn = SG.state_gradient_projections(dn, psi, P.all_spheres(dn))[0]
+        assert normwise(dd[1], -e_dn) < 1e-13
