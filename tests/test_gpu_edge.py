@@ -107,6 +107,22 @@ def test_argument_errors_raise_before_launch():
     assert e.value.code == H.HUB_ESTATE
     rc = H.lib().hub_project(hub._ctx, psi.data_ptr(), 2, 4, psi.data_ptr())   # ld < nstates
     assert rc == H.HUB_EINVAL
+    lib = H.lib()
+    p = psi.data_ptr()
+    assert lib.hub_project(hub._ctx, p, 4, 0, p) == H.HUB_EINVAL                   # no states
+    assert lib.hub_project(hub._ctx, None, 4, 4, p) == H.HUB_EINVAL
+    assert lib.hub_project_sets(hub._ctx, p, 4, 4, -1, 1, p) == H.HUB_EINVAL      # set range
+    assert lib.hub_project_sets(hub._ctx, p, 4, 4, 0, 0, p) == H.HUB_EINVAL
+    assert lib.hub_project_sets(hub._ctx, p, 4, 4, 1, cfg.nq, p) == H.HUB_EINVAL
+    assert lib.hub_apply(hub._ctx, p, p, p, 4, None, float("nan"), p, 4) == H.HUB_EINVAL   # alpha
+    assert lib.hub_apply_sets(hub._ctx, p, p, p, 4, None, 1.0, p, 4, cfg.nq, 1) == H.HUB_EINVAL
+    assert lib.hub_forces(hub._ctx, p, 4, 0, p, p, p, p, p) == H.HUB_EINVAL
+    assert lib.hub_current(hub._ctx, None, 4, 4, p, p, p, p, p) == H.HUB_EINVAL
+    assert lib.hub_forces_state_gradient(hub._ctx, p, 2, 4, p, p, p, p, p) == H.HUB_EINVAL
+    assert lib.hub_energy_fll(hub._ctx, None, p, p, p) == H.HUB_EINVAL
+    for A in ([float("nan"), 0.0, 0.0], [0.0, float("inf"), 0.0]):
+        with pytest.raises(H.HubError):
+            hub.set_vector_potential(A)
 
 
 @pytest.mark.parametrize("fixed", [False, True])
