@@ -480,6 +480,23 @@ def main():
         log(f"f64 plain per-site: {plain:.1f} steps/s, f64 graph: {g64:.1f} steps/s")
         detail.update(fp64_plain_steps_per_s=round(plain, 2), fp64_graph_steps_per_s=round(g64, 2),
                       speedup_vs_fp64_plain=round(value / plain, 3))
+        # where the speedup comes from: the FP64 paths' projection and apply
+        # time per step against the same union-point bytes at FP64 storage
+        esz64 = psi64.element_size()
+        bytes64 = {"project": U_pts * ncol * esz64 * hub64.nsets, "apply": 2 * U_pts * ncol * esz64 * hub64.nsets}
+        for tag, mode in (("fp64_plain_stages", "persite"), ("fp64_batched_stages", "batched")):
+            hub64.profile(True)
+            for _ in range(k64):
+                hub64.step(psi64, f_d, hpsi64, mode=mode, bufs=bufs64)
+            pr = hub64.profile_read()
+            hub64.profile(False)
+            rates = {}
+            for k, b in bytes64.items():
+                ms = pr[k][0] / k64
+                rates[f"{k}_ms_per_step"] = round(ms, 4)
+                rates[f"{k}_launches_per_step"] = pr[k][1] // k64
+                rates[f"{k}_frac"] = round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+            detail[tag] = rates
         # accuracy: one step of each path on the current master states
         b32 = hub32.step(psi32, f_d, torch.zeros_like(psi32), mode="batched", bufs=hub32.step_buffers(S))
         b64 = hub64.step(psi64, f_d, torch.zeros_like(psi64), mode="batched", bufs=hub64.step_buffers(S))
