@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time only the FP32 graph path")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-single-thread", action="store_true",
+                    help="also time one oracle step on one host thread")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--chunk", type=int, default=None, help="sphere entries per work-list chunk")
     ap.add_argument("--classes", default="merged", choices=["merged", "sequential", "concurrent"],
@@ -132,6 +134,32 @@ def cpu_baseline(cfg, psi_host, f, nsteps):
         log(f"oracle step {i}: {times[-1]:.2f} s")
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return statistics.median(times), threads
+
+
+def cpu_single_thread(cfg, psi_host, f):
+    """One oracle step with the BLAS pools held to one thread, and the host
+    it ran on."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import projection as OP
+    from oracle import step as OS
+    from tests.helpers import to_system
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    tens = OS.site_tensors(sys_, sps)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        OS.hubbard_step(sys_, psi_host, f, sps, tens, form="sphere")
+        t = time.perf_counter() - t0
+    log(f"oracle step, one thread: {t:.2f} s")
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"oracle_single_thread_steps_per_s": round(1.0 / t, 4), "host_cpu": model,
+            "host_cpus_visible": os.cpu_count()}
 
 
 def rc_sweep(args):
@@ -520,6 +548,8 @@ def main():
         cpu = {"value": round(1.0 / t_step, 4), "unit": "Hubbard steps/s", "cores": threads, "kind": "oracle",
                "sample": f"median of {args.cpu_steps} whole FP64 oracle steps (sphere form, all "
                          f"{hub32.nsets} k/spin sets) on the same states; Coulomb setup excluded"}
+        if args.cpu_single_thread:
+            detail.update(cpu_single_thread(cfg, psi_host, f))
 
     out = {
         "metric": "Hubbard steps/s (project+occ+U/J+apply), FP32-split vs FP64 at 1e-9 occ err",

@@ -92,6 +92,30 @@ def test_field_off_restores_plain_results(case):
     assert normwise(c0.cpu().numpy(), case["c_plain"].cpu().numpy()) < 1e-13
 
 
+def test_set_ranges_under_the_field(case):
+    """hub_project_sets / hub_apply_sets under A, one set at a time and on a
+    range, reproduce the slices of the all-set calls: each set keeps the
+    phases of its own k + A."""
+    hub, psi_d = case["hub"], case["psi_d"]
+    nq = psi_d.shape[0]
+    hub.set_vector_potential(A2)
+    try:
+        c_all = hub.project(psi_d)
+        n, _, _ = hub.occupations(c_all, case["f_d"], with_pbar=False)
+        h_all = torch.zeros_like(psi_d)
+        hub.apply(case["ueff_d"], n, c_all, h_all)
+        bar = 1e-14 if hub.precision == "f64" else 1e-7
+        for q0, m in [(q, 1) for q in range(nq)] + [(1, nq - 1)]:
+            cs = hub.project(psi_d[q0:q0 + m], sets=(q0, m))
+            h = torch.zeros_like(psi_d[q0:q0 + m])
+            hub.apply(case["ueff_d"], n, cs, h, sets=(q0, m))
+            torch.cuda.synchronize()
+            assert normwise(cs.cpu().numpy(), c_all[q0:q0 + m].cpu().numpy()) < 1e-14, (q0, m)
+            assert normwise(h.cpu().numpy(), h_all[q0:q0 + m].cpu().numpy()) < bar, (q0, m)
+    finally:
+        hub.set_vector_potential(None)
+
+
 def test_graph_replays_follow_the_field(case):
     hub = case["hub"]
     psi_d, f_d = case["psi_d"], case["f_d"]

@@ -93,6 +93,32 @@ def _check_calls(case, hub, ref):
     assert normwise(h.cpu().numpy(), ref["hpsi"]) < bar
 
 
+@pytest.mark.parametrize("grouped", [True, False], ids=["grouped", "persite"])
+def test_set_ranges(case, grouped):
+    """hub_project_sets / hub_apply_sets (one k-point at a time, and a
+    range) reproduce the slices of the all-set calls."""
+    hub, psi_d = case["hub"], case["psi_d"]
+    nq = psi_d.shape[0]
+    assert nq > 1
+    hub.set_worklist(grouped)
+    try:
+        c_all = hub.project(psi_d)
+        n, _, _ = hub.occupations(c_all, case["f_d"], with_pbar=False)
+        ueff = torch.full((hub.nsites,), UEFF, dtype=torch.float64, device="cuda")
+        h_all = torch.zeros_like(psi_d)
+        hub.apply(ueff, n, c_all, h_all)
+        bar = 1e-14 if case["prec"] == "f64" else 1e-7
+        for q0, m in [(q, 1) for q in range(nq)] + [(1, nq - 1)]:
+            cs = hub.project(psi_d[q0:q0 + m], sets=(q0, m))
+            h = torch.zeros_like(psi_d[q0:q0 + m])
+            hub.apply(ueff, n, cs, h, sets=(q0, m))
+            torch.cuda.synchronize()
+            assert normwise(cs.cpu().numpy(), c_all[q0:q0 + m].cpu().numpy()) < 1e-14, (q0, m)
+            assert normwise(h.cpu().numpy(), h_all[q0:q0 + m].cpu().numpy()) < bar, (q0, m)
+    finally:
+        hub.set_worklist(True)
+
+
 def test_steps(case):
     hub, ref = case["hub"], case["ref"]
     S = case["cfg"].nstates
