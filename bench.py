@@ -234,7 +234,7 @@ def main():
     import torch
 
     import paper_1711_08935_amd as H
-    from paper_1711_08935_amd.tune import autotune
+    from paper_1711_08935_amd.tune import autotune, autotune_steps
     from synth import make_config, make_occupations, make_states
 
     cfg = make_config(args.workload)
@@ -499,23 +499,25 @@ def main():
         hpsi64 = torch.zeros_like(psi64)
         if not args.no_tune:
             hub64.step(psi64, f_d, hpsi64, mode="batched", bufs=bufs64)
-            autotune(hub64, psi64, bufs64["c"], bufs64["n"], bufs64["Ueff"])
         k64 = max(5, args.steps // 2)
-        w, e = time_steps(hub64, psi64, f_d, hpsi64, "persite", k64, 2, bufs64, rotate)
-        plain = k64 / (e if rotate is not None else w)
-        w, e = time_steps(hub64, psi64, f_d, hpsi64, "graph", k64, 2, bufs64, rotate)
-        g64 = k64 / (e if rotate is not None else w)
-        log(f"f64 plain per-site: {plain:.1f} steps/s, f64 graph: {g64:.1f} steps/s")
-        detail.update(fp64_plain_steps_per_s=round(plain, 2), fp64_graph_steps_per_s=round(g64, 2),
-                      speedup_vs_fp64_plain=round(value / plain, 3))
         # where the speedup comes from: the FP64 paths' projection and apply
         # time per step against the same union-point bytes at FP64 storage
         esz64 = psi64.element_size()
         bytes64 = {"project": U_pts * ncol * esz64 * hub64.nsets, "apply": 2 * U_pts * ncol * esz64 * hub64.nsets}
-        for tag, mode in (("fp64_plain_stages", "persite"), ("fp64_batched_stages", "batched")):
+
+        def fp64_path(mode):
+            """Steps/s of one FP64 path with shapes tuned for it (whole
+            per-site steps for the plain path), and its stage rates."""
+            if not args.no_tune:
+                if mode == "persite":
+                    autotune_steps(hub64, psi64, f_d, hpsi64, bufs64, mode="persite")
+                else:
+                    autotune(hub64, psi64, bufs64["c"], bufs64["n"], bufs64["Ueff"])
+            w, e = time_steps(hub64, psi64, f_d, hpsi64, mode, k64, 2, bufs64, rotate)
+            rate = k64 / (e if rotate is not None else w)
             hub64.profile(True)
             for _ in range(k64):
-                hub64.step(psi64, f_d, hpsi64, mode=mode, bufs=bufs64)
+                hub64.step(psi64, f_d, hpsi64, mode="persite" if mode == "persite" else "batched", bufs=bufs64)
             pr = hub64.profile_read()
             hub64.profile(False)
             rates = {}
@@ -524,7 +526,13 @@ def main():
                 rates[f"{k}_ms_per_step"] = round(ms, 4)
                 rates[f"{k}_launches_per_step"] = pr[k][1] // k64
                 rates[f"{k}_frac"] = round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
-            detail[tag] = rates
+            return rate, rates
+
+        plain, detail["fp64_plain_stages"] = fp64_path("persite")
+        g64, detail["fp64_batched_stages"] = fp64_path("graph")
+        log(f"f64 plain per-site: {plain:.1f} steps/s, f64 graph: {g64:.1f} steps/s")
+        detail.update(fp64_plain_steps_per_s=round(plain, 2), fp64_graph_steps_per_s=round(g64, 2),
+                      speedup_vs_fp64_plain=round(value / plain, 3))
         # accuracy: one step of each path on the current master states
         b32 = hub32.step(psi32, f_d, torch.zeros_like(psi32), mode="batched", bufs=hub32.step_buffers(S))
         b64 = hub64.step(psi64, f_d, torch.zeros_like(psi64), mode="batched", bufs=hub64.step_buffers(S))

@@ -96,7 +96,7 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
         const int32_t* __restrict__ gb = gi + b * U;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            load_row<T, NV>(psi_q + static_cast<int64_t>(gb[u]) * a.ld * NC + lofs, r[u]);
+            load_row_stream<T, NV>(psi_q + static_cast<int64_t>(gb[u]) * a.ld * NC + lofs, r[u]);
             if constexpr (GAUGE) {
                 ph[u][0] = pg[2 * static_cast<int64_t>(gb[u])];
                 ph[u][1] = pg[2 * static_cast<int64_t>(gb[u]) + 1];

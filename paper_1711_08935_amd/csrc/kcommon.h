@@ -118,19 +118,25 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&v)[N]) {
     }
 }
 
-// State rows are streamed: each element is read (and, in the apply, written)
-// once per step, so the loads and stores carry the non-temporal hint when
-// HUB_STREAM_ROWS is set.
-#ifndef HUB_STREAM_ROWS
-#define HUB_STREAM_ROWS 0
-#endif
-
+// Row access of the entry loops.  The projection streams its state rows
+// with non-temporal loads: each element is read once per step, and loads
+// that do not allocate in the caches leave the chunk tables there and do
+// not evict the apply's pending writes into the projection's time.  The
+// apply reads and writes hpsi with ordinary accesses (non-temporal ones
+// measured slower there).
+typedef float hub_f2 __attribute__((ext_vector_type(2)));
 typedef float hub_f4 __attribute__((ext_vector_type(4)));
 typedef double hub_d2 __attribute__((ext_vector_type(2)));
 
 template <typename T, int N>
-__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[N]) {
-    if constexpr (HUB_STREAM_ROWS && sizeof(T) * N >= 16) {
+__device__ __forceinline__ void load_row_stream(const T* __restrict__ p, T (&v)[N]) {
+    if constexpr (sizeof(T) * N == 8 && sizeof(T) == 4) {
+        const hub_f2 t = __builtin_nontemporal_load(reinterpret_cast<const hub_f2*>(p));
+        v[0] = t[0];
+        v[1] = t[1];
+    } else if constexpr (sizeof(T) * N == 8) {
+        v[0] = __builtin_nontemporal_load(p);
+    } else if constexpr (sizeof(T) * N >= 16) {
         constexpr int per = 16 / sizeof(T);
         using V = typename std::conditional<sizeof(T) == 4, hub_f4, hub_d2>::type;
 #pragma unroll
@@ -145,20 +151,13 @@ __device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[N]) {
 }
 
 template <typename T, int N>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&v)[N]) {
+    load_vec<T, N>(p, v);
+}
+
+template <typename T, int N>
 __device__ __forceinline__ void store_row(T* __restrict__ p, const T (&v)[N]) {
-    if constexpr (HUB_STREAM_ROWS && sizeof(T) * N >= 16) {
-        constexpr int per = 16 / sizeof(T);
-        using V = typename std::conditional<sizeof(T) == 4, hub_f4, hub_d2>::type;
-#pragma unroll
-        for (int i = 0; i < N / per; ++i) {
-            V t;
-#pragma unroll
-            for (int k = 0; k < per; ++k) t[k] = v[i * per + k];
-            __builtin_nontemporal_store(t, reinterpret_cast<V*>(p + i * per));
-        }
-    } else {
-        store_vec<T, N>(p, v);
-    }
+    store_vec<T, N>(p, v);
 }
 
 // Rows per batch of the software-pipelined entry loops: the two batches of

@@ -49,3 +49,34 @@ def autotune(hub, psi, c, n, ueff, reps=5, candidates=CANDIDATES):
     torch.cuda.synchronize()
     best["table"] = table
     return best
+
+
+def autotune_steps(hub, psi, f, hpsi, bufs, mode="persite", reps=3, candidates=CANDIDATES):
+    """Pick the projection and apply shapes for whole steps of one step mode
+    (``persite``: one launch per site and stage, whose small grids favour
+    other shapes than one launch over every chunk).  Every candidate runs
+    reps steps with the library's per-stage events; the fastest shape is
+    kept per kernel.  hpsi accumulates the steps' updates.  Returns the same
+    structure as autotune."""
+    times = {"project": {}, "apply": {}}
+    for shape in candidates:
+        hub.set_tuning(0, *shape)
+        hub.set_tuning(1, *shape)
+        hub.step(psi, f, hpsi, mode=mode, bufs=bufs)
+        hub.profile(True)
+        for _ in range(reps):
+            hub.step(psi, f, hpsi, mode=mode, bufs=bufs)
+        prof = hub.profile_read()
+        hub.profile(False)
+        for name in times:
+            times[name][shape] = prof[name][0] / reps
+    best = {}
+    table = {}
+    for which, name in ((0, "project"), (1, "apply")):
+        shape = min(times[name], key=times[name].get)
+        hub.set_tuning(which, *shape)
+        best[name] = (shape, times[name][shape])
+        table[name] = {f"{k[0]}x{k[1]}{'w' if k[2] else 'p'}": round(v, 4) for k, v in times[name].items()}
+    torch.cuda.synchronize()
+    best["table"] = table
+    return best
