@@ -221,19 +221,44 @@ def test_tuning_variants_agree(case):
     psi_d = case["psi_d"]
     try:
         for cpl, waves, layout in [(c, w, s) for s in (0, 1) for c in (1, 2, 4) for w in (1, 2, 4)]:
-            if True:
-                hub.set_tuning(0, cpl, waves, layout)
-                hub.set_tuning(1, cpl, waves, layout)
-                c = hub.project(psi_d)
-                h = torch.zeros_like(psi_d)
-                hub.apply(case["Ueff"], case["n"], case["c"], h)
-                torch.cuda.synchronize()
-                assert normwise(c.cpu().numpy(), case["c"].cpu().numpy()) < 1e-13, (cpl, waves, layout)
-                bar = 1e-13 if case["prec"] == "f64" else 1e-7
-                assert normwise(h.cpu().numpy(), case["hpsi"].cpu().numpy()) < bar, (cpl, waves, layout)
+            hub.set_tuning(0, cpl, waves, layout)
+            hub.set_tuning(1, cpl, waves, layout)
+            c = hub.project(psi_d)
+            h = torch.zeros_like(psi_d)
+            hub.apply(case["Ueff"], case["n"], case["c"], h)
+            torch.cuda.synchronize()
+            assert normwise(c.cpu().numpy(), case["c"].cpu().numpy()) < 1e-13, (cpl, waves, layout)
+            bar = 1e-13 if case["prec"] == "f64" else 1e-7
+            assert normwise(h.cpu().numpy(), case["hpsi"].cpu().numpy()) < bar, (cpl, waves, layout)
     finally:
         hub.set_tuning(0, 0, 4, -1)
         hub.set_tuning(1, 0, 4, -1)
+
+
+def test_step_tuner_keeps_results(case):
+    """tune.autotune_steps picks the shapes from whole per-site steps; the
+    per-site step with the picked shapes gives the outputs of the default
+    shapes up to summation order."""
+    from paper_1711_08935_amd.tune import CANDIDATES, autotune_steps
+    hub = case["hub"]
+    psi_d, f_d = case["psi_d"], case["f_d"]
+    try:
+        h0 = torch.zeros_like(psi_d)
+        b0 = {k: v.clone() for k, v in hub.step(psi_d, f_d, h0, mode="persite").items()}
+        bufs = hub.step_buffers(b0["nbar"].shape[2])
+        best = autotune_steps(hub, psi_d, f_d, torch.zeros_like(psi_d), bufs, mode="persite", reps=1)
+        assert best["project"][0] in CANDIDATES and best["apply"][0] in CANDIDATES
+        assert len(best["table"]["project"]) == len(CANDIDATES)
+        h1 = torch.zeros_like(psi_d)
+        hub.step(psi_d, f_d, h1, mode="persite", bufs=bufs)
+        torch.cuda.synchronize()
+    finally:
+        hub.set_tuning(0, 0, 4, -1)
+        hub.set_tuning(1, 0, 4, -1)
+    for k in ("c", "n", "pbar", "U", "J", "Ueff"):
+        assert normwise(bufs[k].cpu().numpy(), b0[k].cpu().numpy()) < 1e-12, k
+    bar = 1e-13 if case["prec"] == "f64" else 1e-7
+    assert normwise(h1.cpu().numpy(), h0.cpu().numpy()) < bar
 
 
 def test_worklists_agree(case):
