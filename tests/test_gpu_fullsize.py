@@ -7,7 +7,7 @@ V_U psi; noncollinear workload: every projection and matrix, V_U psi on
 sampled states; forces workload: all forces of the orbital-gradient form, and
 the state-gradient form on sampled states); for the 1024-state batched
 workload it checks every projection and matrix and V_U psi on sampled state
-columns.
+columns; the noncollinear workload with spin-dependent orbitals likewise.
 """
 
 import numpy as np
@@ -170,6 +170,48 @@ def test_spinor_layers_full_size():
     V = [OPOT.potential_matrix(sys_, ref["U"][I] - ref["J"][I], n[I]) for I in range(len(sps))]
     cols = np.sort(np.random.default_rng(3).choice(cfg.nstates, size=8, replace=False))
     h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
+    h = hpsi.cpu().numpy().reshape(hpsi.shape[0], hpsi.shape[1], -1, 2)[:, :, cols]
+    assert normwise(h, h_ref) < 2e-7
+
+
+@pytest.mark.timeout(900)
+def test_spinor_layers_full_size_spin_dependent():
+    """Spin-dependent orbitals at full size (spin-down exponents d 2.6, p 1.1,
+    U_eff fixed), the graph step on the grouped list with tuned shapes:
+    every projection c^sigma, the 2L x 2L occupation blocks, and V_U psi on
+    sampled states against the oracle's per-component sphere form."""
+    from oracle import spinorb as SO
+    ueff = 0.15
+    cfg = make_config("spinor_layers")
+    cfg.sites = [dict(s, zeta_dn=(2.6 if s["l"] == 2 else 1.1)) for s in cfg.sites]
+    print("\n[fullsize] spinor_layers spin-dependent f32", flush=True)
+    psi64 = make_states(cfg, device="cuda")
+    f = make_occupations(cfg)
+    f_d = torch.from_numpy(f).cuda()
+    hub = make_hub(cfg, "f32")
+    assert hub.query(11) > 0
+    psi = psi64.to(hub.state_dtype)
+    del psi64
+    for i in range(hub.nsites):
+        hub.set_fixed_ueff(i, ueff)
+    bufs = hub.step_buffers(cfg.nstates)
+    hpsi = torch.zeros_like(psi)
+    hub.step(psi, f_d, hpsi, mode="batched", bufs=bufs)
+    autotune(hub, psi, bufs["c"], bufs["n"], bufs["Ueff"], reps=2)
+    hpsi.zero_()
+    hub.step(psi, f_d, hpsi, mode="graph", bufs=bufs)
+    torch.cuda.synchronize()
+    sys_ = to_system(cfg)
+    used = psi.cpu().numpy().astype(np.complex128)
+    used = used.reshape(used.shape[0], used.shape[1], -1, 2)
+    c = SO.project_spin(sys_, used, form="sphere")
+    assert normwise(c_to_oracle(hub, bufs["c"]), c) < 1e-12
+    n, _, _ = OO.occupations(sys_, c, f, with_pbar=False)
+    for I in range(hub.nsites):
+        assert normwise(n_site(hub, bufs["n"], I, hub.site_L[I]), n[I]) < 1e-12, I
+    V = [OPOT.potential_matrix(sys_, ueff, nn) for nn in n]
+    cols = np.sort(np.random.default_rng(5).choice(cfg.nstates, size=8, replace=False))
+    h_ref = SO.apply_spin(sys_, c[:, :, cols], V, form="sphere")
     h = hpsi.cpu().numpy().reshape(hpsi.shape[0], hpsi.shape[1], -1, 2)[:, :, cols]
     assert normwise(h, h_ref) < 2e-7
 
