@@ -2,13 +2,18 @@
 """Hubbard steps/s on one MI355X (one step = project + occupations + ACBN0
 U/J + apply, for every site, k-point, spin and state).
 
-Default workload: the NiO-like collinear antiferromagnet (cubic cell 8.35
-bohr, 48^3 grid, 2 Ni d + 2 O p sites, 2x2x2 k-points, 64 complex states per
-k and spin, Fermi-Dirac occupations), synthetic states.  ``value`` is the
-FP32-storage path (FP64 orbital table, FP64 sums) run as one captured
-hipGraph per step; the plain FP64 path (one launch per site and stage, no
-graph) and the FP64 graph path are timed beside it.  Occupation errors of
-the FP32 path are measured against the FP64 path on the same master states.
+Default workload: the batched real-time loop (36 bohr cube, 120^3 grid,
+64 uneven p/d/f sites on a 4x4x4 lattice, 1024 real Gamma-point states,
+f = 1 for 512), synthetic states; between steps the FP64 master states are
+rotated (Givens rotations of angle ~1e-3, the synthetic propagator) and
+converted to FP32, outside the timed region.  ``value`` is the FP32-storage
+path (FP64 orbital table, FP64 sums) run as one captured hipGraph per step;
+the plain FP64 path (one launch per site and stage, no graph) and the FP64
+graph path are timed beside it.  The FP32 gate: occupations and U/J of the
+FP32 path against the FP64 oracle run on the FP64 master states (the CPU
+leg), at most 1e-9 absolute; a failed gate withholds ``value``.  The
+NiO-like collinear antiferromagnet (48^3, 2 Ni d + 2 O p, 2x2x2 k-points, 64
+complex states per k and spin) is measured beside it (``detail.side``).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 Prints one JSON line.
@@ -41,11 +46,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="nio_afm",
+    ap.add_argument("--workload", default="rt_batched",
                     choices=["nio_afm", "rt_batched", "gamma_d", "spinor_layers", "forces_fcc"])
+    ap.add_argument("--side", default="nio_afm",
+                    help="second workload summarized in detail.side (FP32 graph steps/s, stage rates, velocity "
+                         "gauge); 'none' skips it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time only the FP32 graph path")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="whole oracle steps timed (default 3; 1 for the three large workloads)")
     ap.add_argument("--cpu-single-thread", action="store_true",
                     help="also time one oracle step on one host thread")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel shapes")
@@ -116,8 +125,18 @@ def time_steps(hub, psi, f, hpsi, mode, steps, warmup, bufs, rotate=None):
     return wall, sum(a.elapsed_time(b) for a, b in evs) / 1e3
 
 
+def apply_block(cfg):
+    """State columns per block of the oracle's V_U psi, so that one block's
+    complex output stays within about 2 GB of host memory."""
+    ncomp = 2 if cfg.spin == "spinor" else 1
+    per_col = cfg.nq * cfg.G * 16 * ncomp
+    return int(max(1, min(cfg.nstates, 2e9 // per_col)))
+
+
 def cpu_baseline(cfg, psi_host, f, nsteps):
-    """The FP64 oracle (sphere form) timed on the host cores."""
+    """The FP64 oracle (sphere form) timed on the host cores: whole steps
+    (every site, set and state), V_U psi evaluated in column blocks.  Returns
+    (median seconds per step, BLAS threads, the last step's results)."""
     from threadpoolctl import threadpool_info
 
     from oracle import projection as OP
@@ -125,15 +144,38 @@ def cpu_baseline(cfg, psi_host, f, nsteps):
     from tests.helpers import to_system
     sys_ = to_system(cfg)
     sps = OP.all_spheres(sys_)
+    t0 = time.perf_counter()
     tens = OS.site_tensors(sys_, sps)
+    log(f"oracle Coulomb tensors (setup, untimed): {time.perf_counter() - t0:.1f} s")
+    block = apply_block(cfg)
     times = []
+    ref = None
     for i in range(nsteps):
         t0 = time.perf_counter()
-        OS.hubbard_step(sys_, psi_host, f, sps, tens, form="sphere")
+        ref = OS.hubbard_step(sys_, psi_host, f, sps, tens, form="sphere", apply_block=block)
         times.append(time.perf_counter() - t0)
-        log(f"oracle step {i}: {times[-1]:.2f} s")
+        log(f"oracle step {i}: {times[-1]:.2f} s (V_U psi in blocks of {block} columns)")
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return statistics.median(times), threads
+    return statistics.median(times), threads, ref, block
+
+
+def gate_errors(hub, b32, ref):
+    """max |n - n_oracle| over every site and block, and max |U - U_oracle|,
+    |J - J_oracle| (Hartree): the FP32 path's results against the oracle's."""
+    import numpy as np
+    n = b32["n"].cpu().numpy()
+    dn = 0.0
+    for I in range(hub.nsites):
+        L = hub.site_L[I]
+        r = np.asarray(ref["n"][I])
+        if hub.spin == "spinor":
+            g = np.array([[n[I][2 * s_ + t, :L, :L] for t in range(2)] for s_ in range(2)])
+        else:
+            g = n[I][:, :L, :L]
+        dn = max(dn, float(np.max(np.abs(g - r))))
+    du = max(float(np.max(np.abs(b32["U"].cpu().numpy() - ref["U"]))),
+             float(np.max(np.abs(b32["J"].cpu().numpy() - ref["J"]))))
+    return dn, du
 
 
 def cpu_single_thread(cfg, psi_host, f):
@@ -218,6 +260,72 @@ def rc_sweep(args):
                       "data": "synthetic", "config": {"workload": cfg.name, "grid": list(cfg.ngrid),
                                                       "storage": "f32 states", "ueff": "fixed 0.15 Ha"},
                       "sweep": out}))
+
+
+def side_summary(name, args):
+    """FP32 graph steps/s of a second workload with the kernel shapes the
+    autotuner picks for it, the projection's and apply's fractions of peak
+    HBM bandwidth (library HIP events around each stage, algorithmic bytes
+    over the union of sphere points), and for complex workloads the velocity
+    gauge without and with the DFT+U current every step."""
+    import numpy as np
+    import torch
+
+    import paper_1711_08935_amd as H
+    from paper_1711_08935_amd.tune import autotune
+    from synth import make_config, make_occupations, make_states
+
+    cfg = make_config(name)
+    log(f"side workload {name}")
+    psi = make_states(cfg, device="cuda")
+    f_d = torch.from_numpy(make_occupations(cfg)).cuda()
+    hub = H.Hubbard(cfg.cell, cfg.ngrid, cfg.sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                    is_complex=cfg.is_complex, precision="f32", chunk=args.chunk)
+    psi = psi.to(hub.state_dtype)
+    hub.coulomb(-1)
+    S = cfg.nstates
+    bufs = hub.step_buffers(S)
+    h = torch.zeros_like(psi)
+    hub.step(psi, f_d, h, mode="batched", bufs=bufs)
+    if not args.no_tune:
+        autotune(hub, psi, bufs["c"], bufs["n"], bufs["Ueff"])
+    _, ev = time_steps(hub, psi, f_d, h, "graph", args.steps, args.warmup, bufs)
+    out = {"workload": name, "steps_per_s": round(args.steps / ev, 2)}
+    hub.profile(True)
+    for _ in range(max(5, min(args.steps, 30))):
+        hub.step(psi, f_d, h, mode="batched", bufs=bufs)
+    pr = hub.profile_read()
+    hub.profile(False)
+    proj_bytes = union_points(hub) * hub.ncol(S) * psi.element_size() * hub.nsets
+    for k, b in (("project", proj_bytes), ("apply", 2 * proj_bytes)):
+        ms = pr[k][0] / max(1, pr[k][1])
+        out[f"{k}_ms"] = round(ms, 4)
+        out[f"{k}_frac"] = round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    out["small_kernels_us"] = round(1e3 * sum(pr[k][0] / max(1, pr[k][1])
+                                              for k in ("reduce", "nbar", "occupations", "acbn0")), 1)
+    if cfg.is_complex and not args.no_gauge:
+        A0 = np.array([0.05, 0.02, 0.0])
+        for with_current in (False, True):
+            def run(nsteps, i0):
+                for i in range(nsteps):
+                    hub.set_vector_potential(A0 * np.sin(0.1 * (i0 + i)))
+                    hub.step(psi, f_d, h, mode="graph", bufs=bufs)
+                    if with_current:
+                        hub.current(psi, bufs["c"], f_d, bufs["Ueff"], bufs["n"])
+            run(3, 0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run(args.steps, 3)
+            e1.record()
+            torch.cuda.synchronize()
+            key = "gauge_current_steps_per_s" if with_current else "gauge_steps_per_s"
+            out[key] = round(args.steps / (e0.elapsed_time(e1) * 1e-3), 2)
+        hub.set_vector_potential(None)
+    log(f"side workload: {out}")
+    del hub, psi, bufs, h
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -543,25 +651,52 @@ def main():
         d_ar = (b32["n"] - b64r["n"]).abs().max().item()
         du = max((b32["U"] - b64["U"]).abs().max().item(), (b32["J"] - b64["J"]).abs().max().item())
         du_ar = max((b32["U"] - b64r["U"]).abs().max().item(), (b32["J"] - b64r["J"]).abs().max().item())
-        detail.update(f32_occ_err_vs_f64_master=d_end, f32_occ_err_arithmetic=d_ar,
-                      f32_uj_err_vs_f64_master=du, f32_uj_err_arithmetic=du_ar)
-        log(f"f32 occupation error: vs FP64 master {d_end:.2e}, arithmetic {d_ar:.2e}; U/J {du:.2e} / {du_ar:.2e}")
-        del hub64
+        detail.update(f32_occ_err_vs_gpu_f64_master=d_end, f32_occ_err_arithmetic=d_ar,
+                      f32_uj_err_vs_gpu_f64_master=du, f32_uj_err_arithmetic=du_ar)
+        log(f"f32 occupation error: vs GPU FP64 path on the master {d_end:.2e}, arithmetic {d_ar:.2e}; "
+            f"U/J {du:.2e} / {du_ar:.2e}")
+        del hub64, b64, b64r, up
+    else:
+        b32 = hub32.step(psi32, f_d, torch.zeros_like(psi32), mode="batched", bufs=hub32.step_buffers(S))
+        torch.cuda.synchronize()
 
     # ---------------------------------------------------------- CPU oracle
+    # The oracle timed on the host cores, on the FP64 master states that the
+    # FP32 path's last accuracy step was rounded from; its n, U and J are the
+    # reference of the FP32 gate.
     cpu = None
-    if not args.no_cpu_baseline and cfg.name in ("nio_afm", "gamma_d", "spinor_layers"):
+    gate = {"bar": 1e-9, "reference": None}
+    if not args.no_cpu_baseline:
         psi_host = psi64.cpu().numpy()
-        t_step, threads = cpu_baseline(cfg, psi_host, f, args.cpu_steps)
+        nsteps = args.cpu_steps or (1 if cfg.name in ("rt_batched", "spinor_layers", "forces_fcc") else 3)
+        t_step, threads, ref, block = cpu_baseline(cfg, psi_host, f, nsteps)
         cpu = {"value": round(1.0 / t_step, 4), "unit": "Hubbard steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"median of {args.cpu_steps} whole FP64 oracle steps (sphere form, all "
-                         f"{hub32.nsets} k/spin sets) on the same states; Coulomb setup excluded"}
+               "sample": f"median of {nsteps} whole FP64 oracle step(s) (sphere form: all {hub32.nsets} state "
+                         f"sets, {S} states, {len(cfg.sites)} sites; V_U psi in blocks of {block} columns to bound "
+                         f"host memory) on the FP64 master states of the last GPU step; Coulomb setup excluded"}
+        dn, duj = gate_errors(hub32, b32, ref)
+        gate.update(reference="FP64 oracle on the FP64 master states", occ_err=dn, uj_err=duj,
+                    passed=bool(dn <= 1e-9 and duj <= 1e-9))
+        log(f"FP32 gate vs oracle: max|dn| {dn:.2e}, max|dU|,|dJ| {duj:.2e} (bar 1e-9)")
         if args.cpu_single_thread:
             detail.update(cpu_single_thread(cfg, psi_host, f))
+        del psi_host, ref
+    elif "f32_occ_err_vs_gpu_f64_master" in detail:
+        gate.update(reference="GPU FP64 path (pinned to the oracle by the GPU tests) on the FP64 master states",
+                    occ_err=detail["f32_occ_err_vs_gpu_f64_master"], uj_err=detail["f32_uj_err_vs_gpu_f64_master"])
+        gate["passed"] = bool(gate["occ_err"] <= 1e-9 and gate["uj_err"] <= 1e-9)
+    detail["fp32_gate"] = gate
+    del b32
+
+    if args.side != "none" and args.side != cfg.name:
+        del hub32, bufs32, hpsi32, psi32, psi64
+        torch.cuda.empty_cache()
+        detail["side"] = side_summary(args.side, args)
 
     out = {
         "metric": "Hubbard steps/s (project+occ+U/J+apply), FP32-split vs FP64 at 1e-9 occ err",
-        "value": round(value, 2), "unit": "Hubbard steps/s", "n_gpus": 1, "steps": args.steps,
+        "value": round(value, 2) if gate.get("passed", True) else None, "unit": "Hubbard steps/s", "n_gpus": 1,
+        "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(hub_time / args.steps * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic", "config": {"workload": cfg.name, "grid": list(cfg.ngrid), "sites": len(cfg.sites),
@@ -572,6 +707,9 @@ def main():
                                         "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "detail": detail,
     }
+    if not gate.get("passed", True):
+        out["error"] = "FP32 gate failed: occupations or U/J of the FP32 path differ from the reference by more " \
+                       "than 1e-9; value withheld"
     print(json.dumps(out), flush=True)
 
 

@@ -322,6 +322,29 @@ int hub_forces(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const dou
 int hub_forces_state_gradient(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
                               const double* f, const double* Ueff, const double* n, double* F);
 
+/* Gradients of the total Hubbard energy E = sum_I E_U[I] (Eq. E_Dudarev; App. A
+ * for spinors) with U_eff held fixed, as the ACBN0 potential prescribes (the
+ * paper does not differentiate U-bar, J-bar; Sec. III), multiplied by scale
+ * (e.g. the incoming gradient of a reverse-mode pass):
+ *  - grad_psi (device, state layout with leading dimension ldg, may be NULL):
+ *    overwritten with scale * 2 dE/dpsi*, the convention of PyTorch for
+ *    complex inputs (real states: scale * dE/dpsi), i.e. by Eq. minimization
+ *      grad_psi_q[g][col] = scale * 2 g_s dV w_k f_s (V_U psi)_q[g][col],
+ *    g_s = 2 for unpolarized contexts (their channel stands for two spins),
+ *    else 1; every used column of every grid point is written (zero off the
+ *    spheres), padding columns past ncol are not touched;
+ *  - grad_R (device [site][3], may be NULL): scale * dE/dR_I = -scale * F_I,
+ *    F the forces of hub_forces (Sec. IV, through <grad phi|psi>, sphere
+ *    membership and normalization frozen); needs psi (ld, nstates as in
+ *    hub_forces).
+ * c, n: from hub_project / hub_occupations on the same states; f: device
+ * occupations [sets][nstates]; Ueff: device [site].  At least one output.
+ * Errors: HUB_EINVAL (NULL inputs, no output, sizes, scale not finite),
+ * HUB_ESTATE. */
+int hub_energy_gradient(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
+                        const double* f, const double* Ueff, const double* n, double scale, void* grad_psi,
+                        int64_t ldg, double* grad_R);
+
 /* Velocity gauge (Sec. V): with a uniform vector potential A (host array of
  * 3, bohr^-1; NULL switches the field off), the projections and the apply
  * of every later call and graph replay use V^A = exp(-i A.r) V_U exp(i A.r):
@@ -359,6 +382,7 @@ typedef struct hub_step_io {
     double* U; double* J; double* Ueff; int32_t* status;
 } hub_step_io;
 int hub_step(hub_ctx* ctx, const hub_step_io* io, int mode);
+
 
 /* Per-stage device timing with HIP events recorded around the launches of
  * each stage on the context stream (eager launches only; a captured step

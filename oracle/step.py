@@ -19,11 +19,15 @@ def site_tensors(system, spheres, method="fft"):
 
 
 def hubbard_step(system, psi, f, spheres=None, tensors=None, ueff_fixed=None,
-                 form="fullgrid"):
+                 form="fullgrid", apply_block=None, on_block=None):
     """Return a dict with c, n, pbar, nbar, U, J, Ueff, status, V, EU, hpsi.
 
     ``ueff_fixed``: optional per-site list; a finite entry fixes that site's
     U_eff (empirical DFT+U), NaN/None computes it with ACBN0.
+    ``apply_block``: evaluate V_U psi (sphere form) for that many state
+    columns at a time, so that the complex output of a large workload need
+    not be held whole; each block goes to ``on_block(s0, hpsi_block)`` and
+    the returned hpsi is None.  The arithmetic of every column is the same.
     """
     sps = spheres if spheres is not None else projection.all_spheres(system)
     if form == "fullgrid":
@@ -50,7 +54,13 @@ def hubbard_step(system, psi, f, spheres=None, tensors=None, ueff_fixed=None,
         Ueff[I] = U[I] - J[I]
     V = [potential.potential_matrix(system, Ueff[I], n[I]) for I in range(nsites)]
     EU = np.array([potential.energy(system, Ueff[I], n[I]) for I in range(nsites)])
-    if form == "fullgrid":
+    if apply_block is not None:
+        hpsi = None
+        for s0 in range(0, c.shape[2], apply_block):
+            blk = apply_sphere(system, c[:, :, s0:s0 + apply_block], V, sps)
+            if on_block is not None:
+                on_block(s0, blk)
+    elif form == "fullgrid":
         hpsi = potential.apply_fullgrid(system, c, V, sps)
     else:
         hpsi = apply_sphere(system, c, V, sps)

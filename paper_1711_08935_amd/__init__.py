@@ -46,7 +46,8 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_acbn0_uj", "hub_apply", "hub_energy", "hub_forces", "hub_step", "hub_destroy",
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
            "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
-           "hub_energy_fll", "hub_set_site_spin_orbital", "hub_project_sets", "hub_apply_sets"]
+           "hub_energy_fll", "hub_set_site_spin_orbital", "hub_project_sets", "hub_apply_sets",
+           "hub_energy_gradient"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -88,6 +89,7 @@ def lib():
         "hub_project_sets": [P, P, I64, I, I, I, P],
         "hub_apply_sets": [P, P, P, P, I, P, D, P, I64, I, I],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
+        "hub_energy_gradient": [P, P, I64, I, P, P, P, P, D, P, I64, P],
         "hub_destroy": [P],
         "hub_strerror": [I],
         "hub_profile": [P, I],
@@ -424,6 +426,24 @@ class Hubbard:
         _check(getattr(lib(), name)(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)), _dptr(Ueff),
                                     _dptr(n), _dptr(F)), name)
         return F
+
+    def energy_gradient(self, psi, c, f, Ueff, n, scale=1.0, want_psi=True, want_R=True, nstates=None):
+        """scale times the gradients of sum_I E_U[I] at fixed U_eff
+        (hub_energy_gradient): (grad_psi, grad_R).  grad_psi has psi's shape
+        and PyTorch's convention for complex tensors (2 dE/dpsi*); grad_R is
+        dE/dR, (n_sites, 3).  Either may be skipped (None returned)."""
+        ld, S = self._states(psi, nstates)
+        gpsi = None
+        ldg = 0
+        if want_psi:
+            gpsi = torch.empty(psi.shape, dtype=psi.dtype, device=psi.device)
+            ldg, _ = self._states(gpsi, S)
+        gR = torch.empty((self.nsites, 3), dtype=torch.float64, device="cuda") if want_R else None
+        self._stream()
+        _check(lib().hub_energy_gradient(self._ctx, _dptr(psi), ld, S, _dptr(c), _dptr(self._dev(f)),
+                                         _dptr(self._dev(Ueff)), _dptr(n), float(scale), _dptr(gpsi), ldg,
+                                         _dptr(gR)), "hub_energy_gradient")
+        return gpsi, gR
 
     def profile(self, enable=True):
         _check(lib().hub_profile(self._ctx, int(bool(enable))), "hub_profile")

@@ -238,12 +238,16 @@ int ensure(double** buf, size_t* cap, size_t n, hub_ctx* c) {
 
 // Columns per lane: by default the vector that gives each lane 16 bytes per
 // state row (lanes span several state sets when a set is narrow), provided
-// every lane's columns stay aligned and inside the row (ld % cpl == 0).
-int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int which) {
+// every lane's columns stay aligned and inside the row (ld % cpl == 0).  The
+// apply (which = 1) stores whole vectors, so its lanes must also end at the
+// last used column (ncol % cpl == 0): a caller's padding columns past ncol
+// are never written.
+int pick_cpl(const hub_ctx* c, const void* ptr, int64_t ld, int which, int ncol) {
     const size_t e = c->elem();
     auto ok = [&](int cpl) {
         const size_t vb = std::min<size_t>(16, cpl * e);
-        return (ld % cpl == 0) && (reinterpret_cast<uintptr_t>(ptr) % vb == 0);
+        return (ld % cpl == 0) && (which == 0 || ncol % cpl == 0) &&
+               (reinterpret_cast<uintptr_t>(ptr) % vb == 0);
     };
     const int want = c->tune_cpl[which];
     if (want == 1 || ((want == 2 || want == 4) && ok(want))) return want;
@@ -430,7 +434,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
             const int st = run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
                 ProjArgs b = a;
                 b.chunk_list = list;
-                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0), std::min(4 * k, HUB_GF_MAX));
+                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0, ncol), std::min(4 * k, HUB_GF_MAX));
                 b.wide = pick_wide(c, ncol, cpl, 0);
                 return launch_project(b, nch, nq, c->precision, c->is_complex, cpl, c->tune_waves[0], k, s);
             });
@@ -460,7 +464,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     }
     // per-site chunks of spin-dependent orbitals have no velocity-gauge form
     if (spindep && c->gauge) return HUB_ESTATE;
-    int cpl = pick_cpl(c, psi, ld, 0);
+    int cpl = pick_cpl(c, psi, ld, 0, ncol);
     // gradient tiles hold 3L functions, spin-dependent tiles 2L
     if ((grad || spindep) && cpl * c->ncplx() > 4) cpl = 4 / c->ncplx();
     a.wide = pick_wide(c, ncol, cpl, 0);
@@ -590,8 +594,11 @@ int do_acbn0(hub_ctx* c, const double* n, const double* pbar, double* U, double*
 
 // q0, nq: the state sets updated (cc, colscale and hpsi hold those sets
 // only); nq < 0: every set of the context.
+// occ: when not null, each column is also weighted by w_k f_s of its state
+// (f: [nsets][nstates] of the context, kw: the k-point weights).
 int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, int nstates, const double* colscale,
-             double alpha, void* hpsi, int64_t ld, bool per_site, int q0 = 0, int nq = -1) {
+             double alpha, void* hpsi, int64_t ld, bool per_site, int q0 = 0, int nq = -1,
+             const double* occ = nullptr) {
     if (nq < 0) nq = c->nsets();
     const int ncol = c->ncol(nstates);
     int st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(ld) * c->ncplx(), c);
@@ -619,6 +626,8 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     a.n = n;
     a.ueff = Ueff;
     a.colscale = colscale;
+    a.occ = occ;
+    a.kw = c->d_kw;
     a.alpha = alpha;
     a.orb_site = c->d_orb_site;
     a.site_orb0 = c->d_site_orb0;
@@ -636,11 +645,11 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
         return run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
             ApplyArgs b = a;
             b.chunk_list = list;
-            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1), std::min(4 * k, HUB_GF_MAX));
+            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1, ncol), std::min(4 * k, HUB_GF_MAX));
             return launch_apply_grouped(b, nch, nq, c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
         }, true);
     }
-    int cpl = pick_cpl(c, hpsi, ld, 1);
+    int cpl = pick_cpl(c, hpsi, ld, 1, ncol);
     if (c->T.spindep) {
         if (c->gauge) return HUB_ESTATE;       // no velocity-gauge form of these per-site chunks
         // 2L functions per entry: both spin components' orbitals
@@ -1143,8 +1152,9 @@ namespace {
 // Forces (table TAB_GRAD, real part) or velocity-gauge current (TAB_MOMENT,
 // imaginary part): out[site][i] = 2 g sum w f Re/Im sum_a conj(d_{a,i}) B_a,
 // with d the projections of the psi on the table's 3L functions per site.
+// fscale multiplies the result (1: forces or current; -g: g dE_U/dR).
 int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
-                     const double* Ueff, const double* n, double* out, int table) {
+                     const double* Ueff, const double* n, double* out, int table, double fscale = 1.0) {
     if (!c || !cc || !f || !Ueff || !n || !out) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
@@ -1182,6 +1192,7 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
     a.nq = c->nsets();
     a.nblk = c->nblk();
     a.imag = table == TAB_MOMENT;
+    a.scale = fscale;
     StageTimer tm(c, HUB_STAGE_FORCES);
     HUB_TRY(launch_forces(a, c->stream));
     return HUB_OK;
@@ -1266,6 +1277,31 @@ int hub_forces_state_gradient(hub_ctx* c, const void* psi, int64_t ld, int nstat
 int hub_current(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
                 const double* Ueff, const double* n, double* J) {
     return contract_moments(c, psi, ld, nstates, cc, f, Ueff, n, J, TAB_MOMENT);
+}
+
+int hub_energy_gradient(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
+                        const double* Ueff, const double* n, double scale, void* grad_psi, int64_t ldg,
+                        double* grad_R) {
+    if (!c || !cc || !f || !Ueff || !n || !std::isfinite(scale)) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!grad_psi && !grad_R) return HUB_EINVAL;
+    if (grad_psi && !valid_states(c, grad_psi, ldg, nstates)) return HUB_EINVAL;
+    if (grad_R && !valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
+    if (grad_psi) {
+        // every used column of every row starts at zero (the apply writes
+        // sphere points only), then grad += scale 2 g_s dV w_k f V_U psi
+        const int ncol = c->ncol(nstates);
+        HUB_TRY(launch_zero_cols(grad_psi, static_cast<int>(c->elem() / c->ncplx()),
+                                 static_cast<int64_t>(c->nsets()) * c->G(), ldg * c->ncplx(), ncol * c->ncplx(),
+                                 c->stream));
+        const double gs = c->spin_mode == HUB_UNPOLARIZED ? 2.0 : 1.0;
+        const double dV = (c->cell[0] / c->ngrid[0]) * (c->cell[1] / c->ngrid[1]) * (c->cell[2] / c->ngrid[2]);
+        const int st = do_apply(c, Ueff, n, cc, nstates, nullptr, scale * 2.0 * gs * dV, grad_psi, ldg, false, 0, -1,
+                                f);
+        if (st) return st;
+    }
+    if (grad_R) return contract_moments(c, psi, ld, nstates, cc, f, Ueff, n, grad_R, TAB_GRAD, -scale);
+    return HUB_OK;
 }
 
 int hub_set_vector_potential(hub_ctx* c, const double* A) {

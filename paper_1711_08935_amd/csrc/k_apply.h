@@ -70,6 +70,11 @@ __device__ __forceinline__ void coefficient(const ApplyArgs& a, int site, int ai
             const int s = SPINOR ? (col >> 1) : col;
             sc *= a.colscale[static_cast<int64_t>(q) * a.nstates + s];
         }
+        if (a.occ != nullptr && ok) {
+            // w_k f_s of the column's state (gradient of E_U, Eq. minimization)
+            const int s = SPINOR ? (col >> 1) : col;
+            sc *= a.kw[k] * a.occ[static_cast<int64_t>(a.q0 + q) * a.nstates + s];
+        }
         if (!ok || (sgf >= 0 && (col & 1) != sgf)) sc = 0.0;
         const int colc = ok ? col : 0;
         double br = 0.0, bi = 0.0;

@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
     }
     if (tid == 0) {
         const double gs = (a.nblk == 1) ? 2.0 : 1.0;
-        for (int i = 0; i < 3; ++i) a.F[site * 3 + i] = gs * 2.0 * red[0][i];
+        for (int i = 0; i < 3; ++i) a.F[site * 3 + i] = a.scale * (gs * 2.0 * red[0][i]);
     }
 }
 
@@ -615,6 +615,17 @@ __global__ void __launch_bounds__(256) k_gauge_tables(const GaugeArgs a) {
         sincos(t, &sv, &cv);
         out[0] = cv;
         out[1] = sv;
+    }
+}
+
+// ---------------------------------------------------------------- fill
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_cols(T* __restrict__ p, int64_t rows, int64_t ld, int ncol) {
+    const int64_t total = rows * ncol;
+    for (int64_t o = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; o < total;
+         o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t r = o / ncol;
+        p[r * ld + (o - r * ncol)] = T(0);
     }
 }
 
@@ -694,5 +705,17 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t st) {
 
 hipError_t launch_forces(const ForceArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_forces, dim3(a.nsites), dim3(NB), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_cols(void* p, int elem_bytes, int64_t rows, int64_t ld, int ncol, hipStream_t st) {
+    if (rows <= 0 || ncol <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((rows * ncol + 255) / 256, 8192);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_zero_cols<double>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                           static_cast<double*>(p), rows, ld, ncol);
+    else
+        hipLaunchKernelGGL(k_zero_cols<float>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                           static_cast<float*>(p), rows, ld, ncol);
     return hipGetLastError();
 }

@@ -52,6 +52,9 @@ struct ApplyArgs {
     const double* n;          // [site][nblk][7][7][2]
     const double* ueff;       // [site]
     const double* colscale;   // [nq][nstates] or null
+    const double* occ;        // [context sets][nstates] occupations f, or null: then each column is
+                              // also weighted by w_k f_s (energy gradient)
+    const double* kw;         // [nk] k-point weights (with occ)
     double alpha;
     int wide;                 // 1: one state set per wave; 0: sets packed across lanes
     int nchunks;              // chunks in chunk_list (set by the launcher)

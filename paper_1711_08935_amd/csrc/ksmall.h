@@ -82,6 +82,7 @@ struct ForceArgs {
     const int32_t* site_L; const int32_t* site_orb0;
     int nsites; int J; int ncol; int nstates; int ncplx; int spinor; int nspin; int nq; int nblk;
     int imag;                 // 0: 2 Re sum conj(d) B (forces); 1: 2 Im (current)
+    double scale;             // multiplies the result
 };
 
 // Velocity-gauge tables for a uniform vector potential A:
@@ -117,3 +118,6 @@ hipError_t launch_forces(const ForceArgs& a, hipStream_t st);
 hipError_t launch_fll(const FllArgs& a, hipStream_t st);
 hipError_t launch_gauge_tables(const GaugeArgs& a, hipStream_t st);
 hipError_t launch_coulomb(const CoulombArgs& a, hipStream_t st);
+// p[r * ld + i] = 0 for every row r < rows and scalar i < ncol (elem_bytes 4
+// or 8): clears the used columns of a state-layout buffer, padding untouched.
+hipError_t launch_zero_cols(void* p, int elem_bytes, int64_t rows, int64_t ld, int ncol, hipStream_t st);

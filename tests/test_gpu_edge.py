@@ -161,3 +161,102 @@ def test_nonfinite_states_are_flagged(fixed):
     else:
         assert np.isnan(U.cpu().numpy()[0])
     assert H.lib().hub_strerror(H.HUB_ENONFINITE) == b"occupations, U or J not finite"
+
+
+@pytest.mark.parametrize("cplx,nstates,pad", [(False, 6, 2), (True, 5, 1)])
+def test_apply_leaves_padding_columns_untouched(cplx, nstates, pad):
+    """hpsi as a padded view whose leading dimension is even while the used
+    columns are ragged (FP32 real: 6 of 8; FP32 complex: 5 of 6).  The apply
+    writes whole vectors per lane, so the library picks a lane width that
+    ends at the last used column: the padding, filled with -0.0, keeps its
+    sign bit, and the used columns equal the apply into a contiguous
+    buffer."""
+    cfg = _cfg(spin="unpolarized" if not cplx else "collinear", nstates=nstates, cplx=cplx)
+    rng = np.random.default_rng(4)
+    hub = make_hub(cfg, "f32", chunk=64)
+    psi_d, _ = device_states(hub, _rand_psi(cfg, nstates, rng) * 0.1)
+    f_d = torch.from_numpy(rng.uniform(0, 1, size=(cfg.nq, nstates))).cuda()
+    for i in range(hub.nsites):
+        hub.set_fixed_ueff(i, 0.3)
+    c = hub.project(psi_d)
+    n, _, _ = hub.occupations(c, f_d, with_pbar=False, nbar=False)
+    ueff = torch.full((hub.nsites,), 0.3, dtype=torch.float64, device="cuda")
+    ref = torch.zeros_like(psi_d)
+    hub.apply(ueff, n, c, ref)
+    big = torch.empty(psi_d.shape[:2] + (nstates + pad,), dtype=psi_d.dtype, device="cuda")
+    (torch.view_as_real(big) if cplx else big).fill_(-0.0)          # both parts of a complex value
+    view = big[..., :nstates]
+    view.zero_()
+    for cpl in (0, 4, 2):
+        hub.set_tuning(1, cpl, 4, -1)
+        view.zero_()
+        hub.apply(ueff, n, c, view, nstates=nstates)
+        torch.cuda.synchronize()
+        padcols = big[..., nstates:]
+        parts = torch.view_as_real(padcols) if cplx else padcols
+        assert torch.all(parts == 0) and torch.all(torch.signbit(parts)), cpl
+        assert torch.equal(view, ref), cpl
+    hub.set_tuning(1, 0, 4, -1)
+
+
+def test_one_electron_in_one_orbital_is_degenerate():
+    """psi = phi_m of a d shell on a grid point of a cubic grid (exactly
+    orthonormal orbitals), occupied in the spin-up channel only: one
+    electron in one orbital.  Both ACBN0 denominators vanish (Eqs. ACBN0_U,
+    ACBN0_J), so the site is flagged HUB_WDEGENERATE with U = J = 0, as the
+    oracle; n is e_m e_m^T in the up channel and zero in the other, and
+    V_U psi = 0 (U_eff = 0)."""
+    from synth import make_config
+    from tests.gpu_common import oracle_case
+    base = make_config("gamma_d")
+    cfg = Config(name="one_electron", cell=base.cell, ngrid=base.ngrid, sites=base.sites, kpts=np.zeros((1, 3)),
+                 kweights=np.ones(1), spin="collinear", is_complex=False, nstates=1, seed=0)
+    hub = make_hub(cfg, "f64")
+    g, _, phi, _ = hub.site_points(0)
+    m = 2
+    psi = np.zeros((2, cfg.G, 1))
+    np.add.at(psi[0, :, 0], g, phi[:, m])
+    psi[1] = psi[0]
+    f = np.array([[1.0], [0.0]])
+    psi_d, used = device_states(hub, psi)
+    _, _, _, ref = oracle_case(cfg, used, f)
+    assert int(ref["status"][0]) == 1 and ref["U"][0] == 0.0 and ref["J"][0] == 0.0
+    hub.coulomb(-1)
+    hpsi = torch.zeros_like(psi_d)
+    b = hub.step(psi_d, torch.from_numpy(f).cuda(), hpsi, mode="graph")
+    torch.cuda.synchronize()
+    assert int(b["status"][0]) == H.HUB_WDEGENERATE
+    assert b["U"][0].item() == 0.0 and b["J"][0].item() == 0.0 and b["Ueff"][0].item() == 0.0
+    n = n_site(hub, b["n"], 0, 5)
+    e = np.zeros((5, 5))
+    e[m, m] = 1.0
+    assert np.max(np.abs(n[0] - e)) < 1e-12 and np.max(np.abs(n[1])) == 0.0
+    assert normwise(n, ref["n"][0]) < 1e-12
+    assert torch.count_nonzero(hpsi).item() == 0
+
+
+@pytest.mark.parametrize("spin", ["collinear", "spinor"])
+def test_empty_shells(spin):
+    """Every occupation zero: n = P-bar = 0, both denominators vanish on
+    every site (HUB_WDEGENERATE, U = J = 0), E_U = 0 and V_U psi = 0, as the
+    oracle."""
+    from synth import make_config
+    from tests.gpu_common import oracle_case, states_and_occupations
+    cfg = make_config("nio_afm" if spin == "collinear" else "spinor_layers", small=True)
+    psi, f = states_and_occupations(cfg)
+    f = np.zeros_like(f)
+    hub = make_hub(cfg, "f64", chunk=256)
+    psi_d, used = device_states(hub, psi)
+    _, _, _, ref = oracle_case(cfg, used, f)
+    assert np.all(ref["status"] == 1)
+    hub.coulomb(-1)
+    hpsi = torch.zeros_like(psi_d)
+    b = hub.step(psi_d, torch.from_numpy(f).cuda(), hpsi, mode="batched")
+    EU = hub.energy(b["Ueff"], b["n"])
+    torch.cuda.synchronize()
+    assert np.all(b["status"].cpu().numpy() == H.HUB_WDEGENERATE)
+    assert torch.count_nonzero(b["U"]).item() == 0 and torch.count_nonzero(b["J"]).item() == 0
+    assert torch.count_nonzero(b["n"]).item() == 0 and torch.count_nonzero(b["pbar"]).item() == 0
+    assert torch.count_nonzero(EU).item() == 0 and torch.count_nonzero(hpsi).item() == 0
+    c = c_to_oracle(hub, b["c"])
+    assert normwise(c, ref["c"]) < 1e-12

@@ -148,11 +148,13 @@ def test_nio_full_size_large_spheres_in_passes():
 
 
 @pytest.mark.timeout(900)
-def test_spinor_layers_full_size():
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_spinor_layers_full_size(prec):
     """Noncollinear spinors at full size (4 k-points, 256 two-component
-    states): every projection, the 2L x 2L occupation blocks, U and J, and
-    V_U psi on sampled states."""
-    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("spinor_layers", "f32")
+    states), FP32 and FP64 storage: every projection, the 2L x 2L occupation
+    blocks, U and J, and V_U psi on sampled states, against the oracle on the
+    states the device holds."""
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("spinor_layers", prec)
     sys_ = to_system(cfg)
     sps = OP.all_spheres(sys_)
     used = psi.cpu().numpy().astype(np.complex128)
@@ -171,7 +173,7 @@ def test_spinor_layers_full_size():
     cols = np.sort(np.random.default_rng(3).choice(cfg.nstates, size=8, replace=False))
     h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
     h = hpsi.cpu().numpy().reshape(hpsi.shape[0], hpsi.shape[1], -1, 2)[:, :, cols]
-    assert normwise(h, h_ref) < 2e-7
+    assert normwise(h, h_ref) < (2e-7 if prec == "f32" else 1e-12)
 
 
 @pytest.mark.timeout(900)
@@ -266,3 +268,117 @@ def test_forces_full_size():
     Fso = SG.forces_state_gradient(sys_, c[:, :, cols], e, V, fm[:, cols])
     assert np.abs(Fso).max() > 1e-8
     assert normwise(Fs, Fso) < 1e-11
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["nio_afm", "rt_batched"])
+def test_fp32_storage_gate_against_oracle_on_master_states(name):
+    """The FP32 gate end to end: the FP32-storage context runs the graph step
+    (tuned shapes) on the FP64 master states rounded to FP32; the oracle runs
+    on the FP64 master states themselves.  Every occupation entry (n and
+    P-bar, every site and block) within 1e-9 absolute, U-bar and J-bar within
+    1e-9 Ha on every site (Eqs. occ_matrices, ACBN0_U, ACBN0_J).  V_U psi on
+    sampled state columns carries the two FP32 roundings (input states and
+    output) and the difference they make through the projections: normwise
+    within 5e-7."""
+    from oracle import acbn0
+    cfg = make_config(name)
+    print(f"\n[fullsize] FP32 gate {name}", flush=True)
+    master = make_states(cfg, device="cuda")
+    f = make_occupations(cfg)
+    f_d = torch.from_numpy(f).cuda()
+    hub = make_hub(cfg, "f32")
+    psi = master.to(hub.state_dtype)
+    host = master.cpu().numpy()
+    del master
+    hub.coulomb(-1)
+    bufs = hub.step_buffers(cfg.nstates)
+    hpsi = torch.zeros_like(psi)
+    hub.step(psi, f_d, hpsi, mode="batched", bufs=bufs)
+    autotune(hub, psi, bufs["c"], bufs["n"], bufs["Ueff"], reps=2)
+    hpsi.zero_()
+    hub.step(psi, f_d, hpsi, mode="graph", bufs=bufs)
+    torch.cuda.synchronize()
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    c = OP.project_sphere(sys_, host, sps)
+    n, pbar, _ = OO.occupations(sys_, c, f)
+    tens = OS.site_tensors(sys_, sps)
+    U = np.zeros(len(sps))
+    J = np.zeros(len(sps))
+    for I in range(len(sps)):
+        U[I], J[I], _, _ = acbn0.uj_collinear(OO.channels(sys_, n[I]), OO.channels(sys_, pbar[I]), tens[I])
+    dn = max(np.max(np.abs(n_site(hub, bufs["n"], I, hub.site_L[I]) - n[I])) for I in range(hub.nsites))
+    dp = max(np.max(np.abs(n_site(hub, bufs["pbar"], I, hub.site_L[I]) - pbar[I])) for I in range(hub.nsites))
+    dU = np.max(np.abs(bufs["U"].cpu().numpy() - U))
+    dJ = np.max(np.abs(bufs["J"].cpu().numpy() - J))
+    print(f"[gate] {name}: max|dn| {dn:.2e} max|dPbar| {dp:.2e} max|dU| {dU:.2e} max|dJ| {dJ:.2e}", flush=True)
+    assert dn <= 1e-9 and dp <= 1e-9
+    assert dU <= 1e-9 and dJ <= 1e-9
+    assert np.all(bufs["status"].cpu().numpy() == 0)
+    V = [OPOT.potential_matrix(sys_, U[I] - J[I], n[I]) for I in range(len(sps))]
+    cols = np.sort(np.random.default_rng(7).choice(cfg.nstates, size=8, replace=False))
+    h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
+    h = hpsi[:, :, torch.from_numpy(cols).cuda()].cpu().numpy()
+    if not cfg.is_complex:
+        h_ref = h_ref.real
+    assert normwise(h, h_ref) < 5e-7
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_central_difference_full_size():
+    """The many-site forces workload at full size (96^3, 32 d sites, 512 real
+    states) in an FP64 context, U_eff fixed per site (seeded):
+    * d/deps E_U(psi + eps dpsi) by central differences (eps = 1e-6 along a
+      seeded direction: random on the sphere points and occupied states, zero
+      elsewhere, each such state column of unit norm dV |dpsi_s|^2 = 1), each
+      energy from the library's own projection, occupations and energy
+      kernels, equals sum grad_psi dpsi from hub_energy_gradient
+      (Eq. minimization);
+    * grad_psi on sampled state columns equals the oracle's
+      2 g_s dV w f V_U psi, and grad_R the oracle's -F (Sec. IV)."""
+    cfg = make_config("forces_fcc")
+    print("\n[fullsize] adjoint FD forces_fcc f64", flush=True)
+    hub = make_hub(cfg, "f64")
+    psi = make_states(cfg, device="cuda")
+    f = make_occupations(cfg)
+    f_d = torch.from_numpy(f).cuda()
+    rng = np.random.default_rng(12)
+    ueff = rng.uniform(0.1, 0.4, size=hub.nsites)
+    ueff_d = torch.from_numpy(ueff).cuda()
+
+    def energy(x):
+        c = hub.project(x)
+        n, _, _ = hub.occupations(c, f_d, with_pbar=False, nbar=False)
+        return hub.energy(ueff_d, n).sum().item()
+
+    c = hub.project(psi)
+    n, _, _ = hub.occupations(c, f_d, with_pbar=False, nbar=False)
+    gpsi, gR = hub.energy_gradient(psi, c, f_d, ueff_d, n)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12)
+    d = torch.randn(psi.shape, generator=gen, dtype=torch.float64, device="cuda")
+    covered = torch.zeros(hub.G, dtype=torch.bool, device="cuda")
+    for s_ in range(hub.nsites):
+        covered[torch.from_numpy(hub.site_points(s_)[0].astype(np.int64)).cuda()] = True
+    d *= covered[None, :, None] * (f_d > 0)[:, None, :]
+    d /= torch.sqrt(hub.dV * (d * d).sum(dim=1, keepdim=True)).clamp_min(1e-300)
+    eps = 1e-6
+    fd = (energy(psi + eps * d) - energy(psi - eps * d)) / (2 * eps)
+    an = (gpsi * d).sum().item()
+    print(f"[adjoint] finite difference {fd:.12e} analytic {an:.12e}", flush=True)
+    assert abs(an) > 1e-4
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    del d
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    host = psi.cpu().numpy()
+    c_or = OP.project_sphere(sys_, host, sps)
+    n_or, _, _ = OO.occupations(sys_, c_or, f, with_pbar=False)
+    V = [OPOT.potential_matrix(sys_, ueff[I], n_or[I]) for I in range(len(sps))]
+    cols = np.sort(rng.choice(np.flatnonzero(f[0] > 0), size=8, replace=False))
+    h = OS.apply_sphere(sys_, c_or[:, :, cols], V, sps).real
+    g_or = 2.0 * 2.0 * sys_.dV * h * f[:, None, cols]
+    assert normwise(gpsi[:, :, torch.from_numpy(cols).cuda()].cpu().numpy(), g_or) < 1e-12
+    Fo = OF.forces_analytic(sys_, c_or, OF.gradient_projections(sys_, host, sps), V, f)
+    assert normwise(-gR.cpu().numpy(), Fo) < 1e-11

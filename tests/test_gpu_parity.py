@@ -9,8 +9,8 @@ several chunks, column tiles and a ragged tail of columns.  Bars:
   what is compared is the kernels' arithmetic; occupations and U/J must agree
   to 1e-9 absolute (they agree far better), V_U psi to the FP32 rounding of
   the output (normwise 2e-7).
-The end-to-end effect of FP32 storage (vs the FP64 master states) is
-reported by bench.py, not asserted here.
+The end-to-end effect of FP32 storage (FP32 results against the oracle on
+the FP64 master states) is asserted at full size in test_gpu_fullsize.py.
 """
 
 import numpy as np
@@ -194,9 +194,13 @@ def test_forces(case):
 
 
 def test_autograd_energy_gradients(case):
+    """dE_U/dpsi* (PyTorch's convention, spinors included) and dE_U/dR from
+    hub_energy_gradient through the autograd wrapper, at the oracle's U_eff
+    held fixed, against the oracle's adjoint and forces; the wrapper refuses
+    a U_eff that is not given."""
     hub = case["hub"]
-    if hub.spin == "spinor":
-        pytest.skip("autograd wrapper covers collinear layouts")
+    with pytest.raises(ValueError):
+        H.HubbardEnergy.apply(case["psi_d"], None, hub, case["f_d"], None)
     psi = case["psi_d"].clone().requires_grad_(True)
     R = torch.zeros((hub.nsites, 3), dtype=torch.float64, device="cuda", requires_grad=True)
     E = H.HubbardEnergy.apply(psi, R, hub, case["f_d"], case["Ueff"])

@@ -194,3 +194,31 @@ def test_force_vanishes_by_symmetry():
     V = [POT.potential_matrix(sys_, 0.4, n[0])]
     F = FO.forces_analytic(sys_, c, FO.gradient_projections(sys_, psi, sps), V, f)
     assert np.max(np.abs(F)) < 1e-14
+
+
+def test_step_with_column_blocks_matches_whole_step():
+    """The column-blocked apply of the oracle step (used to bound host memory
+    on the 1024-state workload) hands over exactly the columns of the
+    full-grid V_U psi, block by block, ragged last block included."""
+    sys_ = _system()
+    S = 7
+    psi, sps = _states(sys_, S, 21)
+    rng = np.random.default_rng(8)
+    f = rng.uniform(0, 1, size=(sys_.nq, S))
+    ueff = [0.35, 0.2]
+    whole = ST.hubbard_step(sys_, psi, f, sps, ueff_fixed=ueff)
+    got = np.zeros_like(whole["hpsi"])
+    seen = []
+
+    def keep(s0, blk):
+        seen.append((s0, blk.shape[2]))
+        got[:, :, s0:s0 + blk.shape[2]] = blk
+
+    part = ST.hubbard_step(sys_, psi, f, sps, ueff_fixed=ueff, form="sphere", apply_block=3, on_block=keep)
+    assert part["hpsi"] is None
+    assert seen == [(0, 3), (3, 3), (6, 1)]
+    assert normwise(got, whole["hpsi"]) < 1e-13
+    for I in range(len(sps)):
+        assert normwise(part["n"][I], whole["n"][I]) < 1e-13, I
+    for k in ("Ueff", "EU"):
+        assert normwise(part[k], whole[k]) < 1e-13, k
