@@ -65,6 +65,8 @@ extern "C" {
 #define HUB_ESTATE (-4)      /* call not valid in the context's state       */
 #define HUB_ENONFINITE (-5)  /* per-site device status: occupations, U or J
                                 not finite (NaN or Inf in the states)      */
+#define HUB_ESCRATCH (-6)    /* hub_step_noalloc: the step's workspace does
+                                not fit HUB_SCRATCH_BYTES                   */
 #define HUB_WDEGENERATE 1    /* per-site status: a U/J denominator < 1e-12  */
 
 /* spin modes */
@@ -207,7 +209,8 @@ int hub_set_stream(hub_ctx* ctx, void* stream);
  * orbitals covering one grid point, 13 dilated-sphere entries of the
  * state-gradient forces (0 before the first hub_forces_state_gradient),
  * 14 passes of the grouped apply (points covered by more than 16 orbitals
- * have their covers split over passes; 0 without a grouped work list). */
+ * have their covers split over passes; 0 without a grouped work list),
+ * 15 device allocations (hipMalloc) the context has made so far. */
 int hub_query(const hub_ctx* ctx, int what, int64_t* value);
 
 /* Per-site data after hub_finalize_host: L = 2l+1, offset of its first
@@ -383,6 +386,24 @@ typedef struct hub_step_io {
 } hub_step_io;
 int hub_step(hub_ctx* ctx, const hub_step_io* io, int mode);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * batched hub_step (HUB_STEP_BATCHED, the same kernels and summation order,
+ * hence the same results) with every workspace it needs (projection partial
+ * sums, occupation partial sums, N-bar when io->nbar is NULL, the apply's
+ * padding row) carved out of one static device array of HUB_SCRATCH_BYTES
+ * per GPU, which the library holds until the process ends.  The call makes
+ * no hipMalloc or hipFree and creates no event or graph; stage timing
+ * (hub_profile) does not record it.  The scratch array is shared by every
+ * context and call on one GPU and keeps the last call's contents (every
+ * value a step reads from it is written earlier in the same step):
+ * overlapping calls on one GPU, e.g. from two streams, race and must be
+ * serialized by the caller.  Needs hub_finalize (which takes the array's
+ * device address) and the Coulomb tensors unless every U_eff is fixed.
+ * Errors: those of hub_step, and HUB_ESCRATCH when the step's workspace
+ * exceeds HUB_SCRATCH_BYTES (nothing is launched). */
+#define HUB_SCRATCH_BYTES (128u << 20)
+int hub_step_noalloc(hub_ctx* ctx, const hub_step_io* io);
 
 /* Per-stage device timing with HIP events recorded around the launches of
  * each stage on the context stream (eager launches only; a captured step

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhub.so")
 HUB_OK, HUB_EINVAL, HUB_ENOMEM, HUB_EDEVICE, HUB_ESTATE = 0, -1, -2, -3, -4
 HUB_WDEGENERATE = 1
 HUB_ENONFINITE = -5
+HUB_ESCRATCH = -6
 SPIN_MODES = {"unpolarized": 1, "collinear": 2, "spinor": 4}
 PRECISIONS = {"f64": 0, "f32": 1}
 STEP_MODES = {"batched": 0, "graph": 1, "persite": 2}
@@ -47,7 +48,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
            "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
            "hub_energy_fll", "hub_set_site_spin_orbital", "hub_project_sets", "hub_apply_sets",
-           "hub_energy_gradient"]
+           "hub_energy_gradient", "hub_step_noalloc"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -89,6 +90,7 @@ def lib():
         "hub_project_sets": [P, P, I64, I, I, I, P],
         "hub_apply_sets": [P, P, P, P, I, P, D, P, I64, I, I],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
+        "hub_step_noalloc": [P, ctypes.POINTER(StepIO)],
         "hub_energy_gradient": [P, P, I64, I, P, P, P, P, D, P, I64, P],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -475,6 +477,22 @@ class Hubbard:
                     b["U"].data_ptr(), b["J"].data_ptr(), b["Ueff"].data_ptr(), b["status"].data_ptr())
         self._stream()
         _check(lib().hub_step(self._ctx, ctypes.byref(io), STEP_MODES[mode]), "hub_step")
+        return b
+
+    def step_noalloc(self, psi, f, hpsi, bufs, alpha=1.0, nstates=None):
+        """The batched step with its workspaces in the library's static
+        scratch array (hub_step_noalloc): no device allocation.  ``bufs``
+        (from step_buffers) must be given, so nothing is allocated here."""
+        ld, S = self._states(psi, nstates)
+        ldh, S2 = self._states(hpsi, nstates)
+        if S2 != S:
+            raise ValueError("psi and hpsi hold different state counts")
+        b = bufs
+        io = StepIO(psi.data_ptr(), ld, S, self._dev(f).data_ptr(), hpsi.data_ptr(), ldh, float(alpha),
+                    b["c"].data_ptr(), b["n"].data_ptr(), b["pbar"].data_ptr(), b["nbar"].data_ptr(),
+                    b["U"].data_ptr(), b["J"].data_ptr(), b["Ueff"].data_ptr(), b["status"].data_ptr())
+        self._stream()
+        _check(lib().hub_step_noalloc(self._ctx, ctypes.byref(io)), "hub_step_noalloc")
         return b
 
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -30,6 +31,38 @@ struct GraphKey {
     bool valid = false;
 };
 
+}  // namespace
+
+// Workspace of hub_step_noalloc: a file-scope device array, one copy per
+// GPU, alive until the process ends.  Host code never passes its name to a
+// kernel or a copy (on the host it is only a stand-in symbol): it uses the
+// device address that hipGetSymbolAddress returns for each device, taken
+// once per device in hub_finalize with that device current.
+static __device__ __align__(256) unsigned char scratch[HUB_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device ``dev``.
+hipError_t scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = p;
+    return hipSuccess;
+}
+
+void* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
 }  // namespace
 
 struct hub_ctx {
@@ -104,6 +137,17 @@ struct hub_ctx {
     double* d_st_tab_dn = nullptr;           // spin-down orbitals (spin-dependent contexts)
     double* d_nbar_ws = nullptr;
     size_t nbar_cap = 0;
+    // Workspaces of the call in flight come from the buffers above (grown
+    // with hipMalloc on demand) unless ws_fixed points at slices of the
+    // static scratch array (hub_step_noalloc), which are used as they are.
+    struct FixedWs {
+        double* part;
+        double* occ;
+        double* nbar;
+        double* sink;
+    };
+    const FixedWs* ws_fixed = nullptr;
+    int64_t nalloc = 0;                      // device allocations made so far (hub_query 15)
 
     // per-stage event timing
     bool prof = false;
@@ -141,10 +185,18 @@ int map_err(hipError_t e) {
         if (_e != hipSuccess) return map_err(_e); \
     } while (0)
 
+// Every device allocation of a context goes through here (counted).
 template <typename T>
-hipError_t upload(T** dst, const std::vector<T>& src, size_t& bytes) {
+hipError_t dev_malloc(hub_ctx* c, T** p, size_t bytes) {
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+    if (e == hipSuccess) ++c->nalloc;
+    return e;
+}
+
+template <typename T>
+hipError_t upload(hub_ctx* c, T** dst, const std::vector<T>& src, size_t& bytes) {
     const size_t nb = std::max<size_t>(1, src.size()) * sizeof(T);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), nb);
+    hipError_t e = dev_malloc(c, dst, nb);
     if (e != hipSuccess) return e;
     bytes += nb;
     if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
@@ -204,7 +256,7 @@ struct StageTimer {
         return e;
     }
     StageTimer(hub_ctx* ctx, int st) : c(ctx), stage(st) {
-        if (c->prof && !c->capturing) {
+        if (c->prof && !c->capturing && !c->ws_fixed) {
             e0 = get();
             e1 = get();
             if (e0) (void)hipEventRecord(e0, c->stream);
@@ -230,7 +282,7 @@ int ensure(double** buf, size_t* cap, size_t n, hub_ctx* c) {
         *cap = 0;
         drop_graph(c);
     }
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(buf), std::max<size_t>(1, n) * sizeof(double));
+    hipError_t e = dev_malloc(c, buf, std::max<size_t>(1, n) * sizeof(double));
     if (e != hipSuccess) return map_err(e);
     *cap = n;
     return HUB_OK;
@@ -371,9 +423,9 @@ ProjArgs proj_args(hub_ctx* c, const void* psi, int64_t ld, int ncol, int table)
     return a;
 }
 
-ReduceArgs reduce_args(hub_ctx* c, double* out, int ncol, int mult) {
+ReduceArgs reduce_args(hub_ctx* c, const double* part, double* out, int ncol, int mult) {
     ReduceArgs r{};
-    r.part = c->d_part;
+    r.part = part;
     r.prows = c->T.part_rows * mult;
     r.out = out;
     r.nrows = c->T.J * mult;
@@ -416,10 +468,14 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
     const bool spindep = !grad && c->T.spindep;
     const int ncol = c->ncol(nstates);
     const int mult = grad ? 3 : 1;
-    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, spindep ? 2 : mult), c);
-    if (st) return st;
+    double* part = c->ws_fixed ? c->ws_fixed->part : nullptr;
+    if (!part) {
+        const int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, spindep ? 2 : mult), c);
+        if (st) return st;
+        part = c->d_part;
+    }
     ProjArgs a = proj_args(c, psi, ld, ncol, table);
-    a.part = c->d_part;
+    a.part = part;
     a.nq = nq;
     if (!per_site && !grad && grouped(c)) {
         const GroupTables& GT = c->T.grouped;
@@ -441,7 +497,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
             if (st) return st;
         }
         ReduceGroupedArgs r{};
-        r.part = c->d_part;
+        r.part = part;
         r.prows = GT.part_rows;
         r.out = out;
         r.J = c->T.J;
@@ -483,7 +539,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         }
     }
     }
-    ReduceArgs r = reduce_args(c, out, ncol, mult);
+    ReduceArgs r = reduce_args(c, part, out, ncol, mult);
     r.q0 = q0;
     r.colpar = colpar;
     if (spindep) {
@@ -511,13 +567,21 @@ size_t occ_need(const hub_ctx* c, int nstates) {
 int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, double* n, double* pbar, double* nbar,
                    bool per_site) {
     const int ncol = c->ncol(nstates);
-    int st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, nstates), c);
-    if (st) return st;
-    if (pbar && !nbar) {
-        const size_t need = static_cast<size_t>(c->nsets()) * c->T.nspecies * nstates;
-        st = ensure(&c->d_nbar_ws, &c->nbar_cap, need, c);
+    double* ws = c->ws_fixed ? c->ws_fixed->occ : nullptr;
+    if (!ws) {
+        const int st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, nstates), c);
         if (st) return st;
-        nbar = c->d_nbar_ws;
+        ws = c->d_occ_ws;
+    }
+    if (pbar && !nbar) {
+        if (c->ws_fixed) {
+            nbar = c->ws_fixed->nbar;
+        } else {
+            const size_t need = static_cast<size_t>(c->nsets()) * c->T.nspecies * nstates;
+            const int st = ensure(&c->d_nbar_ws, &c->nbar_cap, need, c);
+            if (st) return st;
+            nbar = c->d_nbar_ws;
+        }
     }
     if (nbar) {
         NbarArgs b{};
@@ -554,7 +618,7 @@ int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, d
     o.nblk = c->nblk();
     o.nspecies = c->T.nspecies;
     o.nsplit = hub_occ_splits(c->nk, nstates);
-    o.ws = c->d_occ_ws;
+    o.ws = ws;
     StageTimer tm(c, HUB_STAGE_OCC);
     if (!per_site) {
         HUB_TRY(launch_occ(o, 0, c->T.nsites, c->stream));
@@ -601,11 +665,15 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
              const double* occ = nullptr) {
     if (nq < 0) nq = c->nsets();
     const int ncol = c->ncol(nstates);
-    int st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(ld) * c->ncplx(), c);
-    if (st) return st;
+    double* sink = c->ws_fixed ? c->ws_fixed->sink : nullptr;
+    if (!sink) {
+        const int st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(ld) * c->ncplx(), c);
+        if (st) return st;
+        sink = c->d_sink;
+    }
     ApplyArgs a{};
     a.hpsi = hpsi;
-    a.sink = c->d_sink;
+    a.sink = sink;
     a.pg = c->gauge ? c->d_pg : nullptr;
     a.ld = ld;
     a.qstride = c->G() * ld * c->ncplx();
@@ -696,6 +764,22 @@ bool valid_states(const hub_ctx* c, const void* psi, int64_t ld, int nstates) {
     return psi != nullptr && nstates >= 1 && ld >= c->ncol(nstates);
 }
 
+// Argument checks of a whole step (hub_step, hub_step_noalloc).
+int check_step(const hub_ctx* c, const hub_step_io* io) {
+    if (!c || !io) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (!valid_states(c, io->psi, io->ld, io->nstates) || !valid_states(c, io->hpsi, io->ldh, io->nstates))
+        return HUB_EINVAL;
+    if (!io->f || !io->c || !io->n || !io->pbar || !io->U || !io->J || !io->Ueff || !std::isfinite(io->alpha))
+        return HUB_EINVAL;
+    if (need_tensors(c)) return HUB_ESTATE;
+    return HUB_OK;
+}
+
+// doubles, rounded up so that every slice of the scratch array starts on a
+// 256-byte boundary
+size_t slice256(size_t n) { return (n + 31) / 32 * 32; }
+
 }  // namespace
 
 // =====================================================================  ABI
@@ -711,6 +795,7 @@ const char* hub_strerror(int code) {
     case HUB_ESTATE: return "call not valid in the current context state";
     case HUB_WDEGENERATE: return "degenerate U/J denominator";
     case HUB_ENONFINITE: return "occupations, U or J not finite";
+    case HUB_ESCRATCH: return "workspace larger than the static scratch buffer";
     default: return "unknown status";
     }
 }
@@ -857,6 +942,7 @@ int hub_finalize(hub_ctx* c, void* stream) {
     if (st) return st;
     if (c->built_dev) return HUB_OK;
     HUB_TRY(hipGetDevice(&c->device));
+    HUB_TRY(scratch_address(c->device));
     c->stream = reinterpret_cast<hipStream_t>(stream);
     const HostTables& T = c->T;
     std::vector<int32_t> all(T.chunks.size());
@@ -876,7 +962,7 @@ int hub_finalize(hub_ctx* c, void* stream) {
     b = 0;
     hipError_t e = hipSuccess;
     auto up = [&](auto** dst, const auto& src) {
-        if (e == hipSuccess) e = upload(dst, src, b);
+        if (e == hipSuccess) e = upload(c, dst, src, b);
     };
     up(&c->d_chunks, T.chunks);
     up(&c->d_all, all);
@@ -943,7 +1029,7 @@ int hub_finalize(hub_ctx* c, void* stream) {
         }
     }
     if (e == hipSuccess) {
-        e = hipMalloc(reinterpret_cast<void**>(&c->d_tensor), c->sites.size() * 2401 * sizeof(double));
+        e = dev_malloc(c, &c->d_tensor, c->sites.size() * 2401 * sizeof(double));
         b += c->sites.size() * 2401 * sizeof(double);
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -988,6 +1074,7 @@ int hub_query(const hub_ctx* c, int what, int64_t* v) {
     case 12: *v = T.grouped.nfmax; break;
     case 13: *v = c->stencil_entries; break;
     case 14: *v = T.grouped.ok ? T.grouped.npass : 0; break;
+    case 15: *v = c->nalloc; break;
     default: return HUB_EINVAL;
     }
     return HUB_OK;
@@ -1051,10 +1138,10 @@ int hub_coulomb(hub_ctx* c, int site, double* tensor) {
     for (int s = s0; s < s1; ++s) maxp = std::max(maxp, c->T.spheres[s].g.size());
     int32_t* d_ijk = nullptr;
     double *d_phi = nullptr, *d_rho = nullptr, *d_W = nullptr;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_ijk), maxp * 3 * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_phi), maxp * 7 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_rho), maxp * 28 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_W), maxp * 28 * sizeof(double));
+    hipError_t e = dev_malloc(c, &d_ijk, maxp * 3 * sizeof(int32_t));
+    if (e == hipSuccess) e = dev_malloc(c, &d_phi, maxp * 7 * sizeof(double));
+    if (e == hipSuccess) e = dev_malloc(c, &d_rho, maxp * 28 * sizeof(double));
+    if (e == hipSuccess) e = dev_malloc(c, &d_W, maxp * 28 * sizeof(double));
     double h[3];
     for (int i = 0; i < 3; ++i) h[i] = c->cell[i] / c->ngrid[i];
     const double g0 = hub_g0_cell_average(h);
@@ -1206,7 +1293,7 @@ int gauge_tables(hub_ctx* c) {
                                hipMemcpyHostToDevice, c->stream));
         return HUB_OK;
     }
-    if (!c->d_pg) HUB_TRY(hipMalloc(reinterpret_cast<void**>(&c->d_pg), static_cast<size_t>(c->G()) * 2 * sizeof(double)));
+    if (!c->d_pg) HUB_TRY(dev_malloc(c, &c->d_pg, static_cast<size_t>(c->G()) * 2 * sizeof(double)));
     GaugeArgs g{};
     for (int i = 0; i < 3; ++i) {
         g.A[i] = c->A[i];
@@ -1241,13 +1328,13 @@ int build_stencil(hub_ctx* c) {
         *p = nullptr;
     }
     size_t bytes = 0;
-    HUB_TRY(upload(&c->d_st_chunks, S.chunks, bytes));
-    HUB_TRY(upload(&c->d_st_all, all, bytes));
-    HUB_TRY(upload(&c->d_st_gidx, S.gidx, bytes));
-    HUB_TRY(upload(&c->d_st_tab, S.tab, bytes));
-    HUB_TRY(upload(&c->d_st_site_ptr, S.site_chunk_ptr, bytes));
-    HUB_TRY(upload(&c->d_st_site_ids, S.site_chunk_ids, bytes));
-    if (c->T.spindep) HUB_TRY(upload(&c->d_st_tab_dn, S.tab_dn, bytes));
+    HUB_TRY(upload(c, &c->d_st_chunks, S.chunks, bytes));
+    HUB_TRY(upload(c, &c->d_st_all, all, bytes));
+    HUB_TRY(upload(c, &c->d_st_gidx, S.gidx, bytes));
+    HUB_TRY(upload(c, &c->d_st_tab, S.tab, bytes));
+    HUB_TRY(upload(c, &c->d_st_site_ptr, S.site_chunk_ptr, bytes));
+    HUB_TRY(upload(c, &c->d_st_site_ids, S.site_chunk_ids, bytes));
+    if (c->T.spindep) HUB_TRY(upload(c, &c->d_st_tab_dn, S.tab_dn, bytes));
     c->table_bytes += bytes;
     c->stencil_nchunks = static_cast<int>(S.chunks.size());
     c->stencil_part_rows = S.part_rows;
@@ -1304,6 +1391,27 @@ int hub_energy_gradient(hub_ctx* c, const void* psi, int64_t ld, int nstates, co
     return HUB_OK;
 }
 
+int hub_step_noalloc(hub_ctx* c, const hub_step_io* io) {
+    int st = check_step(c, io);
+    if (st) return st;
+    void* base = scratch_ptr(c->device);
+    if (!base) return HUB_ESTATE;
+    // slices of the scratch array: projection partial sums, occupation
+    // partial sums, N-bar (when the caller passes none), the apply's sink row
+    const int ncol = c->ncol(io->nstates);
+    const size_t n_part = slice256(part_need(c, ncol, c->T.spindep ? 2 : 1));
+    const size_t n_occ = slice256(occ_need(c, io->nstates));
+    const size_t n_nbar = io->nbar ? 0 : slice256(static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates);
+    const size_t n_sink = slice256(static_cast<size_t>(io->ldh) * c->ncplx());
+    if ((n_part + n_occ + n_nbar + n_sink) * sizeof(double) > HUB_SCRATCH_BYTES) return HUB_ESCRATCH;
+    double* p = static_cast<double*>(base);
+    const hub_ctx::FixedWs ws{p, p + n_part, p + n_part + n_occ, p + n_part + n_occ + n_nbar};
+    c->ws_fixed = &ws;
+    st = run_step(c, io, false);
+    c->ws_fixed = nullptr;
+    return st;
+}
+
 int hub_set_vector_potential(hub_ctx* c, const double* A) {
     if (!c) return HUB_EINVAL;
     if (A) {
@@ -1320,18 +1428,13 @@ int hub_set_vector_potential(hub_ctx* c, const double* A) {
 }
 
 int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
-    if (!c || !io) return HUB_EINVAL;
-    if (!built(c)) return HUB_ESTATE;
-    if (!valid_states(c, io->psi, io->ld, io->nstates) || !valid_states(c, io->hpsi, io->ldh, io->nstates))
-        return HUB_EINVAL;
-    if (!io->f || !io->c || !io->n || !io->pbar || !io->U || !io->J || !io->Ueff || !std::isfinite(io->alpha))
-        return HUB_EINVAL;
+    int st = check_step(c, io);
+    if (st) return st;
     if (mode != HUB_STEP_BATCHED && mode != HUB_STEP_GRAPH && mode != HUB_STEP_PERSITE) return HUB_EINVAL;
-    if (need_tensors(c)) return HUB_ESTATE;
     // the step needs the projection workspace and the N-bar buffer; size them
     // before any capture so that the graph never sees a reallocation
     const int ncol = c->ncol(io->nstates);
-    int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, c->T.spindep ? 2 : 1), c);
+    st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, c->T.spindep ? 2 : 1), c);
     if (st) return st;
     if (!io->nbar) {
         st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);
