@@ -14,7 +14,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhub.so")
+# HUB_LIBRARY names another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree libhub.so
+LIB_PATH = os.environ.get("HUB_LIBRARY") or os.path.join(_HERE, "libhub.so")
 
 HUB_OK, HUB_EINVAL, HUB_ENOMEM, HUB_EDEVICE, HUB_ESTATE = 0, -1, -2, -3, -4
 HUB_WDEGENERATE = 1

@@ -7,7 +7,9 @@ projection kernels do.  The result must equal the oracle's -<phi|D psi>
 (4th-order differences of the states, then the plain sphere projection):
 spheres that reach past half the cell, sites next to the cell faces, an s
 shell next to p/d/f shells, generic k-points, and the spin-down orbitals'
-table of a context with spin-dependent orbitals."""
+table of a context with spin-dependent orbitals.  Every case runs both
+with a plain build of the checker and with one under host AddressSanitizer
+and UndefinedBehaviorSanitizer."""
 
 import os
 import shutil
@@ -36,14 +38,20 @@ CASES = [
 ]
 
 
-@pytest.fixture(scope="module")
-def checker(tmp_path_factory):
+# the checker is built plain and with host AddressSanitizer and
+# UndefinedBehaviorSanitizer (any report aborts it with a non-zero status)
+SANITIZE = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+@pytest.fixture(scope="module", params=["plain", "sanitized"])
+def checker(request, tmp_path_factory):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("stencil") / "stencil_tables")
-    subprocess.run([gxx, "-O2", "-ffp-contract=off", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-                    os.path.join(ROOT, "tests", "host", "stencil_tables.cpp"), os.path.join(CSRC, "sphere.cpp"),
+    extra = SANITIZE if request.param == "sanitized" else []
+    subprocess.run([gxx, "-O2", "-ffp-contract=off", "-std=c++17", *extra, "-I", os.path.join(ROOT, "include"), "-I",
+                    CSRC, os.path.join(ROOT, "tests", "host", "stencil_tables.cpp"), os.path.join(CSRC, "sphere.cpp"),
                     "-o", exe], check=True)
     return exe
 
@@ -64,8 +72,10 @@ def test_stencil_tables_match_oracle(checker, tmp_path, case):
                     struct.pack("d", s.zeta_dn if s.zeta_dn is not None else float("nan")))
         f.write(struct.pack("3d", *k) + struct.pack("i", S))
         f.write(np.ascontiguousarray(psi[0]).tobytes())
-    r = subprocess.run([checker, str(inp), str(out)], capture_output=True, text=True)
+    r = subprocess.run([checker, str(inp), str(out)], capture_output=True, text=True,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1"))
     assert r.returncode == 0, r.stdout + r.stderr
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
     J = sum(s.L for s in sites)
     dd = np.fromfile(out, dtype=np.complex128)
     spin = any(s.zeta_dn is not None for s in sites)
