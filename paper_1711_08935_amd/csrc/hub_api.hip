@@ -329,7 +329,8 @@ int clamp_cpl(const hub_ctx* c, int cpl, int nf) {
 }
 
 // Runs launch(k, list, nchunks, stream) over the grouped work list: once
-// with k = HUB_NCLASS + 1 and the merged chunk list, or once per non-empty
+// with a merged class k (HUB_MERGED8 when no point carries more than 8
+// functions, else HUB_MERGED16) and the merged chunk list, or once per non-empty
 // function-count class k.  Concurrent class launches go to side streams
 // forked from the context's stream and joined back to it: the classes write
 // disjoint outputs, so their kernels run concurrently (parallel branches of
@@ -344,17 +345,18 @@ int run_classes(hub_ctx* c, F&& launch, bool per_pass = false) {
     const int np = c->T.grouped.npass;
     if (np > 1) {
         if (!per_pass) {
-            HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m, c->gpass_ptr[np], c->stream));
+            HUB_TRY(launch(HUB_MERGED16, c->d_gall_m, c->gpass_ptr[np], c->stream));
             return HUB_OK;
         }
         for (int p = 0; p < np; ++p)
-            HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m + c->gpass_ptr[p], c->gpass_ptr[p + 1] - c->gpass_ptr[p],
+            HUB_TRY(launch(HUB_MERGED16, c->d_gall_m + c->gpass_ptr[p], c->gpass_ptr[p + 1] - c->gpass_ptr[p],
                            c->stream));
         return HUB_OK;
     }
     // the velocity-gauge kernels are built for the merged launch only
     if (c->class_policy == HUB_CLASSES_MERGED || c->gauge) {
-        HUB_TRY(launch(HUB_NCLASS + 1, c->d_gall_m, c->gcls_ptr[HUB_NCLASS], c->stream));
+        const int merged = c->T.grouped.nfmax <= 8 ? HUB_MERGED8 : HUB_MERGED16;
+        HUB_TRY(launch(merged, c->d_gall_m, c->gcls_ptr[HUB_NCLASS], c->stream));
         return HUB_OK;
     }
     auto one = [&](int k, hipStream_t s) {
@@ -490,7 +492,7 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
             const int st = run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
                 ProjArgs b = a;
                 b.chunk_list = list;
-                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0, ncol), std::min(4 * k, HUB_GF_MAX));
+                const int cpl = clamp_cpl(c, pick_cpl(c, psi, ld, 0, ncol), hub_cls_nfmax(k));
                 b.wide = pick_wide(c, ncol, cpl, 0);
                 return launch_project(b, nch, nq, c->precision, c->is_complex, cpl, c->tune_waves[0], k, s);
             });
@@ -628,6 +630,56 @@ int do_occupations(hub_ctx* c, const double* cc, int nstates, const double* f, d
     return HUB_OK;
 }
 
+// N-bar, n, P-bar and U-bar, J-bar, U_eff of the batched step in two
+// launches (k_step_occ_part, k_step_occ_final): the same sums in the same
+// order as do_occupations followed by do_acbn0.
+int do_step_occ(hub_ctx* c, const hub_step_io* io) {
+    double* ws = c->ws_fixed ? c->ws_fixed->occ : nullptr;
+    if (!ws) {
+        const int st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, io->nstates), c);
+        if (st) return st;
+        ws = c->d_occ_ws;
+    }
+    OccArgs o{};
+    o.c = io->c;
+    o.f = io->f;
+    o.n = io->n;
+    o.pbar = io->pbar;
+    o.kweights = c->d_kw;
+    o.site_L = c->d_site_L;
+    o.site_orb0 = c->d_site_orb0;
+    o.site_species = c->d_site_species;
+    o.J = c->T.J;
+    o.ncol = c->ncol(io->nstates);
+    o.nstates = io->nstates;
+    o.ncplx = c->ncplx();
+    o.spinor = c->spin_mode == HUB_SPINOR;
+    o.nspin = c->nspin();
+    o.nk = c->nk;
+    o.nblk = c->nblk();
+    o.nspecies = c->T.nspecies;
+    o.nsplit = hub_occ_splits(c->nk, io->nstates);
+    o.ws = ws;
+    o.nsites = c->T.nsites;
+    o.species_orb_ptr = c->d_species_orb_ptr;
+    o.species_orb_ids = c->d_species_orb_ids;
+    o.nbar_out = io->nbar;
+    Acbn0Args u{};
+    u.n = io->n;
+    u.pbar = io->pbar;
+    u.tensor = c->d_tensor;
+    u.site_L = c->d_site_L;
+    u.ueff_fixed = c->d_ueff_fixed;
+    u.U = io->U;
+    u.J = io->J;
+    u.Ueff = io->Ueff;
+    u.status = io->status;
+    u.nblk = c->nblk();
+    StageTimer tm(c, HUB_STAGE_OCC);
+    HUB_TRY(launch_step_occ(o, u, c->stream));
+    return HUB_OK;
+}
+
 bool need_tensors(const hub_ctx* c) {
     for (size_t s = 0; s < c->sites.size(); ++s)
         if (std::isnan(c->sites[s].ueff_fixed) && !c->have_tensor[s]) return true;
@@ -713,7 +765,7 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
         return run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
             ApplyArgs b = a;
             b.chunk_list = list;
-            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1, ncol), std::min(4 * k, HUB_GF_MAX));
+            const int cpl = clamp_cpl(c, pick_cpl(c, hpsi, ld, 1, ncol), hub_cls_nfmax(k));
             return launch_apply_grouped(b, nch, nq, c->precision, c->is_complex, cpl, c->tune_waves[1], k, s);
         }, true);
     }
@@ -753,9 +805,14 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
 int run_step(hub_ctx* c, const hub_step_io* io, bool per_site) {
     int st = do_project(c, io->psi, io->ld, io->nstates, io->c, per_site);
     if (st) return st;
-    st = do_occupations(c, io->c, io->nstates, io->f, io->n, io->pbar, io->nbar, per_site);
-    if (st) return st;
-    st = do_acbn0(c, io->n, io->pbar, io->U, io->J, io->Ueff, io->status, per_site);
+    if (per_site) {
+        // the plain path: one launch per site and stage
+        st = do_occupations(c, io->c, io->nstates, io->f, io->n, io->pbar, io->nbar, true);
+        if (st) return st;
+        st = do_acbn0(c, io->n, io->pbar, io->U, io->J, io->Ueff, io->status, true);
+    } else {
+        st = do_step_occ(c, io);
+    }
     if (st) return st;
     return do_apply(c, io->Ueff, io->n, io->c, io->nstates, nullptr, io->alpha, io->hpsi, io->ldh, per_site);
 }

@@ -309,21 +309,25 @@ __global__ void __launch_bounds__(256) k_apply(const ApplyArgs a, const int32_t*
 // Grouped chunks: L is the number of concatenated functions of the chunk's
 // covering sites, 4(CLS-1) < L <= 4 CLS; every grid point lies in one chunk,
 // so the launches of the classes write disjoint points.
-// CLS = HUB_NCLASS + 1: merged launch over every function count.
+// CLS > HUB_NCLASS: merged launch over every function count up to
+// hub_cls_nfmax(CLS).
 template <typename T, bool CPX, bool SPINOR, int CPL, bool WIDE, int CLS, bool GAUGE>
-__global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const int32_t* __restrict__ gidx,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hub_waves_hint(CLS, CPL * (CPX ? 2 : 1)))))
+k_apply_grouped(const ApplyArgs a, const int32_t* __restrict__ gidx,
                                                        const double* __restrict__ tab, const double* __restrict__ pg,
                                                        T* __restrict__ hpsi) {
     constexpr int NV = CPL * (CPX ? 2 : 1);
-    constexpr int NFMAX = CLS > HUB_NCLASS ? HUB_GF_MAX : 4 * CLS;
+    constexpr int NFMAX = hub_cls_nfmax(CLS);
     __shared__ double Bs[NFMAX * NV * HUB_WAVE];
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
     const HubChunk C = a.chunks[a.chunk_list[slot.chunk]];
 #define HUB_ACALL(n) \
     apply_body<T, CPX, SPINOR, CPL, (n), WIDE, true, GAUGE>(a, C, slot.chunk, slot.tile, gidx, tab, pg, hpsi, Bs)
-#define HUB_ACASE(n) \
-    case n: HUB_ACALL(n); break;
+#define HUB_ACASE(n)                      \
+    case n:                               \
+        if constexpr (n <= NFMAX) HUB_ACALL(n); \
+        break;
     if constexpr (CLS > HUB_NCLASS) {
         switch (C.L) {
             HUB_ACASE(1) HUB_ACASE(2) HUB_ACASE(3) HUB_ACASE(4) HUB_ACASE(5) HUB_ACASE(6) HUB_ACASE(7)
@@ -350,7 +354,7 @@ __global__ void __launch_bounds__(256) k_apply_grouped(const ApplyArgs a, const 
 template <typename T, bool CPX, bool SPINOR, int CPL, int CLS>
 hipError_t launch_tg(const ApplyArgs& a, int nchunks, int nq, int waves, hipStream_t st) {
     // a lane's FP64 coefficients (functions x scalars) stay within 96 values
-    if constexpr ((CLS > HUB_NCLASS ? HUB_GF_MAX : 4 * CLS) * CPL * (CPX ? 2 : 1) > 96) {
+    if constexpr (hub_cls_nfmax(CLS) * CPL * (CPX ? 2 : 1) > 96) {
         return hipErrorInvalidValue;
     } else {
         const int64_t cg = (a.ncol + CPL - 1) / CPL;
@@ -466,7 +470,8 @@ hipError_t launch_apply_grouped_prec(const ApplyArgs& a, int nchunks, int nq, in
     case 2: return launch_kg<T, 2>(a, nchunks, nq, cplx, cpl, waves, st);
     case 3: return launch_kg<T, 3>(a, nchunks, nq, cplx, cpl, waves, st);
     case 4: return launch_kg<T, 4>(a, nchunks, nq, cplx, cpl, waves, st);
-    case HUB_NCLASS + 1: return launch_kg<T, HUB_NCLASS + 1>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_MERGED8: return launch_kg<T, HUB_MERGED8>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_MERGED16: return launch_kg<T, HUB_MERGED16>(a, nchunks, nq, cplx, cpl, waves, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -197,7 +197,8 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
 // the compiler can keep the uniform table reads on scalar loads (a store
 // through a pointer that may alias them would force per-lane loads).
 template <typename T, int NV, int MULT, bool WIDE, int CLS, bool GAUGE>
-__global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t* __restrict__ gidx,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(hub_waves_hint(CLS, NV))))
+k_project(const ProjArgs a, const int32_t* __restrict__ gidx,
                                                  const double* __restrict__ tab, const double* __restrict__ pg,
                                                  double* __restrict__ part) {
     __shared__ ProjLds<NV> lds;
@@ -222,9 +223,13 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
         default: break;
         }
     } else if constexpr (CLS > HUB_NCLASS) {
-        // merged launch: every function count of the grouped list
-#define HUB_PCASE(n) \
-    case n: project_body<T, NV, n, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); break;
+        // merged launch: every function count of the grouped list up to the
+        // class's bound
+        constexpr int NFM = hub_cls_nfmax(CLS);
+#define HUB_PCASE(n)                                                                       \
+    case n:                                                                                \
+        if constexpr (n <= NFM) project_body<T, NV, n, WIDE, GAUGE>(a, C, tile, gidx, tab, pg, part, lds); \
+        break;
         switch (C.L) {
             HUB_PCASE(1) HUB_PCASE(2) HUB_PCASE(3) HUB_PCASE(4) HUB_PCASE(5) HUB_PCASE(6) HUB_PCASE(7)
             HUB_PCASE(8) HUB_PCASE(9) HUB_PCASE(10) HUB_PCASE(11) HUB_PCASE(12) HUB_PCASE(13) HUB_PCASE(14)
@@ -249,7 +254,7 @@ __global__ void __launch_bounds__(256) k_project(const ProjArgs a, const int32_t
 // Largest function count of a class (class 0: per-site chunks, L <= 7; the
 // per-site tables hold MULT functions per orbital).
 constexpr int proj_nf_max(int mult, int cls) {
-    return mult > 1 ? 7 * mult : (cls == 0 ? 7 : (cls > HUB_NCLASS ? HUB_GF_MAX : 4 * cls));
+    return mult > 1 ? 7 * mult : hub_cls_nfmax(cls);
 }
 
 template <typename T, int NV, int MULT, int CLS, bool GAUGE>
@@ -301,7 +306,8 @@ hipError_t launch_g(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, i
 }
 
 // Launch the projection for storage type T (orbital or gradient table) over
-// chunks of function-count class cls (HUB_NCLASS + 1: every class).
+// chunks of function-count class cls (HUB_MERGED8 / HUB_MERGED16: merged
+// launches).
 template <typename T>
 hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
                                hipStream_t st) {
@@ -317,7 +323,8 @@ hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx,
     case 2: return launch_g<T, 1, 2>(a, nchunks, nq, cplx, cpl, waves, st);
     case 3: return launch_g<T, 1, 3>(a, nchunks, nq, cplx, cpl, waves, st);
     case 4: return launch_g<T, 1, 4>(a, nchunks, nq, cplx, cpl, waves, st);
-    case HUB_NCLASS + 1: return launch_g<T, 1, HUB_NCLASS + 1>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_MERGED8: return launch_g<T, 1, HUB_MERGED8>(a, nchunks, nq, cplx, cpl, waves, st);
+    case HUB_MERGED16: return launch_g<T, 1, HUB_MERGED16>(a, nchunks, nq, cplx, cpl, waves, st);
     default: return hipErrorInvalidValue;
     }
 }

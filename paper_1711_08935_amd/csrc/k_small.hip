@@ -52,58 +52,72 @@ __global__ void __launch_bounds__(256) k_reduce(const ReduceArgs a) {
 
 // Grouped work list: out[q][j][col] = dV sum over the workspace rows that
 // belong to orbital j of exp(+i k.T_row) part[q][row][col].  A work-group
-// serves 64 columns of one (j, q); its RW waves take interleaved rows with
-// four independent partial sums each (many loads in flight), and the partial
-// sums are combined in a fixed order.  RW follows the rows per orbital.
-constexpr int RW = 16;   // waves of the N-bar kernel and of the wide reduction
-template <int RW>
+// serves 64 columns of one (j, q); each of its RW waves takes a contiguous
+// range of the orbital's rows and walks it in batches of 8: the batch's row
+// indexes and images are uniform (scalar loads), its 8 row values are in
+// flight together (one 8- or 16-byte load per lane each), then added in row
+// order.  The waves' sums are combined in wave order through LDS.  RW
+// follows the rows per orbital.
+template <int RW, int NC>
 __global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedArgs a) {
+    constexpr int NBATCH = 8;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = blockIdx.x * 64 + lane;
     const int j = blockIdx.y;
     const int q = blockIdx.z;
     const bool active = col < a.ncol;
-    const int NC = a.ncplx;
     const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
-    const double* ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
+    const double* __restrict__ ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     // spin-dependent orbitals: spinor column 2s + sigma reads the rows of the
     // orbital of its spin component
     const int64_t shift = (a.spin_shift && (col & 1)) ? a.spin_shift[j] : 0;
-    const double* base = a.part + (static_cast<int64_t>(q) * a.prows + shift) * a.ncol * NC +
-                         static_cast<int64_t>(active ? col : 0) * NC;
-    double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* __restrict__ base = a.part + (static_cast<int64_t>(q) * a.prows + shift) * a.ncol * NC +
+                                      static_cast<int64_t>(active ? col : 0) * NC;
     const int t0 = a.red_ptr[j], t1 = a.red_ptr[j + 1];
-    int t = t0 + wave;
-    for (; t + 3 * RW < t1; t += 4 * RW) {
+    int lo, len;
+    hub_wave_range(t1 - t0, RW, wave, lo, len);
+    const int32_t* __restrict__ rows = a.red_row + t0 + lo;
+    const int32_t* __restrict__ imgs = a.red_img + t0 + lo;
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = 0; b < len; b += NBATCH) {
+        const int nb = len - b < NBATCH ? len - b : NBATCH;
+        double v[NBATCH][NC];
+        double pr[NBATCH], pi[NBATCH];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int tt = t + u * RW;
-            const double* p = base + static_cast<int64_t>(a.red_row[tt]) * a.ncol * NC;
-            if (NC == 2) {
-                const int im = a.red_img[tt];
-                const double pr = ph[2 * im], pi = ph[2 * im + 1];
-                s0[u] += pr * p[0] - pi * p[1];
-                s1[u] += pr * p[1] + pi * p[0];
+        for (int u = 0; u < NBATCH; ++u) {
+            // rows past the wave's range re-read its last row; their values
+            // are replaced by zeros below (branch-free, so that every load of
+            // the batch is issued before the first add)
+            const int t = b + (u < nb ? u : nb - 1);
+            const double* p = base + static_cast<int64_t>(rows[t]) * a.ncol * NC;
+            if constexpr (NC == 2) {
+                const hub_d2 x = *reinterpret_cast<const hub_d2*>(p);
+                v[u][0] = x[0];
+                v[u][1] = x[1];
+                const int im = imgs[t];
+                pr[u] = ph[2 * im];
+                pi[u] = ph[2 * im + 1];
             } else {
-                s0[u] += p[0];
+                v[u][0] = p[0];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NBATCH; ++u) {
+            const bool use = u < nb;
+            if constexpr (NC == 2) {
+                const double x0 = use ? v[u][0] : 0.0, x1 = use ? v[u][1] : 0.0;
+                s0 += pr[u] * x0 - pi[u] * x1;
+                s1 += pr[u] * x1 + pi[u] * x0;
+            } else {
+                s0 += use ? v[u][0] : 0.0;
             }
         }
     }
-    for (; t < t1; t += RW) {
-        const double* p = base + static_cast<int64_t>(a.red_row[t]) * a.ncol * NC;
-        if (NC == 2) {
-            const int im = a.red_img[t];
-            const double pr = ph[2 * im], pi = ph[2 * im + 1];
-            s0[0] += pr * p[0] - pi * p[1];
-            s1[0] += pr * p[1] + pi * p[0];
-        } else {
-            s0[0] += p[0];
-        }
-    }
     __shared__ double red[RW][64][2];
-    red[wave][lane][0] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
-    red[wave][lane][1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    red[wave][lane][0] = s0;
+    red[wave][lane][1] = s1;
     __syncthreads();
     if (wave != 0 || !active) return;
     double r0 = 0.0, r1 = 0.0;
@@ -117,42 +131,69 @@ __global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedA
 }
 
 // ---------------------------------------------------------------- N-bar
-// nbar[q][T][s] = sum_{j in species T} sum_{columns of s} |c[q][j][col]|^2.
-// A work-group serves 64 states of one (T, q); its RW waves take
-// interleaved orbitals with four independent sums each, combined in order.
-__global__ void __launch_bounds__(RW * 64) k_nbar(const NbarArgs a) {
+// nbar[q][T][s] = sum_{j in species T} sum_{columns of s} |c[q][j][col]|^2
+// (Eq. notation_Nbar).  The species' orbitals are split into NBPART
+// interleaved parts, each summed in order; the parts are combined as
+// (p0 + p1) + (p2 + p3).  k_nbar and the fused occupation kernel of the step
+// use exactly this order, so both give the same N-bar to the last bit.
+constexpr int NBPART = 4;
+
+// part ``part`` of N-bar for state s of set q: the species' orbitals
+// ids[t], t = t0 + part, t0 + part + NBPART, ... < t1, added in that order.
+// The orbitals are taken in batches of 8 whose values are all loaded before
+// the first add (orbitals past t1 re-read the batch's first one and add 0),
+// so a long species list costs a few load latencies, not one per orbital.
+template <int NC, int CPS>
+__device__ __forceinline__ double nbar_part_t(const double* __restrict__ c, const int32_t* __restrict__ ids, int t0,
+                                              int t1, int part, int64_t qbase, int s, int ncol) {
+    constexpr int NB8 = 8;
+    const double* cq = c + qbase + static_cast<int64_t>(s) * CPS * NC;
+    double acc = 0.0;
+    for (int t = t0 + part; t < t1; t += NB8 * NBPART) {
+        double r[NB8][CPS * NC];
+#pragma unroll
+        for (int u = 0; u < NB8; ++u) {
+            const int tt = t + u * NBPART < t1 ? t + u * NBPART : t;
+            const double* p = cq + static_cast<int64_t>(ids[tt]) * ncol * NC;
+#pragma unroll
+            for (int x = 0; x < CPS * NC; ++x) r[u][x] = p[x];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NB8; ++u) {
+            double v = 0.0;
+#pragma unroll
+            for (int x = 0; x < CPS * NC; ++x) v = fma(r[u][x], r[u][x], v);
+            acc += t + u * NBPART < t1 ? v : 0.0;
+        }
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double nbar_part(const double* __restrict__ c, const int32_t* __restrict__ ids, int t0,
+                                            int t1, int part, int64_t qbase, int s, int ncol, int NC, int cps) {
+    if (NC == 2)
+        return cps == 2 ? nbar_part_t<2, 2>(c, ids, t0, t1, part, qbase, s, ncol)
+                        : nbar_part_t<2, 1>(c, ids, t0, t1, part, qbase, s, ncol);
+    return nbar_part_t<1, 1>(c, ids, t0, t1, part, qbase, s, ncol);
+}
+
+// A work-group serves 64 states of one (T, q): wave w sums part w.
+__global__ void __launch_bounds__(NBPART * 64) k_nbar(const NbarArgs a) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int s = blockIdx.x * 64 + lane;
     const int T = blockIdx.y;
     const int q = blockIdx.z;
     const bool active = s < a.nstates;
     const int NC = a.ncplx;
-    const int cps = a.spinor ? 2 : 1;
-    const double* cq = a.c + static_cast<int64_t>(q) * a.J * a.ncol * NC + static_cast<int64_t>(active ? s : 0) * cps * NC;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int t0 = a.species_orb_ptr[T], t1 = a.species_orb_ptr[T + 1];
-    int t = t0 + wave;
-    auto term = [&](int tt) {
-        const double* p = cq + static_cast<int64_t>(a.species_orb_ids[tt]) * a.ncol * NC;
-        double v = 0.0;
-        for (int x = 0; x < cps; ++x) {
-            v = fma(p[x * NC], p[x * NC], v);
-            if (NC == 2) v = fma(p[x * NC + 1], p[x * NC + 1], v);
-        }
-        return v;
-    };
-    for (; t + 3 * RW < t1; t += 4 * RW) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += term(t + u * RW);
-    }
-    for (; t < t1; t += RW) acc[0] += term(t);
-    __shared__ double red[RW][64];
-    red[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __shared__ double red[NBPART][64];
+    red[wave][lane] = nbar_part(a.c, a.species_orb_ids, a.species_orb_ptr[T], a.species_orb_ptr[T + 1], wave,
+                                static_cast<int64_t>(q) * a.J * a.ncol * NC, active ? s : 0, a.ncol, NC,
+                                a.spinor ? 2 : 1);
     __syncthreads();
     if (wave != 0 || !active) return;
-    double r = 0.0;
-    for (int w = 0; w < RW; ++w) r += red[w][lane];
+    const double r = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     a.nbar[(static_cast<int64_t>(q) * a.nspecies + T) * a.nstates + s] = r;
 }
 
@@ -250,44 +291,71 @@ __global__ void __launch_bounds__(NB) k_occ_part(const OccArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(NB) k_occ_final(const OccArgs a) {
-    const int site = blockIdx.x;
-    const int ch = blockIdx.y;
-    const int nchan = gridDim.y;
+// Sums the splits of one site and channel in order: out = n and P-bar
+// entries (blocks of the channel, zeros outside the L x L corner), one
+// thread per (entry, value) so that every split's load is in flight.
+__device__ void occ_final_sums(const OccArgs& a, int site, int ch, int nchan, double* n, double* pbar,
+                               double (*Nf)[7][7][2], double (*P)[7][7][2]) {
     const int L = a.site_L[site];
     const int ncp = a.spinor ? 2 * L : L;
     const double* w = a.ws + (static_cast<int64_t>(site) * nchan + ch) * a.nsplit * (HUB_OCC_PAIRS * 4);
-    // write all blocks of this channel (zeros outside the L x L corner)
     const int nblk_here = a.spinor ? 4 : 1;
-    for (int o = threadIdx.x; o < nblk_here * 49; o += NB) {
-        const int blk = o / 49, e = o % 49, i = e / 7, j = e % 7;
-        double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int o = threadIdx.x; o < nblk_here * 49 * 4; o += NB) {
+        const int r = o & 3, eb = o >> 2;
+        const int blk = eb / 49, e = eb % 49, i = e / 7, j = e % 7;
+        double v = 0.0;
         if (i < L && j < L) {
             const int x = a.spinor ? blk / 2 : 0, y = a.spinor ? blk % 2 : 0;
             const int p = (x * L + i) * ncp + (y * L + j);
-            for (int z = 0; z < a.nsplit; ++z)
-                for (int r = 0; r < 4; ++r) v[r] += w[(static_cast<int64_t>(z) * HUB_OCC_PAIRS + p) * 4 + r];
+            const double* wp = w + static_cast<int64_t>(p) * 4 + r;
+            // splits in batches of 8, every load of a batch issued before
+            // the adds, which run in split order (splits past the end add 0)
+            for (int z0 = 0; z0 < a.nsplit; z0 += 8) {
+                double t[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int z = z0 + u < a.nsplit ? z0 + u : z0;
+                    t[u] = wp[static_cast<int64_t>(z) * HUB_OCC_PAIRS * 4];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += z0 + u < a.nsplit ? t[u] : 0.0;
+            }
         }
         const int oblk = a.spinor ? blk : ch;
         const int64_t base = ((static_cast<int64_t>(site) * a.nblk + oblk) * 49 + e) * 2;
-        a.n[base] = v[0];
-        a.n[base + 1] = v[1];
-        if (a.pbar != nullptr) {
-            a.pbar[base] = v[2];
-            a.pbar[base + 1] = v[3];
+        if (r < 2) {
+            n[base + r] = v;
+            if (Nf) Nf[oblk][i][j][r] = v;
+        } else {
+            if (pbar) pbar[base + r - 2] = v;
+            if (P) P[oblk][i][j][r - 2] = v;
         }
     }
+}
+
+__global__ void __launch_bounds__(NB) k_occ_final(const OccArgs a) {
+    occ_final_sums(a, blockIdx.x, blockIdx.y, gridDim.y, a.n, a.pbar, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------- ACBN0
 // U-bar and J-bar of one site (Eqs. ACBN0_U, ACBN0_J; App. B), with the
 // numerators read as P_mm' P_m''m''' (mm'|m''m''') and P_mm' P_m''m'''
 // (mm'''|m''m'), denominators from the bare diagonal occupations.
-__global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
-    const int site = blockIdx.x;
+// The site's P-bar and n blocks ([blk][7][7] complex) are in LDS.
+struct AcbLds {
+    double P[4][7][7][2];
+    double Nf[4][7][7][2];
+    double Ts[2401];
+    double redU[NB], redJ[NB];
+};
+
+// tensor_in_lds: the caller has already put the site's tensor in sm.Ts.
+__device__ void acbn0_site(const Acbn0Args& a, int site, AcbLds& sm, bool tensor_in_lds = false) {
     const int L = a.site_L[site];
     const int tid = threadIdx.x;
     const double fixed = a.ueff_fixed[site];
+    __syncthreads();                          // P and Nf written by the caller
     if (!isnan(fixed)) {
         if (tid == 0) {
             a.U[site] = fixed;
@@ -296,44 +364,38 @@ __global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
             if (a.status) {
                 // flag occupations that are not finite (NaN or Inf in the states)
                 bool finite = true;
-                const double* nb0 = a.n + static_cast<int64_t>(site) * a.nblk * 98;
                 for (int b = 0; b < a.nblk; ++b)
-                    for (int e = 0; e < L * L; ++e) {
-                        const int64_t o = b * 98 + ((e / L) * 7 + e % L) * 2;
-                        finite = finite && isfinite(nb0[o]) && isfinite(nb0[o + 1]);
-                    }
+                    for (int e = 0; e < L * L; ++e)
+                        finite = finite && isfinite(sm.Nf[b][e / L][e % L][0]) && isfinite(sm.Nf[b][e / L][e % L][1]);
                 a.status[site] = finite ? 0 : HUB_ENONFINITE;
             }
         }
         return;
     }
-    __shared__ double P[4][7][7][2];
-    __shared__ double Nd[4][7][2];
-    __shared__ double Ts[2401];
-    __shared__ double redU[NB], redJ[NB];
+    auto& P = sm.P;
+    auto& Ts = sm.Ts;
+    auto& redU = sm.redU;
+    auto& redJ = sm.redJ;
     const int nb = a.nblk;
-    for (int o = tid; o < nb * 49; o += NB) {
-        const int b = o / 49, e = o % 49;
-        const int64_t base = ((static_cast<int64_t>(site) * nb + b) * 49 + e) * 2;
-        P[b][e / 7][e % 7][0] = a.pbar[base];
-        P[b][e / 7][e % 7][1] = a.pbar[base + 1];
-        if (e / 7 == e % 7) {
-            Nd[b][e / 7][0] = a.n[base];
-            Nd[b][e / 7][1] = a.n[base + 1];
-        }
-    }
     const int L2 = L * L, L4 = L2 * L2;
-    const double* Tg = a.tensor + static_cast<int64_t>(site) * 2401;
-    for (int o = tid; o < L4; o += NB) Ts[o] = Tg[o];
-    __syncthreads();
+    if (!tensor_in_lds) {
+        const double* Tg = a.tensor + static_cast<int64_t>(site) * 2401;
+        for (int o = tid; o < L4; o += NB) Ts[o] = Tg[o];
+        __syncthreads();
+    }
 
     // channel layout: unpolarized -> both channels are block 0
     const int c0 = 0;
     const int c1 = (nb == 2) ? 1 : (nb == 4 ? 3 : 0);
     double su = 0.0, sj = 0.0;
+    // o = ((A L + B) L + C) L + D; quotients by L2 and L through a float
+    // reciprocal: (o + 0.5) / L2 stays at least 0.5 / 49 from an integer, far
+    // above the reciprocal's rounding for o < 2401
+    const float rL = 1.0f / static_cast<float>(L), rL2 = 1.0f / static_cast<float>(L2);
     for (int o = tid; o < L4; o += NB) {
-        const int ab = o / L2, cd = o % L2;
-        const int A = ab / L, B = ab % L, Cc = cd / L, D = cd % L;
+        const int ab = static_cast<int>((static_cast<float>(o) + 0.5f) * rL2), cd = o - ab * L2;
+        const int A = static_cast<int>((static_cast<float>(ab) + 0.5f) * rL), B = ab - A * L;
+        const int Cc = static_cast<int>((static_cast<float>(cd) + 0.5f) * rL), D = cd - Cc * L;
         const double t_abcd = Ts[o];
         const double t_adcb = Ts[((A * L + D) * L + Cc) * L + B];
         // numerator U: sum_{alpha beta} P^a_ab P^b_cd (ab|cd) = Re(Ps_ab Ps_cd) (ab|cd)
@@ -355,24 +417,28 @@ __global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
             sj = fma(v, t_adcb, sj);
         }
     }
-    redU[tid] = su;
-    redJ[tid] = sj;
-    __syncthreads();
-    for (int w = NB / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            redU[tid] += redU[tid + w];
-            redJ[tid] += redJ[tid + w];
-        }
-        __syncthreads();
+    // sum over the lanes of each wave (butterfly), then the waves in order
+    for (int m = 32; m >= 1; m >>= 1) {
+        su += __shfl_xor(su, m, 64);
+        sj += __shfl_xor(sj, m, 64);
     }
+    if ((tid & 63) == 0) {
+        redU[tid >> 6] = su;
+        redJ[tid >> 6] = sj;
+    }
+    __syncthreads();
     if (tid != 0) return;
+    for (int w = 1; w < NB / 64; ++w) {
+        redU[0] += redU[w];
+        redJ[0] += redJ[w];
+    }
     double dU = 0.0, dJ = 0.0;
     if (nb != 4) {
         // collinear: N^alpha_m = n^alpha_mm (real part)
         double N[2][7];
         for (int m = 0; m < L; ++m) {
-            N[0][m] = Nd[c0][m][0];
-            N[1][m] = Nd[c1][m][0];
+            N[0][m] = sm.Nf[c0][m][m][0];
+            N[1][m] = sm.Nf[c1][m][m][0];
         }
         for (int al = 0; al < 2; ++al)
             for (int m = 0; m < L; ++m)
@@ -385,7 +451,7 @@ __global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
     } else {
         // spinor (App. B): complex diagonal blocks N^{xy}_m = n^{xy}_mm
         auto re_mul = [&](int b1, int m1, int b2, int m2) {
-            return Nd[b1][m1][0] * Nd[b2][m2][0] - Nd[b1][m1][1] * Nd[b2][m2][1];
+            return sm.Nf[b1][m1][m1][0] * sm.Nf[b2][m2][m2][0] - sm.Nf[b1][m1][m1][1] * sm.Nf[b2][m2][m2][1];
         };
         for (int s = 0; s < 2; ++s) {
             const int ss = 3 * s, oo = 3 * (1 - s), so = 2 * s + (1 - s), os = 2 * (1 - s) + s;
@@ -413,6 +479,171 @@ __global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
     a.J[site] = J;
     a.Ueff[site] = U - J;
     if (a.status) a.status[site] = st;
+}
+
+__global__ void __launch_bounds__(NB) k_acbn0(const Acbn0Args a) {
+    const int site = blockIdx.x;
+    __shared__ AcbLds sm;
+    for (int o = threadIdx.x; o < a.nblk * 49; o += NB) {
+        const int b = o / 49, e = o % 49;
+        const int64_t base = ((static_cast<int64_t>(site) * a.nblk + b) * 49 + e) * 2;
+        sm.P[b][e / 7][e % 7][0] = a.pbar[base];
+        sm.P[b][e / 7][e % 7][1] = a.pbar[base + 1];
+        sm.Nf[b][e / 7][e % 7][0] = a.n[base];
+        sm.Nf[b][e / 7][e % 7][1] = a.n[base + 1];
+    }
+    acbn0_site(a, site, sm);
+}
+
+// ---------------------------------------------------------------- fused step
+// N-bar, n, P-bar and U-bar/J-bar of the batched step in two launches.
+// k_step_occ_part: work-group (site, channel, split) stages the c of its
+// (k-point, state) pairs tile by tile, forms N-bar of each pair from the
+// species' projections (nbar_part: the order of k_nbar; the first site of a
+// species writes it out) and sums its split of n and P-bar as k_occ_part
+// does.  k_step_occ_final: one work-group per site sums every split of every
+// channel in order (as k_occ_final), writes n and P-bar and runs the site's
+// ACBN0 step from LDS (acbn0_site).  The kernel boundary orders the two; a
+// completion count inside one launch was measured slower, since every
+// work-group's device-scope release then writes back its L2.
+struct OccLds {
+    double cs[2][7][TILE][2];
+    double wt[TILE], wtn[TILE];
+    double red[NB][4];
+    double nbp[NBPART][TILE];
+};
+
+__global__ void __launch_bounds__(NB) k_step_occ_part(const OccArgs a) {
+    const int site = blockIdx.x;
+    const int ch = blockIdx.y;
+    const int split = blockIdx.z;
+    const int nchan = gridDim.y;
+    const int L = a.site_L[site];
+    const int orb0 = a.site_orb0[site];
+    const int T = a.site_species[site];
+    const int NC = a.ncplx;
+    const int nsig = a.spinor ? 2 : 1;
+    const int ncp = a.spinor ? 2 * L : L;
+    const int npairs = ncp * ncp;
+    const int nslice = NB / npairs;
+    const int tid = threadIdx.x;
+    const int pair = tid % npairs;
+    const int slice = tid / npairs;
+    const bool worker = slice < nslice;
+    const int ra = pair / ncp, rb = pair % ncp;
+
+    __shared__ struct {
+        OccLds o;
+    } sm;
+
+    // the first site of each species writes that species' N-bar
+    bool writer = a.nbar_out != nullptr;
+    for (int s2 = 0; s2 < site && writer; ++s2) writer = a.site_species[s2] != T;
+    const int sp0 = a.species_orb_ptr[T], sp1 = a.species_orb_ptr[T + 1];
+
+    const int np = a.nk * a.nstates;
+    const int per = (np + a.nsplit - 1) / a.nsplit;
+    const int p0 = split * per;
+    const int p1 = min(np, p0 + per);
+    double nr = 0.0, ni = 0.0, pr = 0.0, pi = 0.0;
+    for (int t0 = p0; t0 < p1; t0 += TILE) {
+        const int pp = t0 + tid;
+        if (tid < TILE) {
+            if (pp < p1) {
+                const int k = pp / a.nstates, s = pp - k * a.nstates;
+                const int q = a.spinor ? k : k * a.nspin + ch;
+                sm.o.wt[tid] = a.kweights[k] * a.f[static_cast<int64_t>(q) * a.nstates + s];
+                for (int x = 0; x < nsig; ++x)
+                    for (int m = 0; m < L; ++m) {
+                        const double* p =
+                            a.c + ((static_cast<int64_t>(q) * a.J + orb0 + m) * a.ncol + s * nsig + x) * NC;
+                        sm.o.cs[x][m][tid][0] = p[0];
+                        sm.o.cs[x][m][tid][1] = (NC == 2) ? p[1] : 0.0;
+                    }
+            } else {
+                sm.o.wt[tid] = 0.0;
+                for (int x = 0; x < nsig; ++x)
+                    for (int m = 0; m < L; ++m) sm.o.cs[x][m][tid][0] = sm.o.cs[x][m][tid][1] = 0.0;
+            }
+        }
+        {
+            // N-bar of the tile's pairs: part tid / TILE (one wave each) of pair tid % TILE
+            static_assert(TILE == 64 && NB == NBPART * TILE, "one N-bar part per wave");
+            const int pl = tid % TILE, part = __builtin_amdgcn_readfirstlane(tid / TILE);
+            const int pq = t0 + pl;
+            double v = 0.0;
+            if (pq < p1) {
+                const int k = pq / a.nstates, s = pq - k * a.nstates;
+                const int q = a.spinor ? k : k * a.nspin + ch;
+                v = nbar_part(a.c, a.species_orb_ids, sp0, sp1, part, static_cast<int64_t>(q) * a.J * a.ncol * NC, s,
+                              a.ncol, NC, nsig);
+            }
+            sm.o.nbp[part][pl] = v;
+        }
+        __syncthreads();
+        if (tid < TILE) {
+            const double nb = (sm.o.nbp[0][tid] + sm.o.nbp[1][tid]) + (sm.o.nbp[2][tid] + sm.o.nbp[3][tid]);
+            sm.o.wtn[tid] = sm.o.wt[tid] * nb;
+            if (a.nbar_out != nullptr && pp < p1) {
+                const int k = pp / a.nstates, s = pp - k * a.nstates;
+                const int q = a.spinor ? k : k * a.nspin + ch;
+                double* out = a.nbar_out + static_cast<int64_t>(q) * a.nspecies * a.nstates + s;
+                if (writer) out[static_cast<int64_t>(T) * a.nstates] = nb;
+                // species ids without a site: N-bar 0 (written by site 0)
+                if (site == 0)
+                    for (int T2 = 0; T2 < a.nspecies; ++T2)
+                        if (a.species_orb_ptr[T2] == a.species_orb_ptr[T2 + 1])
+                            out[static_cast<int64_t>(T2) * a.nstates] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (worker) {
+            const int xa = ra / L, ma = ra % L, xb = rb / L, mb = rb % L;
+            const int nt = min(TILE, p1 - t0);
+            for (int t = slice; t < nt; t += nslice) {
+                const double ar = sm.o.cs[xa][ma][t][0], ai = sm.o.cs[xa][ma][t][1];
+                const double br = sm.o.cs[xb][mb][t][0], bi = sm.o.cs[xb][mb][t][1];
+                const double re = ar * br + ai * bi;
+                const double im = ar * bi - ai * br;
+                nr = fma(sm.o.wt[t], re, nr);
+                ni = fma(sm.o.wt[t], im, ni);
+                pr = fma(sm.o.wtn[t], re, pr);
+                pi = fma(sm.o.wtn[t], im, pi);
+            }
+        }
+        __syncthreads();
+    }
+    sm.o.red[tid][0] = nr;
+    sm.o.red[tid][1] = ni;
+    sm.o.red[tid][2] = pr;
+    sm.o.red[tid][3] = pi;
+    __syncthreads();
+    {
+        double* w = a.ws + ((static_cast<int64_t>(site) * nchan + ch) * a.nsplit + split) * (HUB_OCC_PAIRS * 4);
+        for (int o = tid; o < npairs; o += NB) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int z = 0; z < nslice; ++z)
+                for (int r = 0; r < 4; ++r) v[r] += sm.o.red[z * npairs + o][r];
+            for (int r = 0; r < 4; ++r) w[o * 4 + r] = v[r];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NB) k_step_occ_final(const OccArgs a, const Acbn0Args u) {
+    const int site = blockIdx.x;
+    const int nchan = a.spinor ? 1 : a.nspin;
+    __shared__ AcbLds sm;
+    // the site's tensor first: its loads overlap the sums below
+    const bool tens = isnan(u.ueff_fixed[site]);
+    if (tens) {
+        const int L = a.site_L[site];
+        const double* Tg = u.tensor + static_cast<int64_t>(site) * 2401;
+#pragma unroll 4
+        for (int o = threadIdx.x; o < L * L * L * L; o += NB) sm.Ts[o] = Tg[o];
+    }
+    for (int ch = 0; ch < nchan; ++ch) occ_final_sums(a, site, ch, nchan, a.n, a.pbar, sm.Nf, sm.P);
+    __syncthreads();
+    acbn0_site(u, site, sm, tens);
 }
 
 // ---------------------------------------------------------------- energy
@@ -650,17 +881,21 @@ hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t
     if (a.J <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
     dim3 grid((a.ncol + 63) / 64, a.J, nq);
     // many rows per orbital (overlapping spheres, small chunks): 16 waves
-    if (a.rows_per_orbital >= 64)
-        hipLaunchKernelGGL(k_reduce_grouped<16>, grid, dim3(16 * 64), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_reduce_grouped<4>, grid, dim3(4 * 64), 0, st, a);
+    const bool wide = a.rows_per_orbital >= 64;
+    if (a.ncplx == 2) {
+        if (wide) hipLaunchKernelGGL((k_reduce_grouped<16, 2>), grid, dim3(16 * 64), 0, st, a);
+        else hipLaunchKernelGGL((k_reduce_grouped<4, 2>), grid, dim3(4 * 64), 0, st, a);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_reduce_grouped<16, 1>), grid, dim3(16 * 64), 0, st, a);
+        else hipLaunchKernelGGL((k_reduce_grouped<4, 1>), grid, dim3(4 * 64), 0, st, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_nbar(const NbarArgs& a, int nq, hipStream_t st) {
     if (a.nstates <= 0 || nq <= 0) return hipSuccess;
     dim3 grid((a.nstates + 63) / 64, a.nspecies, nq);
-    hipLaunchKernelGGL(k_nbar, grid, dim3(RW * 64), 0, st, a);
+    hipLaunchKernelGGL(k_nbar, grid, dim3(NBPART * 64), 0, st, a);
     return hipGetLastError();
 }
 
@@ -674,6 +909,15 @@ hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st) {
     const int nchan = a.spinor ? 1 : a.nspin;
     hipLaunchKernelGGL(k_occ_part, dim3(nsites, nchan, a.nsplit), dim3(NB), 0, st, b);
     hipLaunchKernelGGL(k_occ_final, dim3(nsites, nchan), dim3(NB), 0, st, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_occ(const OccArgs& a, const Acbn0Args& u, hipStream_t st) {
+    const int nsites = static_cast<int>(a.nsites);
+    if (nsites <= 0) return hipSuccess;
+    const int nchan = a.spinor ? 1 : a.nspin;
+    hipLaunchKernelGGL(k_step_occ_part, dim3(nsites, nchan, a.nsplit), dim3(NB), 0, st, a);
+    hipLaunchKernelGGL(k_step_occ_final, dim3(nsites), dim3(NB), 0, st, a, u);
     return hipGetLastError();
 }
 

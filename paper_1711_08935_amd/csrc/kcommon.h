@@ -183,6 +183,20 @@ __host__ __device__ constexpr int hub_batch_rows(int nv, int nf) {
 #define HUB_NCLASS 4
 static_assert(HUB_GF_MAX == 4 * HUB_NCLASS, "the classes cover every grouped function count");
 __host__ __device__ constexpr int hub_nf_class(int nf) { return (nf + 3) / 4; }
+// Merged launches cover the chunks of every function count up to a bound:
+// class HUB_NCLASS + m holds NF 1..4m; the kernels are built for m = 2 (a
+// work list whose points carry at most 8 functions: registers sized for 8)
+// and m = 4 (every grouped chunk).
+#define HUB_MERGED8 (HUB_NCLASS + 2)
+#define HUB_MERGED16 (HUB_NCLASS + 4)
+// Waves per SIMD asked of the compiler for a merged kernel: the launches
+// bounded at 8 functions with up to 4 values per lane fit in 128 registers,
+// which gives four waves per SIMD; 1 leaves the allocation free.
+__host__ __device__ constexpr int hub_waves_hint(int cls, int nv) { return cls == HUB_NCLASS + 2 && nv <= 4 ? 4 : 1; }
+// largest function count of a launch class (0: per-site chunks, L <= 7)
+__host__ __device__ constexpr int hub_cls_nfmax(int cls) {
+    return cls > HUB_NCLASS ? 4 * (cls - HUB_NCLASS) : (cls == 0 ? 7 : 4 * cls);
+}
 
 // Work-groups are dispatched to the XCDs round-robin (work-group w runs on
 // XCD w mod 8), and each XCD has its own L2.  The 1-D launch grid maps w to

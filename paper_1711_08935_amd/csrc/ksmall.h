@@ -49,6 +49,10 @@ struct OccArgs {
     int J; int ncol; int nstates; int ncplx; int spinor; int nspin; int nk; int nblk; int nspecies;
     int nsplit;               // (k-point, state) splits of the first pass
     double* ws;               // [site][channel][nsplit][HUB_OCC_PAIRS][4] partial sums
+    // batched step kernels (k_step_occ_part / k_step_occ_final) only:
+    int nsites;
+    const int32_t* species_orb_ptr; const int32_t* species_orb_ids;   // N-bar from c
+    double* nbar_out;         // [q][species][nstates] or null
 };
 
 // (k-point, state) splits of the occupation sums: about 64 pairs each
@@ -113,6 +117,8 @@ hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t
 hipError_t launch_nbar(const NbarArgs& a, int nq, hipStream_t st);
 hipError_t launch_occ(const OccArgs& a, int site0, int nsites, hipStream_t st);
 hipError_t launch_acbn0(const Acbn0Args& a, int site0, int nsites, hipStream_t st);
+// N-bar, n, P-bar, U-bar, J-bar, U_eff of every site in two launches (batched step)
+hipError_t launch_step_occ(const OccArgs& a, const Acbn0Args& u, hipStream_t st);
 hipError_t launch_energy(const EnergyArgs& a, hipStream_t st);
 hipError_t launch_forces(const ForceArgs& a, hipStream_t st);
 hipError_t launch_fll(const FllArgs& a, hipStream_t st);
