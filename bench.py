@@ -31,6 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+# velocity-gauge runs: no current; the current from the step's own
+# projection pass (hub_step_current); the current as a call of its own after
+# the step (hub_current)
+GAUGE_RUNS = (("gauge_steps_per_s", None), ("gauge_current_steps_per_s", "step"),
+              ("gauge_current_separate_steps_per_s", "separate"))
 # sources of the projection and apply kernels (the counter files record
 # their hash: traffic measured on other sources is not reported)
 KERNEL_SOURCES = ["kcommon.h", "k_project.h", "k_project_f32.hip", "k_project_f64.hip", "k_apply.h",
@@ -305,12 +310,13 @@ def side_summary(name, args):
                                               for k in ("reduce", "nbar", "occupations", "acbn0")), 1)
     if cfg.is_complex and not args.no_gauge:
         A0 = np.array([0.05, 0.02, 0.0])
-        for with_current in (False, True):
+        jcur = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+        for key, with_current in GAUGE_RUNS:
             def run(nsteps, i0):
                 for i in range(nsteps):
                     hub.set_vector_potential(A0 * np.sin(0.1 * (i0 + i)))
-                    hub.step(psi, f_d, h, mode="graph", bufs=bufs)
-                    if with_current:
+                    hub.step(psi, f_d, h, mode="graph", bufs=bufs, current=jcur if with_current == "step" else None)
+                    if with_current == "separate":
                         hub.current(psi, bufs["c"], f_d, bufs["Ueff"], bufs["n"])
             run(3, 0)
             torch.cuda.synchronize()
@@ -319,7 +325,6 @@ def side_summary(name, args):
             run(args.steps, 3)
             e1.record()
             torch.cuda.synchronize()
-            key = "gauge_current_steps_per_s" if with_current else "gauge_steps_per_s"
             out[key] = round(args.steps / (e0.elapsed_time(e1) * 1e-3), 2)
         hub.set_vector_potential(None)
     log(f"side workload: {out}")
@@ -454,15 +459,18 @@ def main():
         def field(i):
             return A0 * np.sin(0.1 * i)
 
+        jcur = torch.empty((hub32.nsites, 3), dtype=torch.float64, device="cuda")
+
         def run(nsteps, with_current, i0):
             for i in range(nsteps):
                 hub32.set_vector_potential(field(i0 + i))
-                hub32.step(psi32, f_d, hpsi32, mode="graph", bufs=bufs32)
-                if with_current:
+                hub32.step(psi32, f_d, hpsi32, mode="graph", bufs=bufs32,
+                           current=jcur if with_current == "step" else None)
+                if with_current == "separate":
                     hub32.current(psi32, bufs32["c"], f_d, bufs32["Ueff"], bufs32["n"])
 
         gauge = {}
-        for with_current in (False, True):
+        for key, with_current in GAUGE_RUNS:
             run(3, with_current, 0)
             torch.cuda.synchronize()
             ge0, ge1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -470,7 +478,6 @@ def main():
             run(args.steps, with_current, 3)
             ge1.record()
             torch.cuda.synchronize()
-            key = "gauge_current_steps_per_s" if with_current else "gauge_steps_per_s"
             gauge[key] = round(args.steps / (ge0.elapsed_time(ge1) * 1e-3), 2)
         # per-stage times under a field (batched steps, library HIP events)
         hub32.set_vector_potential(A0)
@@ -478,6 +485,13 @@ def main():
         for _ in range(max(5, min(args.steps, 30))):
             hub32.step(psi32, f_d, hpsi32, mode="batched", bufs=bufs32)
         gprof = hub32.profile_read()
+        # and with the current taken in the step's projection pass: every
+        # stage's average time per step (ms)
+        for _ in range(max(5, min(args.steps, 30))):
+            hub32.step(psi32, f_d, hpsi32, mode="batched", bufs=bufs32, current=jcur)
+        cprof = hub32.profile_read()
+        gauge["current_step_stage_ms"] = {k: round(v[0] / max(5, min(args.steps, 30)), 4)
+                                          for k, v in cprof.items() if v[1]}
         hub32.profile(False)
         hub32.set_vector_potential(None)
         log(f"velocity gauge: {gauge}")

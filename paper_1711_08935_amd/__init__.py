@@ -50,7 +50,7 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
            "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
            "hub_energy_fll", "hub_set_site_spin_orbital", "hub_project_sets", "hub_apply_sets",
-           "hub_energy_gradient", "hub_step_noalloc"]
+           "hub_energy_gradient", "hub_step_noalloc", "hub_step_current"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -93,6 +93,7 @@ def lib():
         "hub_apply_sets": [P, P, P, P, I, P, D, P, I64, I, I],
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_step_noalloc": [P, ctypes.POINTER(StepIO)],
+        "hub_step_current": [P, ctypes.POINTER(StepIO), P, I],
         "hub_energy_gradient": [P, P, I64, I, P, P, P, P, D, P, I64, P],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -467,8 +468,10 @@ class Hubbard:
                     Ueff=torch.empty(self.nsites, dtype=torch.float64, device="cuda"),
                     status=torch.empty(self.nsites, dtype=torch.int32, device="cuda"))
 
-    def step(self, psi, f, hpsi, alpha=1.0, mode="graph", bufs=None, nstates=None):
-        """One Hubbard step; returns the dict of device buffers it filled."""
+    def step(self, psi, f, hpsi, alpha=1.0, mode="graph", bufs=None, nstates=None, current=None):
+        """One Hubbard step; returns the dict of device buffers it filled.
+        ``current``: an (n_sites, 3) FP64 device tensor that receives the
+        velocity-gauge current of the step (hub_step_current)."""
         ld, S = self._states(psi, nstates)
         ldh, S2 = self._states(hpsi, nstates)
         if S2 != S:
@@ -478,7 +481,14 @@ class Hubbard:
                     b["c"].data_ptr(), b["n"].data_ptr(), b["pbar"].data_ptr(), b["nbar"].data_ptr(),
                     b["U"].data_ptr(), b["J"].data_ptr(), b["Ueff"].data_ptr(), b["status"].data_ptr())
         self._stream()
-        _check(lib().hub_step(self._ctx, ctypes.byref(io), STEP_MODES[mode]), "hub_step")
+        if current is None:
+            _check(lib().hub_step(self._ctx, ctypes.byref(io), STEP_MODES[mode]), "hub_step")
+        else:
+            if current.dtype != torch.float64 or not current.is_cuda or tuple(current.shape) != (self.nsites, 3) \
+                    or not current.is_contiguous():
+                raise ValueError("current must be a contiguous (n_sites, 3) float64 CUDA tensor")
+            _check(lib().hub_step_current(self._ctx, ctypes.byref(io), current.data_ptr(), STEP_MODES[mode]),
+                   "hub_step_current")
         return b
 
     def step_noalloc(self, psi, f, hpsi, bufs, alpha=1.0, nstates=None):

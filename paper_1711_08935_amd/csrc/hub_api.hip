@@ -27,6 +27,7 @@ struct DevBuf {
 
 struct GraphKey {
     hub_step_io io{};
+    double* jcur = nullptr;                  // current output of hub_step_current, else null
     int ncol = 0;
     bool valid = false;
 };
@@ -107,6 +108,8 @@ struct hub_ctx {
     int32_t *d_gred_ptr = nullptr, *d_gred_row = nullptr, *d_gred_img = nullptr;
     int32_t* d_gspin_shift = nullptr;        // spin-dependent orbitals: L per orbital
     double* d_gtab = nullptr;
+    double *d_gd0 = nullptr, *d_gfdel = nullptr;   // moment tables of the grouped list, uploaded
+                                                   // at the first hub_step_current
     std::vector<char> have_tensor;
     size_t table_bytes = 0;
 
@@ -214,7 +217,7 @@ void release(hub_ctx* c) {
     f(c->d_phi2); f(c->d_gphi_dn); f(c->d_mphi_dn);
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab); f(c->d_st_tab_dn);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
-    f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift);
+    f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift); f(c->d_gd0); f(c->d_gfdel);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -458,21 +461,35 @@ size_t part_need(const hub_ctx* c, int ncol, int mult) {
     if (mult == 3) rows = std::max<int64_t>(rows, c->stencil_part_rows * 3);
     return static_cast<size_t>(c->nsets()) * rows * ncol * c->ncplx();
 }
+// the grouped projection with the three position-moment components as well
+size_t part_need_moments(const hub_ctx* c, int ncol) {
+    return std::max(part_need(c, ncol, 3),
+                    static_cast<size_t>(4) * c->nsets() * c->T.grouped.part_rows * ncol * c->ncplx());
+}
+// whether hub_step_current takes the moments in the step's own projection
+bool fused_moments(const hub_ctx* c) { return grouped(c) && c->is_complex && !c->T.spindep; }
 
 // q0, nq: the state sets projected (psi and out hold those sets only);
 // nq < 0: every set of the context.
 // colpar >= 0: the reduction writes only the columns of that parity (the
 // spin component whose orbitals the table holds).
+// mout (grouped list, every set): the projections on the position moments
+// about the site centres as well, mout[q][3 j + i][col], from the same
+// pass over psi.
 int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out, bool per_site,
-               int table = TAB_PHI, int q0 = 0, int nq = -1, int colpar = -1) {
+               int table = TAB_PHI, int q0 = 0, int nq = -1, int colpar = -1, double* mout = nullptr) {
     if (nq < 0) nq = c->nsets();
     const bool grad = table != TAB_PHI;
     const bool spindep = !grad && c->T.spindep;
     const int ncol = c->ncol(nstates);
     const int mult = grad ? 3 : 1;
+    if (mout && (per_site || grad || !fused_moments(c) || !c->d_gd0 || c->ws_fixed || q0 != 0 ||
+                 nq != c->nsets()))
+        return HUB_ESTATE;
     double* part = c->ws_fixed ? c->ws_fixed->part : nullptr;
     if (!part) {
-        const int st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, spindep ? 2 : mult), c);
+        const size_t need = mout ? part_need_moments(c, ncol) : part_need(c, ncol, spindep ? 2 : mult);
+        const int st = ensure(&c->d_part, &c->part_cap, need, c);
         if (st) return st;
         part = c->d_part;
     }
@@ -486,7 +503,18 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         a.tab = c->d_gtab;
         a.tabmult = 1;               // grouped chunks count their functions in C.L
         a.prows = GT.part_rows;
-        {
+        const int64_t pplane = static_cast<int64_t>(nq) * GT.part_rows * ncol * c->ncplx();
+        if (mout) {
+            // orbitals and position moments in one launch over every chunk
+            a.chunk_list = c->d_gall_m;
+            a.d0 = c->d_gd0;
+            a.fdel = c->d_gfdel;
+            a.pplane = pplane;
+            const int nch = GT.npass > 1 ? c->gpass_ptr[GT.npass] : c->gcls_ptr[HUB_NCLASS];
+            StageTimer tm(c, HUB_STAGE_PROJECT);
+            HUB_TRY(c->precision == HUB_F64 ? launch_project_mom_f64(a, nch, nq, c->stream)
+                                            : launch_project_mom_f32(a, nch, nq, c->stream));
+        } else {
             StageTimer tm(c, HUB_STAGE_PROJECT);
             // one launch per function-count class
             const int st = run_classes(c, [&](int k, const int32_t* list, int nch, hipStream_t s) {
@@ -516,6 +544,11 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         r.spinor = c->spin_mode == HUB_SPINOR;
         r.q0 = q0;
         r.dV = (c->cell[0] / c->ngrid[0]) * (c->cell[1] / c->ngrid[1]) * (c->cell[2] / c->ngrid[2]);
+        if (mout) {
+            r.ncomp = 4;
+            r.mout = mout;
+            r.pplane = pplane;
+        }
         StageTimer tm(c, HUB_STAGE_REDUCE);
         HUB_TRY(launch_reduce_grouped(r, nq, c->stream));
         return HUB_OK;
@@ -802,8 +835,20 @@ int do_apply(hub_ctx* c, const double* Ueff, const double* n, const double* cc, 
     return HUB_OK;
 }
 
-int run_step(hub_ctx* c, const hub_step_io* io, bool per_site) {
-    int st = do_project(c, io->psi, io->ld, io->nstates, io->c, per_site);
+int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
+                     const double* Ueff, const double* n, double* out, int table, double fscale = 1.0);
+int moment_contraction(hub_ctx* c, const double* cc, const double* f, const double* Ueff, const double* n,
+                       const double* d, int nstates, double* out, bool imag, double fscale);
+
+// One step; jcur: also the velocity-gauge current of the step's states and
+// potential (hub_current), from the moments that the step's projection
+// takes in the same pass over psi where the work list allows, else from a
+// projection of its own.  It is formed before the apply, so hpsi may alias
+// psi.
+int run_step(hub_ctx* c, const hub_step_io* io, bool per_site, double* jcur = nullptr) {
+    const bool fused = jcur && !per_site && fused_moments(c);
+    int st = do_project(c, io->psi, io->ld, io->nstates, io->c, per_site, TAB_PHI, 0, -1, -1,
+                        fused ? c->d_grad : nullptr);
     if (st) return st;
     if (per_site) {
         // the plain path: one launch per site and stage
@@ -814,6 +859,12 @@ int run_step(hub_ctx* c, const hub_step_io* io, bool per_site) {
         st = do_step_occ(c, io);
     }
     if (st) return st;
+    if (jcur) {
+        st = fused ? moment_contraction(c, io->c, io->f, io->Ueff, io->n, c->d_grad, io->nstates, jcur, true, 1.0)
+                   : contract_moments(c, io->psi, io->ld, io->nstates, io->c, io->f, io->Ueff, io->n, jcur,
+                                      TAB_MOMENT);
+        if (st) return st;
+    }
     return do_apply(c, io->Ueff, io->n, io->c, io->nstates, nullptr, io->alpha, io->hpsi, io->ldh, per_site);
 }
 
@@ -836,6 +887,77 @@ int check_step(const hub_ctx* c, const hub_step_io* io) {
 // doubles, rounded up so that every slice of the scratch array starts on a
 // 256-byte boundary
 size_t slice256(size_t n) { return (n + 31) / 32 * 32; }
+
+// hub_step and hub_step_current (jcur: the current's output, else null).
+int step_impl(hub_ctx* c, const hub_step_io* io, int mode, double* jcur) {
+    int st = check_step(c, io);
+    if (st) return st;
+    if (mode != HUB_STEP_BATCHED && mode != HUB_STEP_GRAPH && mode != HUB_STEP_PERSITE) return HUB_EINVAL;
+    // the step needs the projection workspace and the N-bar buffer (with the
+    // current: the moment projections and, on first use, the grouped moment
+    // tables); size them before any capture so that the graph never sees a
+    // reallocation
+    const int ncol = c->ncol(io->nstates);
+    size_t part = part_need(c, ncol, c->T.spindep ? 2 : 1);
+    if (jcur) {
+        const bool fused = mode != HUB_STEP_PERSITE && fused_moments(c);
+        part = std::max(part, fused ? part_need_moments(c, ncol) : part_need(c, ncol, 3));
+        st = ensure(&c->d_grad, &c->grad_cap, static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx(), c);
+        if (st) return st;
+        if (fused && !c->d_gd0) {
+            size_t bytes = 0;
+            HUB_TRY(upload(c, &c->d_gfdel, c->T.grouped.fdel, bytes));
+            HUB_TRY(upload(c, &c->d_gd0, c->T.grouped.d0, bytes));
+            c->table_bytes += bytes;
+        }
+    }
+    st = ensure(&c->d_part, &c->part_cap, part, c);
+    if (st) return st;
+
+    if (!io->nbar) {
+        st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);
+        if (st) return st;
+    }
+    st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(io->ldh) * c->ncplx(), c);
+    if (st) return st;
+    st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, io->nstates), c);
+    if (st) return st;
+    if (mode != HUB_STEP_GRAPH) return run_step(c, io, mode == HUB_STEP_PERSITE, jcur);
+
+    const bool same = c->gkey.valid && c->gkey.ncol == ncol && c->gkey.jcur == jcur &&
+                      std::memcmp(&c->gkey.io, io, sizeof(hub_step_io)) == 0;
+    if (!same) {
+        drop_graph(c);
+        HUB_TRY(hipStreamSynchronize(c->stream));
+        hipStream_t keep = c->stream;
+        c->stream = c->cap_stream;
+        HUB_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
+        st = run_step(c, io, false, jcur);
+        c->capturing = false;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        c->stream = keep;
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return map_err(e);
+        c->graph = g;
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(c);
+            return map_err(e);
+        }
+        c->gkey.io = *io;
+        c->gkey.ncol = ncol;
+        c->gkey.jcur = jcur;
+        c->gkey.valid = true;
+    }
+    HUB_TRY(hipGraphLaunch(c->gexec, c->stream));
+    return HUB_OK;
+}
+
 
 }  // namespace
 
@@ -1298,7 +1420,7 @@ namespace {
 // with d the projections of the psi on the table's 3L functions per site.
 // fscale multiplies the result (1: forces or current; -g: g dE_U/dR).
 int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const double* cc, const double* f,
-                     const double* Ueff, const double* n, double* out, int table, double fscale = 1.0) {
+                     const double* Ueff, const double* n, double* out, int table, double fscale) {
     if (!c || !cc || !f || !Ueff || !n || !out) return HUB_EINVAL;
     if (!built(c)) return HUB_ESTATE;
     if (!valid_states(c, psi, ld, nstates)) return HUB_EINVAL;
@@ -1316,9 +1438,17 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
         st = do_project(c, psi, ld, nstates, c->d_grad, false, table);
     }
     if (st) return st;
+    return moment_contraction(c, cc, f, Ueff, n, c->d_grad, nstates, out, table == TAB_MOMENT, fscale);
+}
+
+// out[site][i] = fscale 2 g sum w f Re (imag: Im) sum_a conj(d_{a,i}) B_a
+// from the moment projections d[q][3 j + i][col] (k_forces).
+int moment_contraction(hub_ctx* c, const double* cc, const double* f, const double* Ueff, const double* n,
+                       const double* d, int nstates, double* out, bool imag, double fscale) {
+    const int ncol = c->ncol(nstates);
     ForceArgs a{};
     a.c = cc;
-    a.d = c->d_grad;
+    a.d = d;
     a.f = f;
     a.n = n;
     a.ueff = Ueff;
@@ -1335,7 +1465,7 @@ int contract_moments(hub_ctx* c, const void* psi, int64_t ld, int nstates, const
     a.nspin = c->nspin();
     a.nq = c->nsets();
     a.nblk = c->nblk();
-    a.imag = table == TAB_MOMENT;
+    a.imag = imag ? 1 : 0;
     a.scale = fscale;
     StageTimer tm(c, HUB_STAGE_FORCES);
     HUB_TRY(launch_forces(a, c->stream));
@@ -1484,55 +1614,11 @@ int hub_set_vector_potential(hub_ctx* c, const double* A) {
     return gauge_tables(c);
 }
 
-int hub_step(hub_ctx* c, const hub_step_io* io, int mode) {
-    int st = check_step(c, io);
-    if (st) return st;
-    if (mode != HUB_STEP_BATCHED && mode != HUB_STEP_GRAPH && mode != HUB_STEP_PERSITE) return HUB_EINVAL;
-    // the step needs the projection workspace and the N-bar buffer; size them
-    // before any capture so that the graph never sees a reallocation
-    const int ncol = c->ncol(io->nstates);
-    st = ensure(&c->d_part, &c->part_cap, part_need(c, ncol, c->T.spindep ? 2 : 1), c);
-    if (st) return st;
-    if (!io->nbar) {
-        st = ensure(&c->d_nbar_ws, &c->nbar_cap, static_cast<size_t>(c->nsets()) * c->T.nspecies * io->nstates, c);
-        if (st) return st;
-    }
-    st = ensure(&c->d_sink, &c->sink_cap, static_cast<size_t>(io->ldh) * c->ncplx(), c);
-    if (st) return st;
-    st = ensure(&c->d_occ_ws, &c->occ_cap, occ_need(c, io->nstates), c);
-    if (st) return st;
-    if (mode != HUB_STEP_GRAPH) return run_step(c, io, mode == HUB_STEP_PERSITE);
+int hub_step(hub_ctx* c, const hub_step_io* io, int mode) { return step_impl(c, io, mode, nullptr); }
 
-    const bool same = c->gkey.valid && c->gkey.ncol == ncol && std::memcmp(&c->gkey.io, io, sizeof(hub_step_io)) == 0;
-    if (!same) {
-        drop_graph(c);
-        HUB_TRY(hipStreamSynchronize(c->stream));
-        hipStream_t keep = c->stream;
-        c->stream = c->cap_stream;
-        HUB_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        c->capturing = true;
-        st = run_step(c, io, false);
-        c->capturing = false;
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-        c->stream = keep;
-        if (st) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
-        }
-        if (e != hipSuccess) return map_err(e);
-        c->graph = g;
-        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            drop_graph(c);
-            return map_err(e);
-        }
-        c->gkey.io = *io;
-        c->gkey.ncol = ncol;
-        c->gkey.valid = true;
-    }
-    HUB_TRY(hipGraphLaunch(c->gexec, c->stream));
-    return HUB_OK;
+int hub_step_current(hub_ctx* c, const hub_step_io* io, double* J, int mode) {
+    if (!J) return HUB_EINVAL;
+    return step_impl(c, io, mode, J);
 }
 
 int hub_profile(hub_ctx* c, int enable) {

@@ -71,6 +71,13 @@ struct GroupTables {
     std::vector<HubChunk> chunks;            // L = number of functions, e0/ne over points
     std::vector<int32_t> gidx;               // per point
     std::vector<double> tab;                 // per point, L values (slot-major)
+    // position moments (velocity-gauge current): per point (in gidx order)
+    // the displacement of its unfolded position from the centre of the site
+    // of its chunk's first cover, d0[point][3]; per chunk and function the
+    // offset from that displacement to the one about the function's own
+    // site, fdel[chunk][HUB_GF_MAX][3] (constant over a chunk's points)
+    std::vector<double> d0;
+    std::vector<double> fdel;
     std::vector<int32_t> f_orb;              // per chunk HUB_GF_MAX: global orbital j of function f
     std::vector<int32_t> f_img;              // per chunk HUB_GF_MAX: lattice image of function f
     std::vector<int32_t> red_ptr;            // CSR orbital j -> workspace rows

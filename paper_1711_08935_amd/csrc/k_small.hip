@@ -65,14 +65,17 @@ __global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedA
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = blockIdx.x * 64 + lane;
     const int j = blockIdx.y;
-    const int q = blockIdx.z;
+    const int ncomp = a.ncomp > 1 ? a.ncomp : 1;
+    const int comp = blockIdx.z % ncomp;
+    const int q = blockIdx.z / ncomp;
     const bool active = col < a.ncol;
     const int k = a.spinor ? a.q0 + q : (a.q0 + q) / a.nspin;
     const double* __restrict__ ph = a.phase + static_cast<int64_t>(k) * a.nimg * 2;
     // spin-dependent orbitals: spinor column 2s + sigma reads the rows of the
     // orbital of its spin component
     const int64_t shift = (a.spin_shift && (col & 1)) ? a.spin_shift[j] : 0;
-    const double* __restrict__ base = a.part + (static_cast<int64_t>(q) * a.prows + shift) * a.ncol * NC +
+    const double* __restrict__ base = a.part + comp * a.pplane +
+                                      (static_cast<int64_t>(q) * a.prows + shift) * a.ncol * NC +
                                       static_cast<int64_t>(active ? col : 0) * NC;
     const int t0 = a.red_ptr[j], t1 = a.red_ptr[j + 1];
     int lo, len;
@@ -125,7 +128,8 @@ __global__ void __launch_bounds__(RW * 64) k_reduce_grouped(const ReduceGroupedA
         r0 += red[w][lane][0];
         r1 += red[w][lane][1];
     }
-    double* o = a.out + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + col) * NC;
+    double* o = comp == 0 ? a.out + ((static_cast<int64_t>(q) * a.J + j) * a.ncol + col) * NC
+                          : a.mout + ((static_cast<int64_t>(q) * a.J * 3 + 3 * j + comp - 1) * a.ncol + col) * NC;
     o[0] = a.dV * r0;
     if (NC == 2) o[1] = a.dV * r1;
 }
@@ -749,7 +753,10 @@ __global__ void k_fll(const FllArgs a) {
 
 // ---------------------------------------------------------------- forces
 // F_i = g_s 2 Re sum_q w_k sum_col f_s sum_a conj(d_{a,i}(col)) B_a(col),
-// B = V c as in the apply kernel (Sec. IV with U_eff fixed).
+// B = V c as in the apply kernel (Sec. IV with U_eff fixed).  One
+// work-group per site: the site's potential blocks V are formed once in LDS,
+// then each thread takes (state set, column) pairs, holds the pair's L (two
+// spin components: 2L) projections in registers and forms B from them.
 __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
     const int site = blockIdx.x;
     const int L = a.site_L[site];
@@ -757,6 +764,16 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
     const int NC = a.ncplx;
     const double U = a.ueff[site];
     const int tid = threadIdx.x;
+    // V[blk][a][b] = U (delta_ab / 2 on the spin-diagonal blocks - n_blk[b][a])
+    __shared__ double V[4][7][7][2];
+    const double* nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
+    for (int o = tid; o < a.nblk * 49; o += NB) {
+        const int blk = o / 49, r = o - blk * 49, ai = r / 7, b = r - ai * 7;
+        const bool diag = a.spinor ? (blk == 0 || blk == 3) : true;
+        V[blk][ai][b][0] = U * ((ai == b && diag) ? 0.5 : 0.0) - U * nb[blk * 98 + (b * 7 + ai) * 2];
+        V[blk][ai][b][1] = -U * nb[blk * 98 + (b * 7 + ai) * 2 + 1];
+    }
+    __syncthreads();
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t total = static_cast<int64_t>(a.nq) * a.ncol;
     for (int64_t o = tid; o < total; o += NB) {
@@ -768,31 +785,34 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
         const double wf = a.kweights[k] * a.f[static_cast<int64_t>(q) * a.nstates + s];
         if (wf == 0.0) continue;
         const double* cq = a.c + (static_cast<int64_t>(q) * a.J + orb0) * a.ncol * NC;
-        const double* nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
-        for (int ai = 0; ai < L; ++ai) {
+        // the pair's projections: component t of spinor column 2s + sigma is
+        // column 2s + t; collinear columns use t = 0 only
+        const int sg = col & 1, base = a.spinor ? col - sg : col;
+        const int nt = a.spinor ? 2 : 1;
+        double cr[2][7], ci[2][7];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int b = 0; b < 7; ++b) {
+                const bool use = t < nt && b < L;
+                const double* p = cq + (static_cast<int64_t>(b) * a.ncol + base + t) * NC;
+                cr[t][b] = use ? p[0] : 0.0;
+                ci[t][b] = (use && NC == 2) ? p[1] : 0.0;
+            }
+#pragma unroll
+        for (int ai = 0; ai < 7; ++ai) {
+            if (ai >= L) break;
             double br = 0.0, bi = 0.0;
-            if (!a.spinor) {
-                const double* nm = nb + ch * 98;
-                for (int b = 0; b < L; ++b) {
-                    const double vr = U * ((ai == b ? 0.5 : 0.0) - nm[(b * 7 + ai) * 2]);
-                    const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
-                    const double cr = cq[(static_cast<int64_t>(b) * a.ncol + col) * NC];
-                    const double ci = (NC == 2) ? cq[(static_cast<int64_t>(b) * a.ncol + col) * NC + 1] : 0.0;
-                    br += vr * cr - vi * ci;
-                    bi += vr * ci + vi * cr;
-                }
-            } else {
-                const int sg = col & 1, base = col - sg;
-                for (int t = 0; t < 2; ++t) {
-                    const double* nm = nb + (2 * t + sg) * 98;
-                    for (int b = 0; b < L; ++b) {
-                        const double vr = U * ((ai == b && t == sg) ? 0.5 : 0.0) - U * nm[(b * 7 + ai) * 2];
-                        const double vi = -U * nm[(b * 7 + ai) * 2 + 1];
-                        const double cr = cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2];
-                        const double ci = cq[(static_cast<int64_t>(b) * a.ncol + base + t) * 2 + 1];
-                        br += vr * cr - vi * ci;
-                        bi += vr * ci + vi * cr;
-                    }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (t >= nt) break;
+                const int blk = a.spinor ? 2 * t + sg : ch;
+#pragma unroll
+                for (int b = 0; b < 7; ++b) {
+                    if (b >= L) break;
+                    const double vr = V[blk][ai][b][0], vi = V[blk][ai][b][1];
+                    br += vr * cr[t][b] - vi * ci[t][b];
+                    bi += vr * ci[t][b] + vi * cr[t][b];
                 }
             }
             for (int i = 0; i < 3; ++i) {
@@ -879,7 +899,8 @@ hipError_t launch_reduce(const ReduceArgs& a, int nq, hipStream_t st) {
 
 hipError_t launch_reduce_grouped(const ReduceGroupedArgs& a, int nq, hipStream_t st) {
     if (a.J <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
-    dim3 grid((a.ncol + 63) / 64, a.J, nq);
+    if (a.ncomp > 1 && !a.mout) return hipErrorInvalidValue;
+    dim3 grid((a.ncol + 63) / 64, a.J, nq * (a.ncomp > 1 ? a.ncomp : 1));
     // many rows per orbital (overlapping spheres, small chunks): 16 waves
     const bool wide = a.rows_per_orbital >= 64;
     if (a.ncplx == 2) {

@@ -28,6 +28,13 @@ struct ProjArgs {
     const double* pg;         // velocity gauge: [G] exp(i A.r_g) (re, im), or null
     double* part;             // [nq][prows][ncol] (x2 complex)
     int64_t prows;            // rows per state set = part_rows * tabmult
+    // position-moment launch (k_project_mom) only: per grouped point the
+    // displacement d0[3] from its chunk's first cover, per chunk and function
+    // the offset fdel[HUB_GF_MAX][3] to its own cover; component i (0: the
+    // orbitals, 1-3: the moments) is written to part + i * pplane
+    const double* d0;
+    const double* fdel;
+    int64_t pplane;
 };
 
 // Launch arguments of the apply kernel (coefficients + scatter).
@@ -231,6 +238,10 @@ hipError_t launch_project_f32(const ProjArgs& a, int nchunks, int nq, int cplx, 
                               hipStream_t st);
 hipError_t launch_project_f64(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
                               hipStream_t st);
+// orbital and position-moment projections of complex states over grouped
+// chunks (k_project_mom.h)
+hipError_t launch_project_mom_f32(const ProjArgs& a, int nchunks, int nq, hipStream_t st);
+hipError_t launch_project_mom_f64(const ProjArgs& a, int nchunks, int nq, hipStream_t st);
 hipError_t launch_apply_f32(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
                             hipStream_t st);
 hipError_t launch_apply_f64(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,

@@ -30,6 +30,12 @@ struct ReduceGroupedArgs {
     int rows_per_orbital;     // average workspace rows per orbital (host)
     const int32_t* spin_shift;  // spin-dependent orbitals: per orbital, the rows from a
                                 // spin-up function to its spin-down one (L); else null
+    // ncomp = 4: the workspace also holds the position-moment projections
+    // (component i + 1 at part + (i + 1) * pplane), reduced into
+    // mout[q][3 j + i][col]
+    int ncomp;                  // 1 or 4 (0 is taken as 1)
+    double* mout;
+    int64_t pplane;
 };
 
 struct NbarArgs {

@@ -482,9 +482,28 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     C.species = -1;
                     C.phi0 = tab0;
                     C.img = sig[0].second;
+                    // position moments (velocity-gauge current): the displacement
+                    // d0 of each point from the centre of its first cover's site
+                    // (unfolded, image-shifted coordinates), and per function the
+                    // constant offset from that cover's displacement to its own
+                    auto disp = [&](const Cover& cv, int i) {
+                        return static_cast<double>(T.spheres[cv.site].ijk[3 * cv.p + i]) * h[i] -
+                               sites[cv.site].R[i];
+                    };
+                    {
+                        const size_t i0 = firsts[b];
+                        double del[HUB_GF_MAX][3] = {};
+                        int f = 0;
+                        for (size_t sl = 0; sl < sig.size(); ++sl)
+                            for (int m = 0; m < smul * T.site_L[sig[sl].first]; ++m, ++f)
+                                for (int i = 0; i < 3; ++i) del[f][i] = disp(cov[i0 + sl], i) - disp(cov[i0], i);
+                        for (int ff = 0; ff < HUB_GF_MAX; ++ff)
+                            for (int i = 0; i < 3; ++i) GT.fdel.push_back(del[ff][i]);
+                    }
                     for (size_t t = 0; t < nb; ++t) {
                         const size_t i0 = firsts[b + t];
                         GT.gidx.push_back(cov[i0].g);
+                        for (int i = 0; i < 3; ++i) GT.d0.push_back(disp(cov[i0], i));
                         for (size_t sl = 0; sl < sig.size(); ++sl) {
                             const Cover& cv = cov[i0 + sl];
                             const int L = T.site_L[cv.site];
@@ -499,6 +518,7 @@ int hub_build_host(const double cell[3], const int ngrid[3], const std::vector<S
                     for (size_t t = nb; t < np; ++t) {
                         GT.gidx.push_back(GT.gidx.back());
                         GT.tab.insert(GT.tab.end(), nf, 0.0);
+                        GT.d0.insert(GT.d0.end(), 3, 0.0);
                     }
                     for (int f = 0; f < HUB_GF_MAX; ++f) {
                         GT.f_orb.push_back(-1);

@@ -80,8 +80,10 @@ def test_nio_full_size_every_output(prec):
 @pytest.mark.timeout(900)
 def test_nio_full_size_velocity_gauge():
     """The bench's real-time configuration with a field on: the graph step
-    under A, then the current.  Every projection c^A, the matrices, U and J,
-    V^A psi on sampled states and the current against the oracle."""
+    under A, then the current; and the graph step that takes the current
+    from its own projection pass (hub_step_current).  Every projection c^A,
+    the matrices, U and J, V^A psi on sampled states and both currents
+    against the oracle."""
     cfg, hub, psi, f, f_d, bufs, hpsi = _setup("nio_afm", "f32")
     A = np.array([0.05, 0.02, -0.03])
     hub.set_vector_potential(A)
@@ -89,7 +91,17 @@ def test_nio_full_size_velocity_gauge():
         hpsi.zero_()
         hub.step(psi, f_d, hpsi, mode="graph", bufs=bufs)
         J = hub.current(psi, bufs["c"], f_d, bufs["Ueff"], bufs["n"]).cpu().numpy()
+        # the step with the current from its own projection pass
+        bufs2 = hub.step_buffers(cfg.nstates)
+        h2 = torch.zeros_like(hpsi)
+        Jf_d = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+        hub.step(psi, f_d, h2, mode="graph", bufs=bufs2, current=Jf_d)
         torch.cuda.synchronize()
+        assert normwise(h2.cpu().numpy(), hpsi.cpu().numpy()) < 2e-7
+        assert normwise(bufs2["c"].cpu().numpy(), bufs["c"].cpu().numpy()) < 1e-13
+        assert normwise(bufs2["U"].cpu().numpy(), bufs["U"].cpu().numpy()) < 1e-13
+        Jf = Jf_d.cpu().numpy()
+        del h2
     finally:
         hub.set_vector_potential(None)
     used = psi.cpu().numpy().astype(np.complex128)
@@ -113,6 +125,8 @@ def test_nio_full_size_velocity_gauge():
     rho = GA.moment_projections(sys_, used, sps, A)
     Jref = GA.current(sys_, cA, rho, V, f)
     assert normwise(J, Jref) < 1e-11
+    assert normwise(Jf, Jref) < 1e-11
+    assert normwise(Jf, J) < 1e-12
 
 
 @pytest.mark.timeout(900)

@@ -140,6 +140,96 @@ def test_graph_replays_follow_the_field(case):
         hub.set_vector_potential(None)
 
 
+@pytest.mark.parametrize("mode", ["batched", "graph", "persite"])
+@pytest.mark.parametrize("worklist", ["grouped", "per-site"])
+def test_step_current(case, mode, worklist):
+    """hub_step_current: the step's outputs are hub_step's (the per-site mode
+    against the per-site step), and its current is the one hub_current gives
+    after the step and the oracle's.  Bitwise where the current takes a
+    projection of its own; with the grouped list (batched and graph modes)
+    the projections come from the moment launch, which sums each column's
+    entries in one sequence, so c and what follows from it agree to
+    rounding."""
+    hub, psi_d, f_d = case["hub"], case["psi_d"], case["f_d"]
+    S = case["cfg"].nstates
+    hub.set_worklist(worklist == "grouped")
+    hub.set_vector_potential(A2)
+    try:
+        h0 = torch.zeros_like(psi_d)
+        ref = hub.step(psi_d, f_d, h0, mode="persite" if mode == "persite" else "batched")
+        Jsep = hub.current(psi_d, ref["c"], f_d, ref["Ueff"], ref["n"])
+        bufs = hub.step_buffers(S)
+        J = torch.full((hub.nsites, 3), float("nan"), dtype=torch.float64, device="cuda")
+        fused = worklist == "grouped" and mode != "persite"
+        hbar = 1e-12 if hub.precision == "f64" else 2e-7
+        first = None
+        for _ in range(3 if mode == "graph" else 1):
+            h = torch.zeros_like(psi_d)
+            hub.step(psi_d, f_d, h, mode=mode, bufs=bufs, current=J)
+            torch.cuda.synchronize()
+            if fused:
+                assert normwise(h.cpu().numpy(), h0.cpu().numpy()) < hbar
+                for k in ("c", "n", "U", "J", "Ueff"):
+                    assert normwise(bufs[k].cpu().numpy(), ref[k].cpu().numpy()) < 1e-13, k
+            else:
+                assert torch.equal(h, h0)
+                for k in ("c", "n", "U", "J", "Ueff"):
+                    assert torch.equal(bufs[k], ref[k]), k
+            assert normwise(J.cpu().numpy(), Jsep.cpu().numpy()) < 1e-12
+            # graph replays repeat the first step bit for bit
+            if first is None:
+                first = (h.clone(), J.clone())
+            else:
+                assert torch.equal(h, first[0]) and torch.equal(J, first[1])
+        cref = GA.project_gauge(case["sys"], case["psi_used"], case["sps"], A2)
+        n, _, _ = OCC.occupations(case["sys"], cref, case["f"], with_pbar=False)
+        ueff = (ref["Ueff"]).cpu().numpy()
+        V = [POT.potential_matrix(case["sys"], u, nn) for u, nn in zip(ueff, n)]
+        rho = GA.moment_projections(case["sys"], case["psi_used"], case["sps"], A2)
+        Jref = GA.current(case["sys"], cref, rho, V, case["f"])
+        assert np.max(np.abs(Jref)) > 1e-8
+        assert normwise(J.cpu().numpy(), Jref) < 1e-11
+    finally:
+        hub.set_vector_potential(None)
+        hub.set_worklist(True)
+
+
+@pytest.mark.parametrize("policy", ["merged", "sequential", "concurrent"])
+def test_step_current_without_field(case, policy):
+    """No field (A = 0, plain kernels) under each class-launch policy (the
+    moment launch does not use the classes): the step's outputs are
+    hub_step's and its current is hub_current's, to rounding."""
+    hub, psi_d, f_d = case["hub"], case["psi_d"], case["f_d"]
+    hub.set_class_launch(policy)
+    try:
+        h0 = torch.zeros_like(psi_d)
+        ref = hub.step(psi_d, f_d, h0, mode="batched")
+        Jsep = hub.current(psi_d, ref["c"], f_d, ref["Ueff"], ref["n"])
+        bufs = hub.step_buffers(case["cfg"].nstates)
+        J = torch.full((hub.nsites, 3), float("nan"), dtype=torch.float64, device="cuda")
+        h = torch.zeros_like(psi_d)
+        hub.step(psi_d, f_d, h, mode="batched", bufs=bufs, current=J)
+        torch.cuda.synchronize()
+        hbar = 1e-12 if hub.precision == "f64" else 2e-7
+        assert normwise(h.cpu().numpy(), h0.cpu().numpy()) < hbar
+        assert normwise(bufs["c"].cpu().numpy(), ref["c"].cpu().numpy()) < 1e-13
+        assert np.max(np.abs(Jsep.cpu().numpy())) > 1e-8
+        assert normwise(J.cpu().numpy(), Jsep.cpu().numpy()) < 1e-12
+    finally:
+        hub.set_class_launch("merged")
+
+
+def test_step_current_rejects_bad_output(case):
+    hub, psi_d, f_d = case["hub"], case["psi_d"], case["f_d"]
+    bufs = hub.step_buffers(case["cfg"].nstates)
+    h = torch.zeros_like(psi_d)
+    with pytest.raises(ValueError):
+        hub.step(psi_d, f_d, h, mode="batched", bufs=bufs,
+                 current=torch.empty((hub.nsites, 2), dtype=torch.float64, device="cuda"))
+    from paper_1711_08935_amd import lib
+    assert lib().hub_step_current(hub._ctx, None, None, 0) == H.HUB_EINVAL
+
+
 def test_real_context_has_no_gauge_form():
     cfg = make_config("gamma_d", small=True)
     hub = make_hub(cfg, "f64")
