@@ -24,6 +24,11 @@
  *    process and no C++ exception crosses the ABI.  Asynchronous device
  *    faults surface as HUB_EDEVICE from a later call.
  *  - One context per stream; a context is not thread-safe.
+ *  - Allocation-failure testing: with HUB_FAIL_ALLOC=N (N >= 1) in the
+ *    environment when hub_create runs, that context's N-th device
+ *    allocation attempt fails once, as if the GPU were out of memory; the
+ *    call returns HUB_ENOMEM, frees what it had allocated, and may be
+ *    repeated.
  *
  * State layouts (T = double for HUB_F64, float for HUB_F32; complex states
  * store (re, im) pairs of T):
@@ -256,6 +261,18 @@ int hub_occupations(hub_ctx* ctx, const double* c, int nstates, const double* f,
  * hub_acbn0_uj.  site = -1 computes every site.  tensor (device, may be NULL)
  * receives L^4 doubles [a][b][c][d] for a single site. */
 int hub_coulomb(hub_ctx* ctx, int site, double* tensor);
+
+/* Setup cache: the Coulomb tensors are the one costly part of the setup
+ * (an O(P^2) sum per site) and depend only on the site's sphere (grid, cell,
+ * centre, l, zeta, rc).  hub_get_coulomb copies the context's tensor of one
+ * site (L^4 doubles [a][b][c][d], device) out; HUB_ESTATE if it has not been
+ * computed or set.  hub_set_coulomb installs one (device, same layout), e.g.
+ * from an earlier context with the same sphere, in place of hub_coulomb; the
+ * caller vouches that it belongs to this site.  Both are asynchronous on the
+ * context stream.  Errors: HUB_EINVAL (null tensor, bad site; set: a site
+ * with spin-dependent orbitals), HUB_ESTATE (before hub_finalize). */
+int hub_get_coulomb(hub_ctx* ctx, int site, double* tensor);
+int hub_set_coulomb(hub_ctx* ctx, int site, const double* tensor);
 
 /* ACBN0 U-bar, J-bar (Eqs. ACBN0_U, ACBN0_J; spinors App. B) and
  * U_eff = U-bar - J-bar per site, from n and pbar (device).  Sites with a

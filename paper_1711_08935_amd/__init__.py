@@ -50,7 +50,8 @@ EXPORTS = ["hub_create", "hub_set_kpoints", "hub_add_site", "hub_set_fixed_ueff"
            "hub_strerror", "hub_profile", "hub_profile_read", "hub_set_worklist", "hub_set_class_launch",
            "hub_set_vector_potential", "hub_current", "hub_forces_state_gradient", "hub_sphere_radius",
            "hub_energy_fll", "hub_set_site_spin_orbital", "hub_project_sets", "hub_apply_sets",
-           "hub_energy_gradient", "hub_step_noalloc", "hub_step_current"]
+           "hub_energy_gradient", "hub_step_noalloc", "hub_step_current", "hub_get_coulomb",
+           "hub_set_coulomb"]
 STAGES = ["project", "reduce", "nbar", "occupations", "acbn0", "apply", "gradproject", "forces"]
 
 
@@ -94,6 +95,8 @@ def lib():
         "hub_step": [P, ctypes.POINTER(StepIO), I],
         "hub_step_noalloc": [P, ctypes.POINTER(StepIO)],
         "hub_step_current": [P, ctypes.POINTER(StepIO), P, I],
+        "hub_get_coulomb": [P, I, P],
+        "hub_set_coulomb": [P, I, P],
         "hub_energy_gradient": [P, P, I64, I, P, P, P, P, D, P, I64, P],
         "hub_destroy": [P],
         "hub_strerror": [I],
@@ -359,6 +362,23 @@ class Hubbard:
         T = torch.empty((Lm, Lm, Lm, Lm), dtype=torch.float64, device="cuda")
         _check(lib().hub_coulomb(self._ctx, int(site), _dptr(T)), "hub_coulomb")
         return T
+
+    def get_coulomb(self, site):
+        """The context's Coulomb tensor of one site (L, L, L, L), FP64."""
+        Lm = self.site_L[site]
+        T = torch.empty((Lm, Lm, Lm, Lm), dtype=torch.float64, device="cuda")
+        self._stream()
+        _check(lib().hub_get_coulomb(self._ctx, int(site), _dptr(T)), "hub_get_coulomb")
+        return T
+
+    def set_coulomb(self, site, tensor):
+        """Install a Coulomb tensor computed earlier for this site's sphere."""
+        Lm = self.site_L[site]
+        t = self._dev(tensor)
+        if tuple(t.shape) != (Lm, Lm, Lm, Lm):
+            raise ValueError(f"site {site} takes an ({Lm},)*4 tensor")
+        self._stream()
+        _check(lib().hub_set_coulomb(self._ctx, int(site), _dptr(t)), "hub_set_coulomb")
 
     def acbn0(self, n, pbar):
         U = torch.empty(self.nsites, dtype=torch.float64, device="cuda")

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -151,6 +152,8 @@ struct hub_ctx {
     };
     const FixedWs* ws_fixed = nullptr;
     int64_t nalloc = 0;                      // device allocations made so far (hub_query 15)
+    int64_t alloc_attempts = 0;
+    int64_t fail_alloc = 0;                  // HUB_FAIL_ALLOC: the attempt that fails (0: none)
 
     // per-stage event timing
     bool prof = false;
@@ -188,9 +191,12 @@ int map_err(hipError_t e) {
         if (_e != hipSuccess) return map_err(_e); \
     } while (0)
 
-// Every device allocation of a context goes through here (counted).
+// Every device allocation of a context goes through here (counted).  With
+// HUB_FAIL_ALLOC=N in the environment at hub_create, the context's N-th
+// allocation attempt fails once, as an out-of-memory would.
 template <typename T>
 hipError_t dev_malloc(hub_ctx* c, T** p, size_t bytes) {
+    if (++c->alloc_attempts == c->fail_alloc) return hipErrorOutOfMemory;
     const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
     if (e == hipSuccess) ++c->nalloc;
     return e;
@@ -206,14 +212,19 @@ hipError_t upload(hub_ctx* c, T** dst, const std::vector<T>& src, size_t& bytes)
     return e;
 }
 
+// Frees every device table and workspace and leaves the pointers null (so a
+// failed hub_finalize can be retried and hub_destroy frees nothing twice).
 void release(hub_ctx* c) {
-    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    auto f = [](auto*& p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    };
     f(c->d_chunks); f(c->d_all); f(c->d_gidx); f(c->d_img); f(c->d_phi); f(c->d_gphi); f(c->d_phase);
     f(c->d_site_chunk_ptr); f(c->d_site_chunk_ids); f(c->d_orb_site); f(c->d_site_L); f(c->d_site_orb0);
     f(c->d_site_species); f(c->d_species_orb_ptr); f(c->d_species_orb_ids); f(c->d_kw); f(c->d_ueff_fixed);
     f(c->d_tensor); f(c->d_part); f(c->d_grad); f(c->d_nbar_ws); f(c->d_sink); f(c->d_occ_ws);
     f(c->d_pg); f(c->d_mphi); f(c->d_images); f(c->d_kred);
-    c->d_pg = nullptr;
+    c->part_cap = c->grad_cap = c->nbar_cap = c->sink_cap = c->occ_cap = 0;
     f(c->d_phi2); f(c->d_gphi_dn); f(c->d_mphi_dn);
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab); f(c->d_st_tab_dn);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
@@ -904,10 +915,10 @@ int step_impl(hub_ctx* c, const hub_step_io* io, int mode, double* jcur) {
         part = std::max(part, fused ? part_need_moments(c, ncol) : part_need(c, ncol, 3));
         st = ensure(&c->d_grad, &c->grad_cap, static_cast<size_t>(c->nsets()) * c->T.J * 3 * ncol * c->ncplx(), c);
         if (st) return st;
-        if (fused && !c->d_gd0) {
+        if (fused) {
             size_t bytes = 0;
-            HUB_TRY(upload(c, &c->d_gfdel, c->T.grouped.fdel, bytes));
-            HUB_TRY(upload(c, &c->d_gd0, c->T.grouped.d0, bytes));
+            if (!c->d_gfdel) HUB_TRY(upload(c, &c->d_gfdel, c->T.grouped.fdel, bytes));
+            if (!c->d_gd0) HUB_TRY(upload(c, &c->d_gd0, c->T.grouped.d0, bytes));
             c->table_bytes += bytes;
         }
     }
@@ -999,6 +1010,7 @@ int hub_create(hub_ctx** out, const double cell[3], const int ngrid[3], int spin
     c->spin_mode = spin_mode;
     c->is_complex = is_complex;
     c->precision = precision;
+    if (const char* fa = std::getenv("HUB_FAIL_ALLOC")) c->fail_alloc = std::max(0LL, std::atoll(fa));
     *out = c;
     return HUB_OK;
 }
@@ -1357,6 +1369,29 @@ int hub_coulomb(hub_ctx* c, int site, double* tensor) {
     if (d_rho) (void)hipFree(d_rho);
     if (d_W) (void)hipFree(d_W);
     return map_err(e);
+}
+
+int hub_get_coulomb(hub_ctx* c, int site, double* tensor) {
+    if (!c || !tensor) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (site < 0 || site >= c->T.nsites) return HUB_EINVAL;
+    if (!c->have_tensor[site]) return HUB_ESTATE;
+    const int L = c->T.site_L[site];
+    HUB_TRY(hipMemcpyAsync(tensor, c->d_tensor + static_cast<size_t>(site) * 2401,
+                           static_cast<size_t>(L) * L * L * L * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return HUB_OK;
+}
+
+int hub_set_coulomb(hub_ctx* c, int site, const double* tensor) {
+    if (!c || !tensor) return HUB_EINVAL;
+    if (!built(c)) return HUB_ESTATE;
+    if (site < 0 || site >= c->T.nsites) return HUB_EINVAL;
+    if (std::isfinite(c->sites[site].zeta_dn)) return HUB_EINVAL;
+    const int L = c->T.site_L[site];
+    HUB_TRY(hipMemcpyAsync(c->d_tensor + static_cast<size_t>(site) * 2401, tensor,
+                           static_cast<size_t>(L) * L * L * L * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    c->have_tensor[site] = 1;
+    return HUB_OK;
 }
 
 int hub_acbn0_uj(hub_ctx* c, const double* n, const double* pbar, double* U, double* J, double* Ueff,

@@ -28,14 +28,13 @@
 
 namespace {
 
-constexpr int MOM_NFW = 8;   // functions per wave
-#ifndef HUB_MOM_U
-#define HUB_MOM_U 4
-#endif
-#ifndef HUB_MOM_STREAM
-#define HUB_MOM_STREAM 1
-#endif
-constexpr int MOM_U = HUB_MOM_U;     // rows per batch of the entry pipeline
+// Functions per wave: 8 (4 x 8 x 2 FP64 accumulators, three waves per
+// SIMD) measured faster than 6 or 4 (more waves per SIMD, but each point's
+// load and preparation repeated by more waves); rows per batch: 4 (8 spills
+// scalar registers and leaves two waves per SIMD).
+constexpr int MOM_NFW = 8;
+constexpr int MOM_WAVES = (HUB_GF_MAX + MOM_NFW - 1) / MOM_NFW;   // waves per work-group
+constexpr int MOM_U = 4;
 
 template <typename T, int NFW, bool GAUGE>
 __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, int ci, int f0, int q, int col,
@@ -79,10 +78,7 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int g = gg[u];
-            if constexpr (HUB_MOM_STREAM)
-                load_row_stream<T, 2>(psi_q + static_cast<int64_t>(g) * rowstride + 2 * colc, r[u]);
-            else
-                load_row<T, 2>(psi_q + static_cast<int64_t>(g) * rowstride + 2 * colc, r[u]);
+            load_row_stream<T, 2>(psi_q + static_cast<int64_t>(g) * rowstride + 2 * colc, r[u]);
             if constexpr (GAUGE) {
                 ph[u][0] = pg[2 * static_cast<int64_t>(g)];
                 ph[u][1] = pg[2 * static_cast<int64_t>(g) + 1];
@@ -170,7 +166,7 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
 }
 
 template <typename T, bool GAUGE>
-__global__ void __launch_bounds__(2 * HUB_WAVE)
+__global__ void __launch_bounds__(MOM_WAVES * HUB_WAVE)
 k_project_mom(const ProjArgs a, const int32_t* __restrict__ gidx, const double* __restrict__ tab,
               const double* __restrict__ d0, const double* __restrict__ fdel, const double* __restrict__ pg,
               double* __restrict__ part) {
@@ -189,6 +185,7 @@ k_project_mom(const ProjArgs a, const int32_t* __restrict__ gidx, const double* 
     const bool active = col < a.ncol;
 #define HUB_MCASE(n) \
     case n: mom_body<T, n, GAUGE>(a, C, ci, f0, q, col, active, gidx, tab, d0, fdel, pg, part); break;
+    static_assert(MOM_NFW == 8, "the cases below cover 1..8 functions");
     switch (nfw) {
         HUB_MCASE(1) HUB_MCASE(2) HUB_MCASE(3) HUB_MCASE(4) HUB_MCASE(5) HUB_MCASE(6) HUB_MCASE(7) HUB_MCASE(8)
     default: break;
@@ -207,10 +204,10 @@ hipError_t launch_project_mom_prec(const ProjArgs& a, int nchunks, int nq, hipSt
     b.tiles = static_cast<int>(static_cast<int64_t>(nq) * ((a.ncol + HUB_WAVE - 1) / HUB_WAVE));
     const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
     if (a.pg)
-        hipLaunchKernelGGL((k_project_mom<T, true>), grid, dim3(2 * HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0,
+        hipLaunchKernelGGL((k_project_mom<T, true>), grid, dim3(MOM_WAVES * HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0,
                            b.fdel, b.pg, b.part);
     else
-        hipLaunchKernelGGL((k_project_mom<T, false>), grid, dim3(2 * HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0,
+        hipLaunchKernelGGL((k_project_mom<T, false>), grid, dim3(MOM_WAVES * HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0,
                            b.fdel, b.pg, b.part);
     return hipGetLastError();
 }
