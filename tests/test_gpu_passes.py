@@ -94,3 +94,36 @@ def test_graph_step_matches_batched(case):
     for h, c in outs[1:]:
         assert torch.equal(h, outs[0][0])
         assert torch.equal(c, outs[0][1])
+
+
+def test_step_current_in_passes(case):
+    """The step with the current (hub_step_current) on the multi-pass list:
+    the moment launch covers every pass at once, each pass's chunks with
+    displacements from their own first cover.  Its current equals
+    hub_current's after the step (to rounding; real contexts take the
+    separate path, bit for bit)."""
+    hub = case["hub"]
+    S = case["cfg"].nstates
+    A = np.array([0.04, -0.03, 0.02]) if hub.is_complex else None
+    hub.set_vector_potential(A)
+    try:
+        bufs = hub.step_buffers(S)
+        h0 = torch.zeros_like(case["psi_d"])
+        ref = hub.step(case["psi_d"], case["f_d"], h0, mode="batched", bufs=bufs)
+        Jsep = hub.current(case["psi_d"], ref["c"], case["f_d"], ref["Ueff"], ref["n"]).cpu().numpy()
+        bufs2 = hub.step_buffers(S)
+        J = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+        h = torch.zeros_like(case["psi_d"])
+        hub.step(case["psi_d"], case["f_d"], h, mode="graph", bufs=bufs2, current=J)
+        torch.cuda.synchronize()
+        J = J.cpu().numpy()
+        if hub.is_complex:
+            assert np.max(np.abs(Jsep)) > 1e-8
+            assert normwise(J, Jsep) < 1e-12
+            assert normwise(bufs2["c"].cpu().numpy(), bufs["c"].cpu().numpy()) < 1e-13
+            assert normwise(h.cpu().numpy(), h0.cpu().numpy()) < (1e-12 if case["prec"] == "f64" else 2e-7)
+        else:
+            assert np.array_equal(J, Jsep)
+            assert torch.equal(h, h0)
+    finally:
+        hub.set_vector_potential(None)

@@ -176,7 +176,15 @@ def test_velocity_gauge(case):
         bufs = hub.step_buffers(case["cfg"].nstates)
         hg = torch.zeros_like(case["psi_d"])
         hub.step(case["psi_d"], case["f_d"], hg, mode="graph", bufs=bufs)
+        # the step with the current: spin-dependent orbitals take the step's
+        # stages and the separate moment projection, so bit for bit hub_current
+        bufs2 = hub.step_buffers(case["cfg"].nstates)
+        hs = torch.zeros_like(case["psi_d"])
+        Js = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+        hub.step(case["psi_d"], case["f_d"], hs, mode="graph", bufs=bufs2, current=Js)
         torch.cuda.synchronize()
+        assert torch.equal(hs, hg)
+        assert np.array_equal(Js.cpu().numpy(), J)
         hub.set_worklist(False)
         with pytest.raises(H.HubError):
             hub.project(case["psi_d"])
