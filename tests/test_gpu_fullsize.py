@@ -188,6 +188,25 @@ def test_spinor_layers_full_size(prec):
     h_ref = OS.apply_sphere(sys_, c[:, :, cols], V, sps)
     h = hpsi.cpu().numpy().reshape(hpsi.shape[0], hpsi.shape[1], -1, 2)[:, :, cols]
     assert normwise(h, h_ref) < (2e-7 if prec == "f32" else 1e-12)
+    # under a field, the graph step with the current from its own pass
+    # against hub_current after the step (checked against the oracle on the
+    # reduced workloads)
+    hub.set_vector_potential([0.04, -0.02, 0.03])
+    try:
+        hpsi.zero_()
+        ref_b = hub.step(psi, f_d, hpsi, mode="batched", bufs=hub.step_buffers(cfg.nstates))
+        Jsep = hub.current(psi, ref_b["c"], f_d, ref_b["Ueff"], ref_b["n"]).cpu().numpy()
+        J = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+        h2 = torch.zeros_like(hpsi)
+        b2 = hub.step_buffers(cfg.nstates)
+        hub.step(psi, f_d, h2, mode="graph", bufs=b2, current=J)
+        torch.cuda.synchronize()
+        assert np.max(np.abs(Jsep)) > 1e-8
+        assert normwise(J.cpu().numpy(), Jsep) < 1e-12
+        assert normwise(b2["c"].cpu().numpy(), ref_b["c"].cpu().numpy()) < 1e-13
+        assert normwise(h2.cpu().numpy(), hpsi.cpu().numpy()) < (2e-7 if prec == "f32" else 1e-12)
+    finally:
+        hub.set_vector_potential(None)
 
 
 @pytest.mark.timeout(900)
