@@ -94,6 +94,55 @@ def test_spinor_ragged_and_real_unpolarized():
     _check(cfg2, "f32", _rand_psi(cfg2, 67, rng) * 0.1, rng.uniform(0, 1, size=(cfg2.nq, 67)))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_step_current_mixed_shells_padded_states(prec):
+    """The step with the current (one pass for c and the moments) on s, p, d
+    and f shells, a site overlapping its own images, 7 states in rows of 9
+    (ragged lanes, caller padding), under a field: the current against
+    hub_current after the step and against the oracle."""
+    from oracle import gauge as GA
+    from oracle import occupations as OCC
+    from oracle import potential as POT
+    from oracle import projection as OP
+    from tests.helpers import to_system
+    cfg = _cfg(nstates=7)
+    rng = np.random.default_rng(5)
+    psi = _rand_psi(cfg, 7, rng) * 0.1
+    f = rng.uniform(0, 1, size=(cfg.nq, 7))
+    hub = make_hub(cfg, prec, chunk=64)
+    ncol = hub.ncol(7)
+    full = np.zeros(psi.shape[:2] + (ncol + 2,), dtype=psi.dtype)
+    full[..., :ncol] = psi
+    big, _ = device_states(hub, full)
+    psi_d = big[..., :ncol]
+    _, used = device_states(hub, psi)
+    f_d = torch.from_numpy(f).cuda()
+    hub.coulomb(-1)
+    A = np.array([0.11, -0.07, 0.05])
+    hub.set_vector_potential(A)
+    try:
+        h0 = torch.zeros_like(psi_d)
+        ref = hub.step(psi_d, f_d, h0, mode="batched", nstates=7)
+        Jsep = hub.current(psi_d, ref["c"], f_d, ref["Ueff"], ref["n"], nstates=7).cpu().numpy()
+        J = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+        h = torch.zeros_like(psi_d)
+        b = hub.step(psi_d, f_d, h, mode="graph", nstates=7, current=J)
+        torch.cuda.synchronize()
+    finally:
+        hub.set_vector_potential(None)
+    J = J.cpu().numpy()
+    assert normwise(J, Jsep) < 1e-12
+    assert normwise(b["c"].cpu().numpy(), ref["c"].cpu().numpy()) < 1e-13
+    sys_ = to_system(cfg)
+    sps = OP.all_spheres(sys_)
+    cA = GA.project_gauge(sys_, used, sps, A)
+    n, _, _ = OCC.occupations(sys_, cA, f, with_pbar=False)
+    V = [POT.potential_matrix(sys_, u, nn) for u, nn in zip(ref["Ueff"].cpu().numpy(), n)]
+    Jo = GA.current(sys_, cA, GA.moment_projections(sys_, used, sps, A), V, f)
+    assert np.abs(Jo).max() > 1e-8
+    assert normwise(J, Jo) < 1e-11
+
+
 def test_argument_errors_raise_before_launch():
     cfg = _cfg(nstates=4)
     hub = make_hub(cfg, "f64")
