@@ -8,9 +8,11 @@ Importing fails loudly when the library has not been built
 """
 
 import ctypes
+import hashlib
 import math
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -175,7 +177,14 @@ class Hubbard:
             self.kweights = kw
         else:
             self.kweights = [1.0]
+        self._sphere_keys = []
         for s in sites:
+            # what a site's Coulomb tensor depends on: the grid, its centre,
+            # shell and sphere (exact float images)
+            self._sphere_keys.append(hashlib.sha256(repr((
+                [float(v).hex() for v in cell], [int(v) for v in ngrid], [float(v).hex() for v in s["R"]],
+                int(s["l"]), float(s["zeta"]).hex(), float(s["rc"]).hex())).encode()).hexdigest()
+                if s.get("zeta_dn") is None else None)
             sid = ctypes.c_int()
             _check(L.hub_add_site(self._ctx, _darr(s["R"]), int(s["l"]), float(s["zeta"]), float(s["rc"]),
                                   int(s.get("species", 0)), ctypes.byref(sid)), "hub_add_site")
@@ -379,6 +388,41 @@ class Hubbard:
             raise ValueError(f"site {site} takes an ({Lm},)*4 tensor")
         self._stream()
         _check(lib().hub_set_coulomb(self._ctx, int(site), _dptr(t)), "hub_set_coulomb")
+
+    def save_coulomb(self, path):
+        """Write the context's Coulomb tensors (the costly part of the
+        set-up) to an .npz file, each under the key of its sphere."""
+        keys, tens = [], []
+        for site, key in enumerate(self._sphere_keys):
+            if key is None:
+                continue
+            try:
+                t = self.get_coulomb(site)
+            except HubError as e:
+                if e.code != HUB_ESTATE:
+                    raise
+                continue
+            keys.append(key)
+            tens.append(t.cpu().numpy().ravel())
+        np.savez(path, keys=np.array(keys), **{f"t{i}": t for i, t in enumerate(tens)})
+        return len(keys)
+
+    def load_coulomb(self, path):
+        """Install the tensors of an .npz file from save_coulomb for every
+        site whose sphere key matches; returns how many were installed (the
+        other sites still need hub_coulomb)."""
+        with np.load(path, allow_pickle=False) as z:
+            have = {str(k): i for i, k in enumerate(z["keys"])}
+            done = 0
+            for site, key in enumerate(self._sphere_keys):
+                if key is None or key not in have:
+                    continue
+                Lm = self.site_L[site]
+                t = torch.from_numpy(z[f"t{have[key]}"].reshape(Lm, Lm, Lm, Lm)).cuda()
+                self.set_coulomb(site, t)
+                done += 1
+        torch.cuda.synchronize()
+        return done
 
     def acbn0(self, n, pbar):
         U = torch.empty(self.nsites, dtype=torch.float64, device="cuda")

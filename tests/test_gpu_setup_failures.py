@@ -6,8 +6,9 @@
   tables of the step with the current) returns HUB_ENOMEM and can be
   repeated; the context then gives the results of a context that never
   failed, bit for bit, and is destroyed cleanly.
-* hub_get_coulomb / hub_set_coulomb: tensors taken from one context and
-  installed in another with the same spheres give the same step.
+* hub_get_coulomb / hub_set_coulomb (and the .npz cache on them): tensors
+  taken from one context and installed in another with the same spheres
+  give the same step.
 """
 
 import numpy as np
@@ -116,3 +117,32 @@ def test_coulomb_tensors_carry_over(clean):
     assert torch.equal(outs[0][0], ref[0])
     a.close()
     b.close()
+
+
+def test_coulomb_cache_file(clean, tmp_path):
+    """save_coulomb / load_coulomb: an .npz file of the tensors keyed by
+    sphere; a context with the same spheres takes them all, one with a
+    changed radius on one site takes the others."""
+    cfg, psi, f_d, ref, _ = clean
+    a = _context(cfg)
+    a.coulomb(-1)
+    path = str(tmp_path / "coulomb.npz")
+    assert a.save_coulomb(path) == a.nsites
+    b = _context(cfg)
+    assert b.load_coulomb(path) == b.nsites
+    for s in range(a.nsites):
+        assert torch.equal(a.get_coulomb(s), b.get_coulomb(s))
+    bufs = b.step_buffers(cfg.nstates)
+    h = torch.zeros_like(psi)
+    b.step(psi, f_d, h, mode="batched", bufs=bufs)
+    torch.cuda.synchronize()
+    assert torch.equal(h, ref[0])
+    sites = [dict(s) for s in cfg.sites]
+    sites[0]["rc"] = sites[0]["rc"] + 0.1
+    d = H.Hubbard(cfg.cell, cfg.ngrid, sites, kpts=cfg.kpts, kweights=cfg.kweights, spin=cfg.spin,
+                  is_complex=cfg.is_complex, precision="f32")
+    assert d.load_coulomb(path) == d.nsites - 1
+    with pytest.raises(H.HubError):
+        d.get_coulomb(0)
+    for x in (a, b, d):
+        x.close()
