@@ -29,6 +29,8 @@ def hubbard_step(system, psi, f, spheres=None, tensors=None, ueff_fixed=None,
     not be held whole; each block goes to ``on_block(s0, hpsi_block)`` and
     the returned hpsi is None.  The arithmetic of every column is the same.
     """
+    if apply_block is not None and form != "sphere":
+        raise ValueError("apply_block evaluates the sphere form of V_U psi")
     sps = spheres if spheres is not None else projection.all_spheres(system)
     if form == "fullgrid":
         c = projection.project_fullgrid(system, psi, sps)
