@@ -215,7 +215,9 @@ int hub_set_stream(hub_ctx* ctx, void* stream);
  * state-gradient forces (0 before the first hub_forces_state_gradient),
  * 14 passes of the grouped apply (points covered by more than 16 orbitals
  * have their covers split over passes; 0 without a grouped work list),
- * 15 device allocations (hipMalloc) the context has made so far. */
+ * 15 device allocations (hipMalloc) the context has made so far, 16 step
+ * graphs captured so far (HUB_STEP_GRAPH keeps the last two argument sets'
+ * graphs; a third set replaces the one used least recently). */
 int hub_query(const hub_ctx* ctx, int what, int64_t* value);
 
 /* Per-site data after hub_finalize_host: L = 2l+1, offset of its first
@@ -392,8 +394,10 @@ int hub_current(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const do
  * (n, N-bar, P-bar) -> U-bar, J-bar, U_eff (or fixed U) -> hpsi += alpha V_U psi.
  * All pointers are device pointers owned by the caller; see the layouts
  * above.  mode: HUB_STEP_BATCHED, HUB_STEP_GRAPH (captured once per distinct
- * argument set and replayed) or HUB_STEP_PERSITE (one launch per site and
- * stage).  Needs the Coulomb tensors unless every site has a fixed U. */
+ * argument set and replayed; the graphs of the last two argument sets are
+ * kept, counting hub_step_current's output pointer as an argument) or
+ * HUB_STEP_PERSITE (one launch per site and stage).  Needs the Coulomb
+ * tensors unless every site has a fixed U. */
 typedef struct hub_step_io {
     const void* psi; int64_t ld; int nstates;
     const double* f;

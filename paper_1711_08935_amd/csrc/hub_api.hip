@@ -163,10 +163,19 @@ struct hub_ctx {
     double prof_ms[HUB_NSTAGES] = {0};
     int64_t prof_n[HUB_NSTAGES] = {0};
 
-    // captured step
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    GraphKey gkey;
+    // captured steps: two, so that a caller that alternates between two
+    // argument sets (e.g. hub_step and, every few steps, hub_step_current)
+    // replays both without capturing again; the least recently used one is
+    // replaced
+    struct GraphSlot {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        GraphKey key;
+        uint64_t used = 0;
+    };
+    GraphSlot gslot[2];
+    uint64_t gclock = 0;
+    int64_t ncapture = 0;                    // step graphs captured so far (hub_query 16)
 
     int nsets() const { return spin_mode == HUB_SPINOR ? nk : nk * (spin_mode == HUB_COLLINEAR ? 2 : 1); }
     int nspin() const { return spin_mode == HUB_COLLINEAR ? 2 : 1; }
@@ -212,6 +221,8 @@ hipError_t upload(hub_ctx* c, T** dst, const std::vector<T>& src, size_t& bytes)
     return e;
 }
 
+void drop_graph(hub_ctx* c);
+
 // Frees every device table and workspace and leaves the pointers null (so a
 // failed hub_finalize can be retried and hub_destroy frees nothing twice).
 void release(hub_ctx* c) {
@@ -229,8 +240,7 @@ void release(hub_ctx* c) {
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab); f(c->d_st_tab_dn);
     f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift); f(c->d_gd0); f(c->d_gfdel);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
+    drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (int k = 0; k < HUB_NCLASS; ++k) {
         if (c->side[k]) (void)hipStreamDestroy(c->side[k]);
@@ -241,16 +251,18 @@ void release(hub_ctx* c) {
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     c->fork_ev = nullptr;
     c->cap_stream = nullptr;
-    c->gexec = nullptr;
-    c->graph = nullptr;
+}
+
+void drop_slot(hub_ctx::GraphSlot& g) {
+    if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.gexec = nullptr;
+    g.graph = nullptr;
+    g.key.valid = false;
 }
 
 void drop_graph(hub_ctx* c) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->gexec = nullptr;
-    c->graph = nullptr;
-    c->gkey.valid = false;
+    for (auto& g : c->gslot) drop_slot(g);
 }
 
 // Stage timer: records an event pair around the launches of one stage when
@@ -935,10 +947,16 @@ int step_impl(hub_ctx* c, const hub_step_io* io, int mode, double* jcur) {
     if (st) return st;
     if (mode != HUB_STEP_GRAPH) return run_step(c, io, mode == HUB_STEP_PERSITE, jcur);
 
-    const bool same = c->gkey.valid && c->gkey.ncol == ncol && c->gkey.jcur == jcur &&
-                      std::memcmp(&c->gkey.io, io, sizeof(hub_step_io)) == 0;
-    if (!same) {
-        drop_graph(c);
+    hub_ctx::GraphSlot* slot = nullptr;
+    for (auto& g : c->gslot)
+        if (g.key.valid && g.key.ncol == ncol && g.key.jcur == jcur &&
+            std::memcmp(&g.key.io, io, sizeof(hub_step_io)) == 0)
+            slot = &g;
+    if (!slot) {
+        slot = &c->gslot[0];
+        for (auto& g : c->gslot)
+            if (!g.key.valid || g.used < slot->used) slot = &g;
+        drop_slot(*slot);
         HUB_TRY(hipStreamSynchronize(c->stream));
         hipStream_t keep = c->stream;
         c->stream = c->cap_stream;
@@ -954,18 +972,20 @@ int step_impl(hub_ctx* c, const hub_step_io* io, int mode, double* jcur) {
             return st;
         }
         if (e != hipSuccess) return map_err(e);
-        c->graph = g;
-        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        slot->graph = g;
+        e = hipGraphInstantiate(&slot->gexec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            drop_graph(c);
+            drop_slot(*slot);
             return map_err(e);
         }
-        c->gkey.io = *io;
-        c->gkey.ncol = ncol;
-        c->gkey.jcur = jcur;
-        c->gkey.valid = true;
+        slot->key.io = *io;
+        slot->key.ncol = ncol;
+        slot->key.jcur = jcur;
+        slot->key.valid = true;
+        ++c->ncapture;
     }
-    HUB_TRY(hipGraphLaunch(c->gexec, c->stream));
+    slot->used = ++c->gclock;
+    HUB_TRY(hipGraphLaunch(slot->gexec, c->stream));
     return HUB_OK;
 }
 
@@ -1266,6 +1286,7 @@ int hub_query(const hub_ctx* c, int what, int64_t* v) {
     case 13: *v = c->stencil_entries; break;
     case 14: *v = T.grouped.ok ? T.grouped.npass : 0; break;
     case 15: *v = c->nalloc; break;
+    case 16: *v = c->ncapture; break;
     default: return HUB_EINVAL;
     }
     return HUB_OK;

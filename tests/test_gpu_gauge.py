@@ -219,6 +219,33 @@ def test_step_current_without_field(case, policy):
         hub.set_class_launch("merged")
 
 
+def test_alternating_step_graphs_are_kept(case):
+    """hub_step and hub_step_current alternating in graph mode replay their
+    two captured graphs (hub_query 16 counts captures), each giving what the
+    batched mode gives."""
+    hub, psi_d, f_d = case["hub"], case["psi_d"], case["f_d"]
+    S = case["cfg"].nstates
+    bufs = hub.step_buffers(S)
+    J = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
+    hb = torch.zeros_like(psi_d)
+    hub.step(psi_d, f_d, hb, mode="batched", bufs=bufs)
+    hcb = torch.zeros_like(psi_d)
+    Jb = J.clone()
+    hub.step(psi_d, f_d, hcb, mode="batched", bufs=bufs, current=Jb)
+    torch.cuda.synchronize()
+    n0 = hub.query(16)
+    h = torch.empty_like(psi_d)
+    hc = torch.empty_like(psi_d)
+    for _ in range(3):
+        h.zero_()
+        hub.step(psi_d, f_d, h, mode="graph", bufs=bufs)
+        hc.zero_()
+        hub.step(psi_d, f_d, hc, mode="graph", bufs=bufs, current=J)
+        torch.cuda.synchronize()
+        assert torch.equal(h, hb) and torch.equal(hc, hcb) and torch.equal(J, Jb)
+    assert hub.query(16) - n0 == 2
+
+
 def test_step_current_rejects_bad_output(case):
     hub, psi_d, f_d = case["hub"], case["psi_d"], case["f_d"]
     bufs = hub.step_buffers(case["cfg"].nstates)
