@@ -62,6 +62,14 @@ def test_strerror_and_invalid_arguments():
     # device entry points refuse to run before hub_finalize (no GPU touched)
     assert lib.hub_project(ctx, ctypes.c_void_p(1), 8, 8, ctypes.c_void_p(1)) == H.HUB_ESTATE
     assert lib.hub_step(ctx, None, 0) == H.HUB_EINVAL
+    assert lib.hub_step_current(ctx, None, None, 0) == H.HUB_EINVAL                  # no current output
+    io = H.StepIO()
+    assert lib.hub_step_current(ctx, ctypes.byref(io), ctypes.c_void_p(8), 0) == H.HUB_ESTATE   # not on a GPU yet
+    assert lib.hub_get_coulomb(ctx, 0, ctypes.c_void_p(8)) == H.HUB_ESTATE
+    assert lib.hub_set_coulomb(ctx, 0, ctypes.c_void_p(8)) == H.HUB_ESTATE
+    assert lib.hub_get_coulomb(ctx, 0, None) == H.HUB_EINVAL
+    assert lib.hub_set_coulomb(ctx, 0, None) == H.HUB_EINVAL
+    assert lib.hub_query(ctx, 16, ctypes.byref(v)) == H.HUB_OK and v.value == 0      # no graph captured
     assert lib.hub_destroy(ctx) == H.HUB_OK
     # a sphere that holds no grid point is rejected
     ctx2 = ctypes.c_void_p()
