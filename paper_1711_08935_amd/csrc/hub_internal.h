@@ -53,8 +53,8 @@ struct SiteSphere {
 };
 
 // Largest number of functions (orbitals of all covering sites) a grouped
-// chunk may carry; beyond it the grouped work list is not built and the
-// layered per-site work list serves every launch.
+// chunk may carry; the covers of a point with more are split over passes
+// of at most this many functions each.
 #define HUB_GF_MAX 16
 
 // Work list grouped by cover signature: every grid point covered by any
