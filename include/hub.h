@@ -390,7 +390,7 @@ int hub_set_vector_potential(hub_ctx* ctx, const double* A);
 int hub_current(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, const double* c,
                 const double* f, const double* Ueff, const double* n, double* J);
 
-/* One whole Hubbard step (the metric's unit of work): project -> occupations
+/* One whole Hubbard step: project -> occupations
  * (n, N-bar, P-bar) -> U-bar, J-bar, U_eff (or fixed U) -> hpsi += alpha V_U psi.
  * All pointers are device pointers owned by the caller; see the layouts
  * above.  mode: HUB_STEP_BATCHED, HUB_STEP_GRAPH (captured once per distinct
