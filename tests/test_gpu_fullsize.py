@@ -252,8 +252,13 @@ def test_spinor_layers_full_size_spin_dependent():
 
 
 @pytest.mark.timeout(900)
-def test_rt_batched_full_size_sampled():
-    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("rt_batched", "f32")
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_rt_batched_full_size_sampled(prec):
+    """The 1024-state batched workload in both storage precisions (FP64: the
+    states of the plain FP64 path the bench compares with): every projection
+    and matrix, U and J, V_U psi on sampled columns against the oracle; in
+    FP64 the per-site step (one launch per site and stage) as well."""
+    cfg, hub, psi, f, f_d, bufs, hpsi = _setup("rt_batched", prec)
     sys_ = to_system(cfg)
     sps = OP.all_spheres(sys_)
     used = psi[0].cpu().numpy().astype(np.float64)[None]            # 1.7M x 1024 FP64 on the host
@@ -271,7 +276,16 @@ def test_rt_batched_full_size_sampled():
     V = [OPOT.potential_matrix(sys_, ref["U"][I] - ref["J"][I], n[I]) for I in range(len(sps))]
     h_ref = OS.apply_sphere(sys_, c_ref[:, :, cols], V, sps).real
     h = hpsi[0][:, torch.from_numpy(cols).cuda()].cpu().numpy()[None]
-    assert normwise(h, h_ref) < 2e-7
+    assert normwise(h, h_ref) < (2e-7 if prec == "f32" else 1e-12)
+    if prec == "f64":
+        bp = hub.step_buffers(cfg.nstates)
+        hp = torch.zeros_like(psi)
+        hub.step(psi, f_d, hp, mode="persite", bufs=bp)
+        torch.cuda.synchronize()
+        assert normwise(bp["c"].cpu().numpy(), c_ref) < 1e-12
+        _compare_matrices(hub, bp, ref)
+        hps = hp[0][:, torch.from_numpy(cols).cuda()].cpu().numpy()[None]
+        assert normwise(hps, h_ref) < 1e-12
 
 
 @pytest.mark.timeout(900)
