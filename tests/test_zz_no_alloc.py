@@ -1,7 +1,8 @@
 """hub_step_noalloc, called through the C ABI, against hub_step in its
 batched mode on the same inputs (the same kernels in the same order: the
 outputs must be bitwise equal), on two calls in a row whose second has fewer
-states, for a complex collinear, a real and a spinor context.  The context's
+states, for a complex collinear (also under a vector potential), a real and
+a spinor context.  The context's
 device-allocation count (hub_query 15) does not move across the calls, while
 a plain hub_step on a fresh context allocates its workspaces; a step whose
 workspace exceeds HUB_SCRATCH_BYTES is refused before any launch."""
@@ -28,15 +29,20 @@ def _io(psi, ld, nst, f, hpsi, ldh, b):
                     b["J"].data_ptr(), b["Ueff"].data_ptr(), b["status"].data_ptr())
 
 
-@pytest.mark.parametrize("name,prec", [("nio_afm", "f64"), ("rt_batched", "f32"), ("spinor_layers", "f32")])
-def test_noalloc_step_matches_batched_step(name, prec):
-    print(f"\n[noalloc] {name} {prec}", flush=True)
+@pytest.mark.parametrize("name,prec,field", [("nio_afm", "f64", False), ("rt_batched", "f32", False),
+                                             ("spinor_layers", "f32", False), ("nio_afm", "f32", True)])
+def test_noalloc_step_matches_batched_step(name, prec, field):
+    print(f"\n[noalloc] {name} {prec} field={field}", flush=True)
     cfg = make_config(name, small=True)
     psi, f = states_and_occupations(cfg)
     hub = make_hub(cfg, prec, chunk=256)
     psi_d, _ = device_states(hub, psi)
     f_d = torch.from_numpy(f).cuda()
     hub.coulomb(-1)
+    if field:
+        # the velocity gauge's tables are made when the field is set, so the
+        # step under a field allocates nothing either
+        hub.set_vector_potential([0.05, -0.03, 0.02])
     S = cfg.nstates
     ld = hub.ncol(S)
     lib = H.lib()
