@@ -295,19 +295,25 @@ __global__ void __launch_bounds__(NB) k_occ_part(const OccArgs a) {
     }
 }
 
-// Sums the splits of one site and channel in order: out = n and P-bar
-// entries (blocks of the channel, zeros outside the L x L corner), one
-// thread per (entry, value) so that every split's load is in flight.
-__device__ void occ_final_sums(const OccArgs& a, int site, int ch, int nchan, double* n, double* pbar,
+// Sums the splits of one site and NCH channels (ch0, ch0 + 1, ...) in
+// order: out = n and P-bar entries (blocks of the channel, zeros outside the
+// L x L corner), one thread per (entry, value) so that every split's load is
+// in flight, the loads of all NCH channels issued before the adds (each
+// channel's sum in split order, as with one channel at a time).
+template <int NCH>
+__device__ void occ_final_sums(const OccArgs& a, int site, int ch0, int nchan, double* n, double* pbar,
                                double (*Nf)[7][7][2], double (*P)[7][7][2]) {
     const int L = a.site_L[site];
     const int ncp = a.spinor ? 2 * L : L;
-    const double* w = a.ws + (static_cast<int64_t>(site) * nchan + ch) * a.nsplit * (HUB_OCC_PAIRS * 4);
+    const int64_t chstride = static_cast<int64_t>(a.nsplit) * (HUB_OCC_PAIRS * 4);
+    const double* w = a.ws + (static_cast<int64_t>(site) * nchan + ch0) * chstride;
     const int nblk_here = a.spinor ? 4 : 1;
     for (int o = threadIdx.x; o < nblk_here * 49 * 4; o += NB) {
         const int r = o & 3, eb = o >> 2;
         const int blk = eb / 49, e = eb % 49, i = e / 7, j = e % 7;
-        double v = 0.0;
+        double v[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) v[c] = 0.0;
         if (i < L && j < L) {
             const int x = a.spinor ? blk / 2 : 0, y = a.spinor ? blk % 2 : 0;
             const int p = (x * L + i) * ncp + (y * L + j);
@@ -315,31 +321,38 @@ __device__ void occ_final_sums(const OccArgs& a, int site, int ch, int nchan, do
             // splits in batches of 8, every load of a batch issued before
             // the adds, which run in split order (splits past the end add 0)
             for (int z0 = 0; z0 < a.nsplit; z0 += 8) {
-                double t[8];
+                double t[NCH][8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int z = z0 + u < a.nsplit ? z0 + u : z0;
-                    t[u] = wp[static_cast<int64_t>(z) * HUB_OCC_PAIRS * 4];
-                }
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int z = z0 + u < a.nsplit ? z0 + u : z0;
+                        t[c][u] = wp[c * chstride + static_cast<int64_t>(z) * HUB_OCC_PAIRS * 4];
+                    }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v += z0 + u < a.nsplit ? t[u] : 0.0;
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[c] += z0 + u < a.nsplit ? t[c][u] : 0.0;
             }
         }
-        const int oblk = a.spinor ? blk : ch;
-        const int64_t base = ((static_cast<int64_t>(site) * a.nblk + oblk) * 49 + e) * 2;
-        if (r < 2) {
-            n[base + r] = v;
-            if (Nf) Nf[oblk][i][j][r] = v;
-        } else {
-            if (pbar) pbar[base + r - 2] = v;
-            if (P) P[oblk][i][j][r - 2] = v;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int oblk = a.spinor ? blk : ch0 + c;
+            const int64_t base = ((static_cast<int64_t>(site) * a.nblk + oblk) * 49 + e) * 2;
+            if (r < 2) {
+                n[base + r] = v[c];
+                if (Nf) Nf[oblk][i][j][r] = v[c];
+            } else {
+                if (pbar) pbar[base + r - 2] = v[c];
+                if (P) P[oblk][i][j][r - 2] = v[c];
+            }
         }
     }
 }
 
 __global__ void __launch_bounds__(NB) k_occ_final(const OccArgs a) {
-    occ_final_sums(a, blockIdx.x, blockIdx.y, gridDim.y, a.n, a.pbar, nullptr, nullptr);
+    occ_final_sums<1>(a, blockIdx.x, blockIdx.y, gridDim.y, a.n, a.pbar, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------- ACBN0
@@ -645,7 +658,10 @@ __global__ void __launch_bounds__(NB) k_step_occ_final(const OccArgs a, const Ac
 #pragma unroll 4
         for (int o = threadIdx.x; o < L * L * L * L; o += NB) sm.Ts[o] = Tg[o];
     }
-    for (int ch = 0; ch < nchan; ++ch) occ_final_sums(a, site, ch, nchan, a.n, a.pbar, sm.Nf, sm.P);
+    if (nchan == 2)
+        occ_final_sums<2>(a, site, 0, 2, a.n, a.pbar, sm.Nf, sm.P);
+    else
+        for (int ch = 0; ch < nchan; ++ch) occ_final_sums<1>(a, site, ch, nchan, a.n, a.pbar, sm.Nf, sm.P);
     __syncthreads();
     acbn0_site(u, site, sm, tens);
 }
