@@ -411,15 +411,14 @@ int hub_step(hub_ctx* ctx, const hub_step_io* io, int mode);
  * of the step's input states and potential: J[site][3] (device, caller
  * owned, overwritten) is what hub_current(psi, io->c, io->f, io->Ueff,
  * io->n, J) returns after the step, formed before the apply (so hpsi may
- * alias psi).  For complex states on the grouped work list without
- * spin-dependent orbitals (modes HUB_STEP_BATCHED and HUB_STEP_GRAPH) one
- * launch takes the projections c and the position-moment projections
+ * alias psi).  For complex states on the grouped work list (modes
+ * HUB_STEP_BATCHED and HUB_STEP_GRAPH; spin-dependent orbitals included)
+ * one launch takes the projections c and the position-moment projections
  * rho_{a,i} in the same pass over the states; it sums each column's entries
  * in one sequence, so c and everything that follows from it (n, U, J,
  * U_eff, hpsi) agree with hub_step's to rounding, and J with hub_current's.
- * Elsewhere (HUB_STEP_PERSITE, the per-site work list, spin-dependent
- * orbitals, real states) it runs hub_step's stages, bit for bit, and
- * hub_current's own projection.  The first fused call uploads the moment
+ * Elsewhere (HUB_STEP_PERSITE, the per-site work list, real states) it runs
+ * hub_step's stages, bit for bit, and hub_current's own projection.  The first fused call uploads the moment
  * tables (three displacements per grouped point).  Errors: those of
  * hub_step; HUB_EINVAL for a null J. */
 int hub_step_current(hub_ctx* ctx, const hub_step_io* io, double* J, int mode);

@@ -490,7 +490,7 @@ size_t part_need_moments(const hub_ctx* c, int ncol) {
                     static_cast<size_t>(4) * c->nsets() * c->T.grouped.part_rows * ncol * c->ncplx());
 }
 // whether hub_step_current takes the moments in the step's own projection
-bool fused_moments(const hub_ctx* c) { return grouped(c) && c->is_complex && !c->T.spindep; }
+bool fused_moments(const hub_ctx* c) { return grouped(c) && c->is_complex; }
 
 // q0, nq: the state sets projected (psi and out hold those sets only);
 // nq < 0: every set of the context.

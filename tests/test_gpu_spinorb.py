@@ -176,15 +176,17 @@ def test_velocity_gauge(case):
         bufs = hub.step_buffers(case["cfg"].nstates)
         hg = torch.zeros_like(case["psi_d"])
         hub.step(case["psi_d"], case["f_d"], hg, mode="graph", bufs=bufs)
-        # the step with the current: spin-dependent orbitals take the step's
-        # stages and the separate moment projection, so bit for bit hub_current
+        # the step with the current from its own pass: each component's
+        # moments about its site from the spin-dependent orbitals, summed in
+        # the moment launch's order (to rounding hub_current's)
         bufs2 = hub.step_buffers(case["cfg"].nstates)
         hs = torch.zeros_like(case["psi_d"])
         Js = torch.empty((hub.nsites, 3), dtype=torch.float64, device="cuda")
         hub.step(case["psi_d"], case["f_d"], hs, mode="graph", bufs=bufs2, current=Js)
         torch.cuda.synchronize()
-        assert torch.equal(hs, hg)
-        assert np.array_equal(Js.cpu().numpy(), J)
+        Js = Js.cpu().numpy()
+        assert normwise(hs.cpu().numpy(), hg.cpu().numpy()) < (1e-12 if case["prec"] == "f64" else 2e-7)
+        assert normwise(Js, J) < 1e-12
         hub.set_worklist(False)
         with pytest.raises(H.HubError):
             hub.project(case["psi_d"])
@@ -202,6 +204,7 @@ def test_velocity_gauge(case):
     assert normwise(hg.cpu().numpy(), href) < bar
     Jo = GA.current(sys_, cA, SO.moment_projections_spin(sys_, used, A), V, f)
     assert normwise(J, Jo) < 1e-11
+    assert normwise(Js, Jo) < 1e-11
 
 
 def test_state_gradient_forces(case):
