@@ -102,6 +102,8 @@ struct hub_ctx {
     bool use_grouped = true;
     int class_policy = HUB_CLASSES_MERGED;
     int32_t* d_gall_m = nullptr;             // chunk list of the merged launch, by pass
+    int32_t* d_gmom = nullptr;               // work items of the moment projection (k_project_mom.h)
+    int nmom = 0;
     std::vector<int> gpass_ptr;              // d_gall_m[gpass_ptr[p], gpass_ptr[p+1]): chunks of pass p
     int gcls_ptr[HUB_NCLASS + 1] = {};       // d_gall[gcls_ptr[k-1], gcls_ptr[k]): chunks of class k
     HubChunk* d_gchunks = nullptr;
@@ -238,7 +240,7 @@ void release(hub_ctx* c) {
     c->part_cap = c->grad_cap = c->nbar_cap = c->sink_cap = c->occ_cap = 0;
     f(c->d_phi2); f(c->d_gphi_dn); f(c->d_mphi_dn);
     f(c->d_st_chunks); f(c->d_st_all); f(c->d_st_gidx); f(c->d_st_site_ptr); f(c->d_st_site_ids); f(c->d_st_tab); f(c->d_st_tab_dn);
-    f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
+    f(c->d_gchunks); f(c->d_gall); f(c->d_gall_m); f(c->d_gmom); f(c->d_ggidx); f(c->d_gf_orb); f(c->d_gf_img); f(c->d_gred_ptr);
     f(c->d_gred_row); f(c->d_gred_img); f(c->d_gtab); f(c->d_gspin_shift); f(c->d_gd0); f(c->d_gfdel);
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -529,14 +531,13 @@ int do_project(hub_ctx* c, const void* psi, int64_t ld, int nstates, double* out
         const int64_t pplane = static_cast<int64_t>(nq) * GT.part_rows * ncol * c->ncplx();
         if (mout) {
             // orbitals and position moments in one launch over every chunk
-            a.chunk_list = c->d_gall_m;
+            a.chunk_list = c->d_gmom;
             a.d0 = c->d_gd0;
             a.fdel = c->d_gfdel;
             a.pplane = pplane;
-            const int nch = GT.npass > 1 ? c->gpass_ptr[GT.npass] : c->gcls_ptr[HUB_NCLASS];
             StageTimer tm(c, HUB_STAGE_PROJECT);
-            HUB_TRY(c->precision == HUB_F64 ? launch_project_mom_f64(a, nch, nq, c->stream)
-                                            : launch_project_mom_f32(a, nch, nq, c->stream));
+            HUB_TRY(c->precision == HUB_F64 ? launch_project_mom_f64(a, c->nmom, nq, c->stream)
+                                            : launch_project_mom_f32(a, c->nmom, nq, c->stream));
         } else {
             StageTimer tm(c, HUB_STAGE_PROJECT);
             // one launch per function-count class
@@ -1225,6 +1226,25 @@ int hub_finalize(hub_ctx* c, void* stream) {
         for (int32_t i : gm) ++c->gpass_ptr[T.grouped.chunks[i].layer + 1];
         for (int p = 0; p < T.grouped.npass; ++p) c->gpass_ptr[p + 1] += c->gpass_ptr[p];
         up(&c->d_gall_m, gm);
+        // moment projection: one item per half of a chunk's functions, the
+        // costliest (entries times the FP64 instructions per entry) first
+        std::vector<int32_t> items;
+        std::vector<int64_t> cost;
+        for (int32_t i : gm) {
+            const HubChunk& C = T.grouped.chunks[i];
+            for (int h = 0; h * HUB_MOM_NFW < C.L; ++h) {
+                const int nfw = std::min(HUB_MOM_NFW, C.L - h * HUB_MOM_NFW);
+                items.push_back(2 * i + h);
+                cost.push_back(static_cast<int64_t>(C.ne) * (8 * nfw + 12));
+            }
+        }
+        std::vector<int32_t> order(items.size());
+        for (size_t x = 0; x < order.size(); ++x) order[x] = static_cast<int32_t>(x);
+        std::stable_sort(order.begin(), order.end(), [&cost](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+        std::vector<int32_t> mom(items.size());
+        for (size_t x = 0; x < order.size(); ++x) mom[x] = items[order[x]];
+        c->nmom = static_cast<int>(mom.size());
+        up(&c->d_gmom, mom);
         up(&c->d_ggidx, T.grouped.gidx);
         up(&c->d_gtab, T.grouped.tab);
         up(&c->d_gf_orb, T.grouped.f_orb);

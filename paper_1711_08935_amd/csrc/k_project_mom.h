@@ -13,14 +13,14 @@
 // about the function's own site, into four planes of the workspace; the
 // grouped reduction then applies dV and the Bloch phases to all four.
 //
-// Work mapping: a 1-D grid of (chunk, column tile) work-groups (hub_slot);
-// each lane owns one complex column of one state set (64 columns per wave);
-// a work-group has two waves, wave w taking functions 8w..8w+7 of the chunk
-// (the second wave of a chunk with at most 8 functions exits at once), so
-// both waves read the same rows, the second one mostly from the caches.
-// Per entry a wave does 4 x 2 x NFW FP64 FMAs on one row value, its
-// conversion and (under a field) its phase rotation: the orbital and moment
-// components share the row's load and preparation.
+// Work mapping: a 1-D grid of one-wave work-groups over (item, column tile)
+// (hub_slot); an item is one half of a chunk's functions (functions
+// 8h..8h+7), each lane owns one complex column of one state set (64 columns
+// per wave).  The host orders the items by their cost (entries times the
+// instructions per entry), longest first, so that short items fill the end
+// of the launch.  Per entry a wave does 4 x 2 x NFW FP64 FMAs on one row
+// value, its conversion and (under a field) its phase rotation: the orbital
+// and moment components share the row's load and preparation.
 
 #pragma once
 
@@ -32,8 +32,8 @@ namespace {
 // SIMD) measured faster than 6 or 4 (more waves per SIMD, but each point's
 // load and preparation repeated by more waves); rows per batch: 4 (8 spills
 // scalar registers and leaves two waves per SIMD).
-constexpr int MOM_NFW = 8;
-constexpr int MOM_WAVES = (HUB_GF_MAX + MOM_NFW - 1) / MOM_NFW;   // waves per work-group
+constexpr int MOM_NFW = HUB_MOM_NFW;
+static_assert(2 * MOM_NFW >= HUB_GF_MAX, "two halves cover a chunk's functions");
 constexpr int MOM_U = 4;
 
 template <typename T, int NFW, bool GAUGE>
@@ -166,17 +166,17 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
 }
 
 template <typename T, bool GAUGE>
-__global__ void __launch_bounds__(MOM_WAVES * HUB_WAVE)
+__global__ void __launch_bounds__(HUB_WAVE)
 k_project_mom(const ProjArgs a, const int32_t* __restrict__ gidx, const double* __restrict__ tab,
               const double* __restrict__ d0, const double* __restrict__ fdel, const double* __restrict__ pg,
               double* __restrict__ part) {
     const HubSlot slot = hub_slot(a.tiles);
     if (slot.chunk >= a.nchunks) return;
-    const int ci = a.chunk_list[slot.chunk];
+    const int item = a.chunk_list[slot.chunk];
+    const int ci = item >> 1;
     const HubChunk C = a.chunks[ci];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HUB_WAVE);
-    const int lane = threadIdx.x & (HUB_WAVE - 1);
-    const int f0 = wave * MOM_NFW;
+    const int lane = threadIdx.x;
+    const int f0 = (item & 1) * MOM_NFW;
     const int nfw = C.L - f0 < MOM_NFW ? C.L - f0 : MOM_NFW;
     if (nfw <= 0) return;
     const int tps = (a.ncol + HUB_WAVE - 1) / HUB_WAVE;     // column tiles per state set
@@ -193,22 +193,22 @@ k_project_mom(const ProjArgs a, const int32_t* __restrict__ gidx, const double* 
 #undef HUB_MCASE
 }
 
-// Launch over nchunks grouped chunks (every pass, functions <= 16 per
-// chunk) of complex states of storage type T.
+// Launch over nitems work items of grouped chunks (every pass, functions
+// <= 16 per chunk) of complex states of storage type T.
 template <typename T>
-hipError_t launch_project_mom_prec(const ProjArgs& a, int nchunks, int nq, hipStream_t st) {
-    if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+hipError_t launch_project_mom_prec(const ProjArgs& a, int nitems, int nq, hipStream_t st) {
+    if (nitems <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
     if (a.ncplx != 2 || !a.d0 || !a.fdel) return hipErrorInvalidValue;
     ProjArgs b = a;
-    b.nchunks = nchunks;
+    b.nchunks = nitems;
     b.tiles = static_cast<int>(static_cast<int64_t>(nq) * ((a.ncol + HUB_WAVE - 1) / HUB_WAVE));
-    const dim3 grid(static_cast<unsigned>(hub_slot_grid(nchunks, b.tiles)));
+    const dim3 grid(static_cast<unsigned>(hub_slot_grid(nitems, b.tiles)));
     if (a.pg)
-        hipLaunchKernelGGL((k_project_mom<T, true>), grid, dim3(MOM_WAVES * HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0,
-                           b.fdel, b.pg, b.part);
+        hipLaunchKernelGGL((k_project_mom<T, true>), grid, dim3(HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0, b.fdel,
+                           b.pg, b.part);
     else
-        hipLaunchKernelGGL((k_project_mom<T, false>), grid, dim3(MOM_WAVES * HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0,
-                           b.fdel, b.pg, b.part);
+        hipLaunchKernelGGL((k_project_mom<T, false>), grid, dim3(HUB_WAVE), 0, st, b, b.gidx, b.tab, b.d0, b.fdel,
+                           b.pg, b.part);
     return hipGetLastError();
 }
 

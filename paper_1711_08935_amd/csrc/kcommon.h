@@ -239,9 +239,12 @@ hipError_t launch_project_f32(const ProjArgs& a, int nchunks, int nq, int cplx, 
 hipError_t launch_project_f64(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
                               hipStream_t st);
 // orbital and position-moment projections of complex states over grouped
-// chunks (k_project_mom.h)
-hipError_t launch_project_mom_f32(const ProjArgs& a, int nchunks, int nq, hipStream_t st);
-hipError_t launch_project_mom_f64(const ProjArgs& a, int nchunks, int nq, hipStream_t st);
+// chunks (k_project_mom.h).  Work items: chunk * 2 + h, h the half of the
+// chunk's functions (h = 1 only for chunks with more than HUB_MOM_NFW
+// functions); a.chunk_list holds nitems of them.
+#define HUB_MOM_NFW 8
+hipError_t launch_project_mom_f32(const ProjArgs& a, int nitems, int nq, hipStream_t st);
+hipError_t launch_project_mom_f64(const ProjArgs& a, int nitems, int nq, hipStream_t st);
 hipError_t launch_apply_f32(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
                             hipStream_t st);
 hipError_t launch_apply_f64(const ApplyArgs& a, int nchunks, int nq, int cplx, int cpl, int waves,
