@@ -49,7 +49,7 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
     const int32_t* __restrict__ gi = gidx + C.e0;
     const double* __restrict__ tb = tab + C.phi0 + f0;          // entry e: tb[e * NF + f]
     const double* __restrict__ dp = d0 + 3 * static_cast<int64_t>(C.e0);
-    const int64_t rowstride = a.ld * 2;
+    const uint32_t rowstride = static_cast<uint32_t>(a.ld * 2);   // elements (checked at launch)
 
     double acc[4][NFW][2];
 #pragma unroll
@@ -63,11 +63,22 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
         double w[NFW];
         double d[3];
     };
-    auto read_ent = [&](int e, Ent& x) {
+    // read at 32-bit byte offsets from the chunk's table and displacement
+    // rows (a chunk's are far below 4 GiB), advanced entry by entry; the
+    // offsets stop at the last entry, so the read after it repeats it
+    const uint32_t wstep = static_cast<uint32_t>(NF) * sizeof(double);
+    const uint32_t wlast = static_cast<uint32_t>(C.ne - 1) * wstep;
+    const uint32_t dlast = static_cast<uint32_t>(C.ne - 1) * (3 * sizeof(double));
+    uint32_t wnext = 0, dnext = 0;
+    auto read_next = [&](Ent& x) {
+        const char* __restrict__ wb = reinterpret_cast<const char*>(tb) + wnext;
+        const char* __restrict__ db = reinterpret_cast<const char*>(dp) + dnext;
 #pragma unroll
-        for (int f = 0; f < NFW; ++f) x.w[f] = tb[static_cast<int64_t>(e) * NF + f];
+        for (int f = 0; f < NFW; ++f) x.w[f] = *reinterpret_cast<const double*>(wb + f * sizeof(double));
 #pragma unroll
-        for (int i = 0; i < 3; ++i) x.d[i] = dp[3 * e + i];
+        for (int i = 0; i < 3; ++i) x.d[i] = *reinterpret_cast<const double*>(db + i * sizeof(double));
+        wnext = min(wnext + wstep, wlast);
+        dnext = min(dnext + static_cast<uint32_t>(3 * sizeof(double)), dlast);
     };
     // grid points of batch b (read one batch before their rows are loaded)
     auto read_idx = [&](int b, int (&g)[U]) {
@@ -78,10 +89,13 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int g = gg[u];
-            load_row_stream<T, 2>(psi_q + static_cast<int64_t>(g) * rowstride + 2 * colc, r[u]);
+            load_row_stream<T, 2>(psi_q + static_cast<uint64_t>(static_cast<uint32_t>(g)) * rowstride + 2 * colc,
+                                  r[u]);
             if constexpr (GAUGE) {
-                ph[u][0] = pg[2 * static_cast<int64_t>(g)];
-                ph[u][1] = pg[2 * static_cast<int64_t>(g) + 1];
+                const char* __restrict__ pb = reinterpret_cast<const char*>(pg) +
+                                              static_cast<uint32_t>(g) * static_cast<uint32_t>(2 * sizeof(double));
+                ph[u][0] = *reinterpret_cast<const double*>(pb);
+                ph[u][1] = *reinterpret_cast<const double*>(pb + sizeof(double));
             }
         }
     };
@@ -113,12 +127,11 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
     // read while the current one is contracted (the scheduling barriers keep
     // those reads from being hoisted together).  The entry after the last
     // re-reads the last one.
-    auto fma_batch = [&](int b, Ent& cur, const T (&r)[U][2], const double (&ph)[U][2]) {
+    auto fma_batch = [&](Ent& cur, const T (&r)[U][2], const double (&ph)[U][2]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             Ent nx;
-            const int e = b * U + u + 1;
-            read_ent(e < C.ne ? e : C.ne - 1, nx);
+            read_next(nx);
             fma_entry(cur, r[u], ph[u]);
             __builtin_amdgcn_sched_barrier(0);
             cur = nx;
@@ -133,7 +146,7 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
         int ga[U], gb[U];
         Ent cur;
         read_idx(0, ga);
-        read_ent(0, cur);
+        read_next(cur);
         load_batch(ga, ra, pa);
         read_idx(nbt > 1 ? 1 : 0, gb);
         int b = 0;
@@ -141,13 +154,13 @@ __device__ __forceinline__ void mom_body(const ProjArgs& a, const HubChunk& C, i
             load_batch(gb, rb, pb);
             read_idx(b + 2 < nbt ? b + 2 : nbt - 1, ga);
             __builtin_amdgcn_sched_barrier(0);
-            fma_batch(b, cur, ra, pa);
+            fma_batch(cur, ra, pa);
             load_batch(ga, ra, pa);
             read_idx(b + 3 < nbt ? b + 3 : nbt - 1, gb);
             __builtin_amdgcn_sched_barrier(0);
-            fma_batch(b + 1, cur, rb, pb);
+            fma_batch(cur, rb, pb);
         }
-        if (b < nbt) fma_batch(b, cur, ra, pa);
+        if (b < nbt) fma_batch(cur, ra, pa);
     }
     if (!active) return;
     const double* __restrict__ del = fdel + (static_cast<int64_t>(ci) * HUB_GF_MAX + f0) * 3;
@@ -198,7 +211,8 @@ k_project_mom(const ProjArgs a, const int32_t* __restrict__ gidx, const double* 
 template <typename T>
 hipError_t launch_project_mom_prec(const ProjArgs& a, int nitems, int nq, hipStream_t st) {
     if (nitems <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
-    if (a.ncplx != 2 || !a.d0 || !a.fdel) return hipErrorInvalidValue;
+    if (a.ncplx != 2 || !a.d0 || !a.fdel || a.ld < 0 || a.ld * 2 > static_cast<int64_t>(UINT32_MAX))
+        return hipErrorInvalidValue;
     ProjArgs b = a;
     b.nchunks = nitems;
     b.tiles = static_cast<int>(static_cast<int64_t>(nq) * ((a.ncol + HUB_WAVE - 1) / HUB_WAVE));
