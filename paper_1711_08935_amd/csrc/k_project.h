@@ -92,14 +92,21 @@ __device__ __forceinline__ void project_body(const ProjArgs& a, const HubChunk& 
     // orbital values
     const int nbt = nj / U;
     // grid-point phases of a batch (velocity gauge; unused otherwise)
+    // row offsets as a 32-bit index times a 32-bit stride (one scalar
+    // multiply pair on the path from the index read to the row load; the
+    // stride is checked at launch), phases at 32-bit byte offsets
+    const uint32_t rowstride = static_cast<uint32_t>(a.ld * NC);
     auto load_batch = [&](int b, T (&r)[U][NV], double (&ph)[U][2]) {
         const int32_t* __restrict__ gb = gi + b * U;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            load_row_stream<T, NV>(psi_q + static_cast<int64_t>(gb[u]) * a.ld * NC + lofs, r[u]);
+            const uint32_t g = static_cast<uint32_t>(gb[u]);
+            load_row_stream<T, NV>(psi_q + static_cast<uint64_t>(g) * rowstride + lofs, r[u]);
             if constexpr (GAUGE) {
-                ph[u][0] = pg[2 * static_cast<int64_t>(gb[u])];
-                ph[u][1] = pg[2 * static_cast<int64_t>(gb[u]) + 1];
+                const char* __restrict__ pb =
+                    reinterpret_cast<const char*>(pg) + g * static_cast<uint32_t>(2 * sizeof(double));
+                ph[u][0] = *reinterpret_cast<const double*>(pb);
+                ph[u][1] = *reinterpret_cast<const double*>(pb + sizeof(double));
             }
         }
     };
@@ -389,6 +396,7 @@ template <typename T>
 hipError_t launch_project_prec(const ProjArgs& a, int nchunks, int nq, int cplx, int cpl, int waves, int cls,
                                hipStream_t st) {
     if (nchunks <= 0 || nq <= 0 || a.ncol <= 0) return hipSuccess;
+    if (a.ld < 0 || a.ld * a.ncplx > static_cast<int64_t>(UINT32_MAX)) return hipErrorInvalidValue;
     if (a.tabmult == 3) return cls == 0 ? launch_g<T, 3, 0>(a, nchunks, nq, cplx, cpl, waves, st)
                                         : hipErrorInvalidValue;
     // spin-dependent orbitals: complex spinor states, per-site chunks
