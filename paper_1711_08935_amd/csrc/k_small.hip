@@ -770,10 +770,14 @@ __global__ void k_fll(const FllArgs a) {
 // ---------------------------------------------------------------- forces
 // F_i = g_s 2 Re sum_q w_k sum_col f_s sum_a conj(d_{a,i}(col)) B_a(col),
 // B = V c as in the apply kernel (Sec. IV with U_eff fixed).  One
-// work-group per site: the site's potential blocks V are formed once in LDS,
-// then each thread takes (state set, column) pairs, holds the pair's L (two
-// spin components: 2L) projections in registers and forms B from them.
-__global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
+// work-group of NBF threads per site: the site's potential blocks V are
+// formed once in LDS, then each thread takes (state set, column) pairs (one
+// each for up to NBF pairs per site), holds the pair's L (two spin
+// components: 2L) projections in registers and forms B from them; the
+// threads' sums are added within each wave (butterfly) and then over the
+// waves in order.
+constexpr int NBF = 1024;
+__global__ void __launch_bounds__(NBF) k_forces(const ForceArgs a) {
     const int site = blockIdx.x;
     const int L = a.site_L[site];
     const int orb0 = a.site_orb0[site];
@@ -783,7 +787,7 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
     // V[blk][a][b] = U (delta_ab / 2 on the spin-diagonal blocks - n_blk[b][a])
     __shared__ double V[4][7][7][2];
     const double* nb = a.n + static_cast<int64_t>(site) * a.nblk * 98;
-    for (int o = tid; o < a.nblk * 49; o += NB) {
+    for (int o = tid; o < a.nblk * 49; o += NBF) {
         const int blk = o / 49, r = o - blk * 49, ai = r / 7, b = r - ai * 7;
         const bool diag = a.spinor ? (blk == 0 || blk == 3) : true;
         V[blk][ai][b][0] = U * ((ai == b && diag) ? 0.5 : 0.0) - U * nb[blk * 98 + (b * 7 + ai) * 2];
@@ -792,7 +796,7 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
     __syncthreads();
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t total = static_cast<int64_t>(a.nq) * a.ncol;
-    for (int64_t o = tid; o < total; o += NB) {
+    for (int64_t o = tid; o < total; o += NBF) {
         const int q = static_cast<int>(o / a.ncol);
         const int col = static_cast<int>(o % a.ncol);
         const int k = a.spinor ? q : q / a.nspin;
@@ -838,17 +842,19 @@ __global__ void __launch_bounds__(NB) k_forces(const ForceArgs a) {
             }
         }
     }
-    __shared__ double red[NB][3];
-    for (int i = 0; i < 3; ++i) red[tid][i] = acc[i];
+    __shared__ double red[NBF / 64][3];
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int i = 0; i < 3; ++i) acc[i] += __shfl_xor(acc[i], m, 64);
+    if ((tid & 63) == 0)
+        for (int i = 0; i < 3; ++i) red[tid >> 6][i] = acc[i];
     __syncthreads();
-    for (int w = NB / 2; w > 0; w >>= 1) {
-        if (tid < w)
-            for (int i = 0; i < 3; ++i) red[tid][i] += red[tid + w][i];
-        __syncthreads();
-    }
     if (tid == 0) {
         const double gs = (a.nblk == 1) ? 2.0 : 1.0;
-        for (int i = 0; i < 3; ++i) a.F[site * 3 + i] = a.scale * (gs * 2.0 * red[0][i]);
+        for (int i = 0; i < 3; ++i) {
+            double v = 0.0;
+            for (int w = 0; w < NBF / 64; ++w) v += red[w][i];
+            a.F[site * 3 + i] = a.scale * (gs * 2.0 * v);
+        }
     }
 }
 
@@ -985,7 +991,7 @@ hipError_t launch_energy(const EnergyArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_forces(const ForceArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_forces, dim3(a.nsites), dim3(NB), 0, st, a);
+    hipLaunchKernelGGL(k_forces, dim3(a.nsites), dim3(NBF), 0, st, a);
     return hipGetLastError();
 }
 
