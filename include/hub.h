@@ -372,7 +372,9 @@ int hub_energy_gradient(hub_ctx* ctx, const void* psi, int64_t ld, int nstates, 
  * of every later call and graph replay use V^A = exp(-i A.r) V_U exp(i A.r):
  * the phase of sphere point p is exp(i (k+A).T_p) exp(i A.r_g), r_g the
  * cell grid point and T_p its lattice image (r_p = r_g + T_p, the unfolded
- * point).  Complex contexts only (HUB_EINVAL otherwise).  The device tables
+ * point).  Complex contexts of at most 2^28 - 1 grid points only (the
+ * phase table is addressed with 32-bit byte offsets; HUB_EINVAL
+ * otherwise).  The device tables
  * are updated on the context's stream, so a captured step graph stays valid
  * while the field is on; switching it on or off rebuilds the graph at the
  * next graph-mode hub_step.  With a field the grouped work list is launched

@@ -1678,7 +1678,9 @@ int hub_step_noalloc(hub_ctx* c, const hub_step_io* io) {
 int hub_set_vector_potential(hub_ctx* c, const double* A) {
     if (!c) return HUB_EINVAL;
     if (A) {
-        if (!c->is_complex) return HUB_EINVAL;
+        // the kernels address the grid-point phase table with 32-bit byte
+        // offsets (16 bytes per point)
+        if (!c->is_complex || c->G() > static_cast<int64_t>(UINT32_MAX / 16)) return HUB_EINVAL;
         for (int i = 0; i < 3; ++i)
             if (!std::isfinite(A[i])) return HUB_EINVAL;
     }

@@ -71,6 +71,15 @@ def test_strerror_and_invalid_arguments():
     assert lib.hub_set_coulomb(ctx, 0, None) == H.HUB_EINVAL
     assert lib.hub_query(ctx, 16, ctypes.byref(v)) == H.HUB_OK and v.value == 0      # no graph captured
     assert lib.hub_destroy(ctx) == H.HUB_OK
+    # the velocity gauge's grid-point phase table is addressed with 32-bit
+    # byte offsets: a field is refused on grids of 2^28 points or more, and
+    # accepted (host state only, before hub_finalize) below that
+    A = (ctypes.c_double * 3)(0.01, 0.0, 0.0)
+    for n, want in ((646, H.HUB_EINVAL), (645, H.HUB_OK)):
+        big = ctypes.c_void_p()
+        assert lib.hub_create(ctypes.byref(big), cell, (ctypes.c_int * 3)(n, n, n), 2, 1, 0) == H.HUB_OK
+        assert lib.hub_set_vector_potential(big, A) == want, n
+        assert lib.hub_destroy(big) == H.HUB_OK
     # a sphere that holds no grid point is rejected
     ctx2 = ctypes.c_void_p()
     assert lib.hub_create(ctypes.byref(ctx2), cell, ng, 1, 0, 0) == H.HUB_OK
