@@ -29,9 +29,11 @@
 namespace {
 
 // Functions per wave: 8 (4 x 8 x 2 FP64 accumulators, three waves per
-// SIMD) measured faster than 6 or 4 (more waves per SIMD, but each point's
-// load and preparation repeated by more waves); rows per batch: 4 (8 spills
-// scalar registers and leaves two waves per SIMD).
+// SIMD) measured faster than 6 or 4, and than items of at most 5 functions
+// (four waves per SIMD, 424 us against 385 on the NiO-like workload): more
+// waves per SIMD, but each point's load and preparation repeated by more
+// waves; rows per batch: 4 (8 spills scalar registers and leaves two waves
+// per SIMD).
 constexpr int MOM_NFW = HUB_MOM_NFW;
 static_assert(2 * MOM_NFW >= HUB_GF_MAX, "two halves cover a chunk's functions");
 constexpr int MOM_U = 4;
